@@ -1,0 +1,144 @@
+/*
+ * symstair.h - C ABI of the MI355X (gfx950) symmetric-stair PCG library.
+ *
+ * The library solves, for a batch of independent problems, the symmetric
+ * positive-definite block-tridiagonal Schur-complement system S lambda = gamma
+ * of a trajectory-optimization KKT system (Bu & Plancher, Sec. II-A,
+ * Eq. (schur) and the theta/phi/zeta block definitions), with preconditioned
+ * conjugate gradient (Sec. II-B) under one of three preconditioners:
+ * block-Jacobi (Sec. II-C, Eq. (jacobi)), the additive stair preconditioner
+ * (Sec. III, Eqs. (stair), (stair_inv) and the additive combination) and the
+ * symmetric stair preconditioner (Sec. IV).
+ *
+ * Conventions shared by every entry point
+ *   - Problem p has N[p] >= 1 knots (block rows), state size nx[p] in [1, 64]
+ *     and control size nu[p] in [0, 64].
+ *   - S is the NEGATED (positive-definite) Schur complement of the paper's
+ *     footnote: block row k = 0..N-1 has diagonal
+ *       D_0 = Q_0^-1,
+ *       D_k = Q_k^-1 + A_{k-1} Q_{k-1}^-1 A_{k-1}^T + B_{k-1} R_{k-1}^-1 B_{k-1}^T,
+ *     and sub-diagonal L_k = S[k][k-1] = -A_{k-1} Q_{k-1}^-1 (k >= 1).  The
+ *     returned lambda therefore equals minus the paper's lambda*.
+ *   - Input arrays are DEVICE pointers to packed row-major FP64 blocks; the
+ *     packing offsets are those returned by ssp_layout (problem after problem,
+ *     knot after knot).  A[N-1], B[N-1] and R[N-1] are read-only padding: the
+ *     last knot's dynamics do not enter S.
+ *   - All calls are asynchronous on `stream` (a hipStream_t, NULL = default
+ *     stream); outputs are valid after the stream is synchronised.  A handle
+ *     must not be used from two host threads at once.
+ *   - Numerical outcomes go to the per-problem status array and never fail
+ *     the call; the call-level ssp_status reports argument, allocation or
+ *     HIP runtime errors only.  No C++ exception crosses this interface.
+ */
+#ifndef SYMSTAIR_H
+#define SYMSTAIR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ssp_batch ssp_batch; /* opaque; owns every device workspace */
+
+typedef enum {
+    SSP_OK = 0,
+    SSP_ERR_ARG = 1,   /* invalid argument (null pointer, bad size, bad enum) */
+    SSP_ERR_ALLOC = 2, /* device or host allocation failed */
+    SSP_ERR_HIP = 3,   /* a HIP runtime call failed (message: ssp_last_error) */
+    SSP_ERR_STATE = 4  /* call out of order (e.g. solve before build) */
+} ssp_status;
+
+/* Per-problem status codes (values of prob_status[p]). */
+enum {
+    SSP_P_OK = 0,
+    SSP_P_NOT_SPD = 1,   /* a Q_k, R_k or D_k has a non-positive pivot */
+    SSP_P_MAXITER = 2,   /* max_iter inner iterations or max refinement steps reached */
+    SSP_P_NONFINITE = 3, /* NaN/Inf in gamma, lambda0 or a recurrence scalar */
+    SSP_P_BREAKDOWN = 4  /* p^T S p <= 0 or r^T z <= 0 inside PCG */
+};
+
+typedef enum {
+    SSP_PC_BLOCK_JACOBI = 0, /* Phi^-1 = block-diag(D_k^-1)                      */
+    SSP_PC_STAIR_ADD = 1,    /* Phi^-1 = (Psi_l^-1 + Psi_r^-1) / 2               */
+    SSP_PC_SYM_STAIR = 2     /* Phi^-1 = Psi_l^-1 + Psi_r^-1 - D^-1              */
+} ssp_precon;
+
+typedef enum {
+    SSP_FP64 = 0,          /* S, Phi^-1 stored and applied in FP64             */
+    SSP_FP32 = 1,          /* FP32 storage and PCG, one solve, FP64 true residual */
+    SSP_FP32_REFINE64 = 2  /* FP32 inner PCG inside FP64 iterative refinement  */
+} ssp_precision;
+
+/* Create a batch handle on HIP device `device` for `nprob` >= 1 problems of
+ * sizes N[p], nx[p], nu[p] (HOST arrays, copied).  Allocates the metadata;
+ * matrix storage is allocated by the first ssp_build.  *out receives the
+ * handle (NULL on failure). */
+ssp_status ssp_batch_create(int32_t nprob, const int32_t *N, const int32_t *nx, const int32_t *nu,
+                            int device, ssp_batch **out);
+
+/* Free every device and host resource of the handle (NULL is a no-op).
+ * Synchronises the device first. */
+ssp_status ssp_batch_destroy(ssp_batch *b);
+
+/* Packing offsets (HOST int64 arrays of nprob + 1 entries, any may be NULL):
+ * problem p's A and Q blocks start at element off_nn[p], its B blocks at
+ * off_nu[p], its R blocks at off_uu[p], its gamma / lambda entries at
+ * off_v[p]; entry nprob is the total element count of each array. */
+ssp_status ssp_layout(const ssp_batch *b, int64_t *off_nn, int64_t *off_nu, int64_t *off_uu,
+                      int64_t *off_v);
+
+/* Build S and Phi^-1 (Sec. II-A block formulas; Sec. III / IV
+ * preconditioners) from the per-knot blocks, entirely on the device in FP64,
+ * then store them in the precision `prec` will solve in (FP32 storage keeps
+ * the FP64 remainder of S as a second FP32 array for the refinement
+ * residual).  A, Q, B, R: device FP64, layout of ssp_layout.  prob_status:
+ * device int32[nprob], overwritten with SSP_P_OK or SSP_P_NOT_SPD. */
+ssp_status ssp_build(ssp_batch *b, ssp_precon pc, ssp_precision prec, const double *A,
+                     const double *B, const double *Q, const double *R, int32_t *prob_status,
+                     void *stream);
+
+/* Solve S lambda = gamma for every problem with PCG (Sec. II-B) to
+ * ||gamma - S lambda||_2 <= rel_tol * ||gamma||_2, using the preconditioner
+ * and precision of the last ssp_build.
+ *   gamma:    device FP64 [off_v[nprob]] (read only)
+ *   lambda:   device FP64, in = initial guess when use_lambda0 != 0,
+ *             out = solution (always written)
+ *   iters:    device int32[nprob], inner PCG iterations (S-products)
+ *   relres:   device FP64[nprob], final true relative residual in FP64
+ *   prob_status: device int32[nprob], in = build status (problems that
+ *             failed to build are skipped), out = solve status.
+ *   max_iter: cap on the inner iterations per problem (<= 0: 10 * N * nx).
+ * FP32_REFINE64 runs at most 5 refinement steps; the inner relative
+ * tolerance of step j is clamp(0.5 * rel_tol * ||gamma|| / ||r_j||, 1e-6, 1). */
+ssp_status ssp_solve(ssp_batch *b, double rel_tol, int32_t max_iter, const double *gamma,
+                     double *lambda, int use_lambda0, int32_t *iters, double *relres,
+                     int32_t *prob_status, void *stream);
+
+/* Refinement steps (outer FP64 residual corrections) each problem took in
+ * the last ssp_solve: copied into the caller's device int32[nprob]. */
+ssp_status ssp_solve_outer(const ssp_batch *b, int32_t *outer, void *stream);
+
+/* Copy the stored matrices out as FP64 blocks (device pointers, N blocks of
+ * nx x nx per problem at offsets off_nn): which = 0 -> S (diag = D_k,
+ * off = L_k, FP32 storage returns hi + lo), which = 1 -> Phi^-1 (diag =
+ * D_k^-1, off = Phi^-1[k][k-1], zero for block-Jacobi), which = 2 -> S as the
+ * PCG reads it (the FP32 hi part only under FP32 storage). */
+ssp_status ssp_export(const ssp_batch *b, int which, double *diag, double *off, void *stream);
+
+/* Kernel-mapping knobs of the batched PCG kernel (the autotuner sets them):
+ * threads per workgroup (64, 128, 256 or 512) and the LDS staging budget in
+ * bytes per workgroup (0 = library default).  Returns SSP_ERR_ARG if the
+ * budget cannot hold one knot of the largest nx. */
+ssp_status ssp_set_mapping(ssp_batch *b, int32_t threads, int32_t lds_bytes);
+
+/* Human-readable text of a call-level status, and of the last HIP error seen
+ * by this thread (static storage, never NULL). */
+const char *ssp_status_str(ssp_status s);
+const char *ssp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SYMSTAIR_H */

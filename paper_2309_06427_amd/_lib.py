@@ -1,0 +1,62 @@
+"""ctypes declarations of the C ABI in ``include/symstair.h`` (names kept 1:1).
+
+Loading fails loudly when ``libsymstair.so`` has not been built: there is no
+fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsymstair.so")
+
+SSP_OK, SSP_ERR_ARG, SSP_ERR_ALLOC, SSP_ERR_HIP, SSP_ERR_STATE = range(5)
+SSP_P_OK, SSP_P_NOT_SPD, SSP_P_MAXITER, SSP_P_NONFINITE, SSP_P_BREAKDOWN = range(5)
+SSP_PC_BLOCK_JACOBI, SSP_PC_STAIR_ADD, SSP_PC_SYM_STAIR = range(3)
+SSP_FP64, SSP_FP32, SSP_FP32_REFINE64 = range(3)
+
+PC = {"bj": SSP_PC_BLOCK_JACOBI, "add": SSP_PC_STAIR_ADD, "sym": SSP_PC_SYM_STAIR}
+PREC = {"fp64": SSP_FP64, "fp32": SSP_FP32, "fp32_refine64": SSP_FP32_REFINE64}
+
+# every symbol the header declares: name -> (restype, argtypes)
+_vp, _i32, _i64, _d = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+_pi32, _pi64 = C.POINTER(C.c_int32), C.POINTER(C.c_int64)
+SIGNATURES = {
+    "ssp_batch_create": (C.c_int, [_i32, _pi32, _pi32, _pi32, C.c_int, C.POINTER(_vp)]),
+    "ssp_batch_destroy": (C.c_int, [_vp]),
+    "ssp_layout": (C.c_int, [_vp, _pi64, _pi64, _pi64, _pi64]),
+    "ssp_build": (C.c_int, [_vp, C.c_int, C.c_int, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "ssp_solve": (C.c_int, [_vp, _d, _i32, _vp, _vp, C.c_int, _vp, _vp, _vp, _vp]),
+    "ssp_export": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp]),
+    "ssp_solve_outer": (C.c_int, [_vp, _vp, _vp]),
+    "ssp_set_mapping": (C.c_int, [_vp, _i32, _i32]),
+    "ssp_status_str": (C.c_char_p, [C.c_int]),
+    "ssp_last_error": (C.c_char_p, []),
+}
+
+_lib = None
+
+
+class SspError(RuntimeError):
+    pass
+
+
+def load() -> C.CDLL:
+    """Load the built library (raises if it is missing)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise SspError(f"HIP library not built: {LIB_PATH} is missing "
+                           "(run python -m paper_2309_06427_amd.build_lib)")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype, f.argtypes = res, args
+        _lib = L
+    return _lib
+
+
+def check(status: int, what: str) -> None:
+    if status != SSP_OK:
+        L = load()
+        raise SspError(f"{what}: {L.ssp_status_str(status).decode()} ({L.ssp_last_error().decode()})")

@@ -1,0 +1,286 @@
+// Assembly of S and Phi^-1 from per-knot blocks, in FP64 on the device.
+//
+// Three knot-parallel phases (a launch boundary between phases supplies the
+// neighbour knot's results):
+//   1. Q_k^-1 and R_k^-1                      (Sec. II-A block entries)
+//   2. D_k = Q_k^-1 + A_{k-1} Q_{k-1}^-1 A_{k-1}^T + B_{k-1} R_{k-1}^-1 B_{k-1}^T,
+//      L_k = -A_{k-1} Q_{k-1}^-1, D_k^-1          (negated Eq. (schur) blocks;
+//      D^-1 is the block-Jacobi inverse, Eq. (jacobi))
+//   3. Phi^-1[k][k-1] = -D_k^-1 L_k D_{k-1}^-1 (symmetric stair, Sec. IV),
+//      half of it for the additive stair (Sec. III), nothing for block-Jacobi.
+// One 64-lane workgroup handles one knot with its matrices in LDS.  SPD
+// inverses use Gauss-Jordan elimination without pivoting: for an SPD matrix
+// every pivot is a positive Schur-complement diagonal, so a non-positive
+// pivot flags the matrix as not positive definite.
+#include "ssp_device.h"
+#include "ssp_host.h"
+
+namespace ssp {
+
+namespace {
+
+constexpr int T = kWave;  // threads per knot team
+
+// In-place inverse of the SPD n x n matrix a (row-major, LDS).  col: n
+// doubles of LDS.  Returns false if a pivot is not positive (uniform).
+__device__ bool team_spd_inverse(double *a, double *col, int n) {
+    const int lane = threadIdx.x;
+    bool ok = true;
+    for (int k = 0; k < n; ++k) {
+        __syncthreads();
+        const double piv = a[k * n + k];
+        if (!(piv > 0.0)) ok = false;
+        const double inv = 1.0 / piv;
+        for (int i = lane; i < n; i += T) col[i] = a[i * n + k];
+        __syncthreads();
+        for (int j = lane; j < n; j += T) a[k * n + j] = (j == k ? 1.0 : a[k * n + j]) * inv;
+        __syncthreads();
+        for (int e = lane; e < n * n; e += T) {
+            const int i = e / n, j = e - i * n;
+            if (i != k) a[e] = (j == k ? 0.0 : a[e]) - col[i] * a[k * n + j];
+        }
+    }
+    __syncthreads();
+    // symmetrise (the exact inverse is symmetric)
+    for (int e = lane; e < n * n; e += T) {
+        const int i = e / n, j = e - i * n;
+        if (i < j) {
+            const double s = 0.5 * (a[i * n + j] + a[j * n + i]);
+            a[i * n + j] = s;
+            a[j * n + i] = s;
+        }
+    }
+    __syncthreads();
+    return ok;
+}
+
+// C (m x n) = X (m x k) * Y, Y stored k x n (ty = 0) or n x k (ty = 1, i.e. Y^T).
+__device__ void team_gemm(int m, int k, int n, const double *X, const double *Y, bool ty, double *Cm) {
+    for (int e = threadIdx.x; e < m * n; e += T) {
+        const int i = e / n, j = e - i * n;
+        double s = 0.0;
+        if (ty)
+            for (int l = 0; l < k; ++l) s += X[i * k + l] * Y[j * k + l];
+        else
+            for (int l = 0; l < k; ++l) s += X[i * k + l] * Y[l * n + j];
+        Cm[e] = s;
+    }
+    __syncthreads();
+}
+
+__device__ void team_load(double *dst, const double *src, int cnt) {
+    for (int e = threadIdx.x; e < cnt; e += T) dst[e] = src[e];
+}
+
+__device__ void team_store(double *dst, const double *src, int cnt) {
+    for (int e = threadIdx.x; e < cnt; e += T) dst[e] = src[e];
+}
+
+template <typename TM>
+__device__ void store_split(TM *hi, float *lo, const double *src, int cnt, double scale) {
+    for (int e = threadIdx.x; e < cnt; e += T) {
+        const double v = scale * src[e];
+        const TM h = (TM)v;
+        hi[e] = h;
+        if (lo) lo[e] = (float)(v - (double)h);
+    }
+}
+
+__device__ __forceinline__ void knot_of(const BuildArgs &a, int &p, int &k) {
+    const int g = blockIdx.x;
+    p = a.knot_prob[g];
+    k = g - (int)a.koff[p];
+}
+
+}  // namespace
+
+// Phase 1: Q_k^-1 (every knot) and R_k^-1 (k < N-1).
+__global__ __launch_bounds__(T) void k_build_inv(BuildArgs a) {
+    extern __shared__ double sm[];
+    int p, k;
+    knot_of(a, p, k);
+    const int N = a.N[p], nx = a.nx[p], nu = a.nu[p];
+    double *m = sm, *col = sm + a.mx * a.mx;
+    team_load(m, a.Q + a.off_nn[p] + (int64_t)k * nx * nx, nx * nx);
+    bool ok = team_spd_inverse(m, col, nx);
+    team_store(a.Qinv + a.off_nn[p] + (int64_t)k * nx * nx, m, nx * nx);
+    if (k < N - 1 && nu > 0) {
+        __syncthreads();
+        team_load(m, a.R + a.off_uu[p] + (int64_t)k * nu * nu, nu * nu);
+        ok = team_spd_inverse(m, col, nu) && ok;
+        team_store(a.Rinv + a.off_uu[p] + (int64_t)k * nu * nu, m, nu * nu);
+    }
+    if (!ok && threadIdx.x == 0) atomicOr(a.status + p, kNotSpd);
+}
+
+// Phase 2: D_k, L_k (stored in TM, plus the FP32 remainder for FP32 storage)
+// and D_k^-1 into the FP64 workspace.
+template <typename TM>
+__global__ __launch_bounds__(T) void k_build_S(BuildArgs a) {
+    extern __shared__ double sm[];
+    int p, k;
+    knot_of(a, p, k);
+    const int nx = a.nx[p], nu = a.nu[p];
+    const int nn = nx * nx;
+    const int64_t o = a.off_nn[p] + (int64_t)k * nn;
+    double *Dm = sm, *Am = Dm + nn, *Qp = Am + nn, *T1 = Qp + nn, *Bm = T1 + nn;
+    double *Rm = Bm + nx * nu, *BR = Rm + nu * nu, *col = BR + nx * nu;
+    team_load(Dm, a.Qinv + o, nn);
+    if (k > 0) {
+        const int64_t om = o - nn;
+        team_load(Am, a.A + om, nn);
+        team_load(Qp, a.Qinv + om, nn);
+        __syncthreads();
+        team_gemm(nx, nx, nx, Am, Qp, false, T1);  // A Q^-1 (= phi, L_k = -phi)
+        for (int e = threadIdx.x; e < nn; e += T) {
+            double s = 0.0;
+            const int i = e / nx, j = e - i * nx;
+            for (int l = 0; l < nx; ++l) s += T1[i * nx + l] * Am[j * nx + l];  // A Q^-1 A^T
+            Dm[e] += s;
+        }
+        if (nu > 0) {
+            const int64_t ob = a.off_nu[p] + (int64_t)(k - 1) * nx * nu;
+            const int64_t ou = a.off_uu[p] + (int64_t)(k - 1) * nu * nu;
+            team_load(Bm, a.B + ob, nx * nu);
+            team_load(Rm, a.Rinv + ou, nu * nu);
+            __syncthreads();
+            team_gemm(nx, nu, nu, Bm, Rm, false, BR);  // B R^-1
+            for (int e = threadIdx.x; e < nn; e += T) {
+                double s = 0.0;
+                const int i = e / nx, j = e - i * nx;
+                for (int l = 0; l < nu; ++l) s += BR[i * nu + l] * Bm[j * nu + l];  // B R^-1 B^T
+                Dm[e] += s;
+            }
+        }
+        __syncthreads();
+        store_split((TM *)a.SL + o, a.SLlo ? a.SLlo + o : nullptr, T1, nn, -1.0);
+        team_store(a.L64 + o, T1, nn);  // L64 holds +phi; phase 3 applies the sign
+    } else {
+        for (int e = threadIdx.x; e < nn; e += T) {
+            ((TM *)a.SL)[o + e] = (TM)0;
+            if (a.SLlo) a.SLlo[o + e] = 0.f;
+            a.L64[o + e] = 0.0;
+        }
+    }
+    __syncthreads();
+    // exact symmetry of the stored D (the PCG kernel reads D by columns)
+    for (int e = threadIdx.x; e < nn; e += T) {
+        const int i = e / nx, j = e - i * nx;
+        if (i < j) {
+            const double s = 0.5 * (Dm[i * nx + j] + Dm[j * nx + i]);
+            Dm[i * nx + j] = s;
+            Dm[j * nx + i] = s;
+        }
+    }
+    __syncthreads();
+    store_split((TM *)a.SD + o, a.SDlo ? a.SDlo + o : nullptr, Dm, nn, 1.0);
+    __syncthreads();
+    const bool ok = team_spd_inverse(Dm, col, nx);
+    team_store(a.Dinv64 + o, Dm, nn);
+    if (!ok && threadIdx.x == 0) atomicOr(a.status + p, kNotSpd);
+}
+
+// Phase 3: Phi^-1 blocks in TM.
+template <typename TM>
+__global__ __launch_bounds__(T) void k_build_phi(BuildArgs a) {
+    extern __shared__ double sm[];
+    int p, k;
+    knot_of(a, p, k);
+    const int nx = a.nx[p];
+    const int nn = nx * nx;
+    const int64_t o = a.off_nn[p] + (int64_t)k * nn;
+    double *Di = sm, *Lm = Di + nn, *Dp = Lm + nn, *T1 = Dp + nn, *T2 = T1 + nn;
+    team_load(Di, a.Dinv64 + o, nn);
+    __syncthreads();
+    store_split((TM *)a.PD + o, (float *)nullptr, Di, nn, 1.0);
+    if (a.PM == nullptr) return;  // block-Jacobi: no off-diagonal blocks
+    if (k == 0) {
+        for (int e = threadIdx.x; e < nn; e += T) ((TM *)a.PM)[o + e] = (TM)0;
+        return;
+    }
+    team_load(Lm, a.L64 + o, nn);          // +phi = -L_k
+    team_load(Dp, a.Dinv64 + o - nn, nn);  // D_{k-1}^-1
+    __syncthreads();
+    team_gemm(nx, nx, nx, Di, Lm, false, T1);
+    team_gemm(nx, nx, nx, T1, Dp, false, T2);
+    // -D_k^-1 L_k D_{k-1}^-1 = +D_k^-1 phi D_{k-1}^-1 ; additive stair halves it
+    store_split((TM *)a.PM + o, (float *)nullptr, T2, nn, a.pc == 1 ? 0.5 : 1.0);
+}
+
+// Export kernel: dst[e] = hi[e] (+ lo[e]) as FP64.
+template <typename TM>
+__global__ void k_export(const TM *hi, const float *lo, double *dst, int64_t n) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+        dst[e] = (double)hi[e] + (lo ? (double)lo[e] : 0.0);
+}
+
+__global__ void k_fill_i32(int32_t *dst, int32_t v, int64_t n) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+        dst[e] = v;
+}
+
+__global__ void k_fill_f64(double *dst, double v, int64_t n) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+        dst[e] = v;
+}
+
+// ------------------------------------------------------------- launchers ---
+
+static size_t lds_phase1(int mx) { return sizeof(double) * (mx * mx + mx); }
+static size_t lds_phase2(int nx, int nu) { return sizeof(double) * (4 * nx * nx + 2 * nx * nu + nu * nu + nx); }
+static size_t lds_phase3(int nx) { return sizeof(double) * 5 * nx * nx; }
+
+hipError_t launch_build(const BuildArgs &a, int64_t knots, int nx_max, int nu_max, bool fp32, hipStream_t s) {
+    if (knots == 0) return hipSuccess;
+    const dim3 grid((unsigned)knots), block(T);
+    size_t l1 = lds_phase1(a.mx), l2 = lds_phase2(nx_max, nu_max), l3 = lds_phase3(nx_max);
+    hipError_t e;
+    if ((e = hipFuncSetAttribute((const void *)k_build_inv, hipFuncAttributeMaxDynamicSharedMemorySize, (int)l1)))
+        return e;
+    hipLaunchKernelGGL(k_build_inv, grid, block, l1, s, a);
+    if ((e = hipGetLastError())) return e;
+    if (fp32) {
+        if ((e = hipFuncSetAttribute((const void *)k_build_S<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)l2)))
+            return e;
+        if ((e = hipFuncSetAttribute((const void *)k_build_phi<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)l3)))
+            return e;
+        hipLaunchKernelGGL(k_build_S<float>, grid, block, l2, s, a);
+        if ((e = hipGetLastError())) return e;
+        hipLaunchKernelGGL(k_build_phi<float>, grid, block, l3, s, a);
+    } else {
+        if ((e = hipFuncSetAttribute((const void *)k_build_S<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)l2)))
+            return e;
+        if ((e = hipFuncSetAttribute((const void *)k_build_phi<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)l3)))
+            return e;
+        hipLaunchKernelGGL(k_build_S<double>, grid, block, l2, s, a);
+        if ((e = hipGetLastError())) return e;
+        hipLaunchKernelGGL(k_build_phi<double>, grid, block, l3, s, a);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_export(const void *hi, const float *lo, bool fp32, double *dst, int64_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const int blocks = (int)((n + 255) / 256 < 65536 ? (n + 255) / 256 : 65536);
+    if (fp32)
+        hipLaunchKernelGGL(k_export<float>, dim3(blocks), dim3(256), 0, s, (const float *)hi, lo, dst, n);
+    else
+        hipLaunchKernelGGL(k_export<double>, dim3(blocks), dim3(256), 0, s, (const double *)hi, lo, dst, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int32_t *dst, int32_t v, int64_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const int blocks = (int)((n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096);
+    hipLaunchKernelGGL(k_fill_i32, dim3(blocks), dim3(256), 0, s, dst, v, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_f64(double *dst, double v, int64_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const int blocks = (int)((n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096);
+    hipLaunchKernelGGL(k_fill_f64, dim3(blocks), dim3(256), 0, s, dst, v, n);
+    return hipGetLastError();
+}
+
+}  // namespace ssp

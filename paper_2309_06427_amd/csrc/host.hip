@@ -1,0 +1,378 @@
+// Host side of the C ABI declared in include/symstair.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/symstair.h"
+#include "ssp_host.h"
+
+namespace {
+
+thread_local std::string g_last_error = "no error";
+
+ssp_status hip_fail(hipError_t e, const char *what) {
+    g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+    return SSP_ERR_HIP;
+}
+
+#define SSP_HIP(call)                                   \
+    do {                                                \
+        hipError_t e_ = (call);                         \
+        if (e_ != hipSuccess) return hip_fail(e_, #call); \
+    } while (0)
+
+struct DevGuard {
+    int prev = -1;
+    explicit DevGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DevGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+template <typename T>
+hipError_t dalloc(T **p, size_t count) {
+    *p = nullptr;
+    if (count == 0) count = 1;
+    return hipMalloc((void **)p, count * sizeof(T));
+}
+
+}  // namespace
+
+struct ssp_batch {
+    int device = 0;
+    int P = 0;
+    std::vector<int32_t> N, nx, nu;
+    std::vector<int64_t> off_nn, off_nu, off_uu, off_v, koff;
+    int nx_max = 1, nu_max = 0;
+    int64_t knots = 0;
+    // device metadata
+    int32_t *dN = nullptr, *dnx = nullptr, *dnu = nullptr, *dorder = nullptr, *dknot = nullptr;
+    int64_t *doff_nn = nullptr, *doff_nu = nullptr, *doff_uu = nullptr, *doff_v = nullptr, *dkoff = nullptr;
+    // FP64 build workspaces
+    double *Qinv = nullptr, *Rinv = nullptr, *L64 = nullptr, *Dinv64 = nullptr;
+    // stored matrices
+    bool fp32 = false;
+    bool have_storage = false;
+    void *SD = nullptr, *SL = nullptr, *PD = nullptr, *PM = nullptr;
+    float *SDlo = nullptr, *SLlo = nullptr;
+    // solve workspace
+    void *work = nullptr;
+    double *r64 = nullptr;
+    int32_t *douter = nullptr;
+    // state
+    bool built = false;
+    ssp_precon pc = SSP_PC_SYM_STAIR;
+    ssp_precision prec = SSP_FP64;
+    int threads = 256;
+    int lds_bytes = 0;  // 0: default
+};
+
+namespace {
+
+void free_storage(ssp_batch *b) {
+    for (void *p : {b->SD, b->SL, b->PD, b->PM, (void *)b->SDlo, (void *)b->SLlo, b->work})
+        if (p) (void)hipFree(p);
+    b->SD = b->SL = b->PD = b->PM = b->work = nullptr;
+    b->SDlo = b->SLlo = nullptr;
+    b->have_storage = false;
+}
+
+ssp_status alloc_storage(ssp_batch *b, bool fp32) {
+    if (b->have_storage && b->fp32 == fp32 && b->PM) return SSP_OK;
+    free_storage(b);
+    const size_t elem = fp32 ? sizeof(float) : sizeof(double);
+    const size_t nn = (size_t)b->off_nn[b->P];
+    const size_t nv = (size_t)b->off_v[b->P];
+    for (void **p : {&b->SD, &b->SL, &b->PD, &b->PM})
+        if (hipMalloc(p, std::max<size_t>(nn, 1) * elem) != hipSuccess) {
+            free_storage(b);
+            g_last_error = "hipMalloc of matrix storage failed";
+            return SSP_ERR_ALLOC;
+        }
+    if (fp32) {
+        if (dalloc(&b->SDlo, nn) != hipSuccess || dalloc(&b->SLlo, nn) != hipSuccess) {
+            free_storage(b);
+            g_last_error = "hipMalloc of FP32 remainder storage failed";
+            return SSP_ERR_ALLOC;
+        }
+    }
+    if (hipMalloc(&b->work, std::max<size_t>(7 * nv, 1) * elem) != hipSuccess) {
+        free_storage(b);
+        g_last_error = "hipMalloc of solve workspace failed";
+        return SSP_ERR_ALLOC;
+    }
+    b->fp32 = fp32;
+    b->have_storage = true;
+    return SSP_OK;
+}
+
+int effective_lds(const ssp_batch *b) {
+    if (b->lds_bytes > 0) return b->lds_bytes;
+    return ssp::pcg_default_lds(b->nx_max, b->fp32, b->threads);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *ssp_status_str(ssp_status s) {
+    switch (s) {
+        case SSP_OK: return "ok";
+        case SSP_ERR_ARG: return "invalid argument";
+        case SSP_ERR_ALLOC: return "allocation failed";
+        case SSP_ERR_HIP: return "HIP runtime error";
+        case SSP_ERR_STATE: return "call out of order";
+    }
+    return "unknown status";
+}
+
+const char *ssp_last_error(void) { return g_last_error.c_str(); }
+
+ssp_status ssp_batch_create(int32_t nprob, const int32_t *N, const int32_t *nx, const int32_t *nu, int device,
+                            ssp_batch **out) {
+    if (!out) return SSP_ERR_ARG;
+    *out = nullptr;
+    if (nprob < 1 || !N || !nx || !nu) return SSP_ERR_ARG;
+    int ndev = 0;
+    SSP_HIP(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) return SSP_ERR_ARG;
+    for (int p = 0; p < nprob; ++p)
+        if (N[p] < 1 || nx[p] < 1 || nx[p] > 64 || nu[p] < 0 || nu[p] > 64) return SSP_ERR_ARG;
+
+    ssp_batch *b = new (std::nothrow) ssp_batch();
+    if (!b) return SSP_ERR_ALLOC;
+    b->device = device;
+    b->P = nprob;
+    b->N.assign(N, N + nprob);
+    b->nx.assign(nx, nx + nprob);
+    b->nu.assign(nu, nu + nprob);
+    b->off_nn.assign(nprob + 1, 0);
+    b->off_nu.assign(nprob + 1, 0);
+    b->off_uu.assign(nprob + 1, 0);
+    b->off_v.assign(nprob + 1, 0);
+    b->koff.assign(nprob + 1, 0);
+    for (int p = 0; p < nprob; ++p) {
+        const int64_t n = N[p], x = nx[p], u = nu[p];
+        b->off_nn[p + 1] = b->off_nn[p] + n * x * x;
+        b->off_nu[p + 1] = b->off_nu[p] + n * x * u;
+        b->off_uu[p + 1] = b->off_uu[p] + n * u * u;
+        b->off_v[p + 1] = b->off_v[p] + n * x;
+        b->koff[p + 1] = b->koff[p] + n;
+        b->nx_max = std::max(b->nx_max, (int)x);
+        b->nu_max = std::max(b->nu_max, (int)u);
+    }
+    b->knots = b->koff[nprob];
+    // the per-knot FP64 assembly keeps 4 nx^2 + 2 nx nu + nu^2 + nx doubles in LDS
+    const int64_t asm_bytes = 8 * (4ll * b->nx_max * b->nx_max + 2ll * b->nx_max * b->nu_max +
+                                   (int64_t)b->nu_max * b->nu_max + b->nx_max);
+    if (b->knots > INT32_MAX || asm_bytes > 160 * 1024) {
+        delete b;
+        return SSP_ERR_ARG;
+    }
+    // problem order: largest N * nx^2 first, ties by index
+    std::vector<int32_t> order(nprob);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t c) {
+        return (int64_t)N[a] * nx[a] * nx[a] > (int64_t)N[c] * nx[c] * nx[c];
+    });
+    std::vector<int32_t> knot_prob((size_t)b->knots);
+    for (int p = 0; p < nprob; ++p)
+        std::fill(knot_prob.begin() + b->koff[p], knot_prob.begin() + b->koff[p + 1], p);
+
+    DevGuard g(device);
+    ssp_status rc = SSP_OK;
+    auto up = [&](auto **dst, const auto *src, size_t cnt) {
+        if (rc != SSP_OK) return;
+        if (dalloc(dst, cnt) != hipSuccess) {
+            rc = SSP_ERR_ALLOC;
+            return;
+        }
+        hipError_t e = hipMemcpy(*dst, src, cnt * sizeof(**dst), hipMemcpyHostToDevice);
+        if (e != hipSuccess) rc = hip_fail(e, "hipMemcpy metadata");
+    };
+    up(&b->dN, b->N.data(), nprob);
+    up(&b->dnx, b->nx.data(), nprob);
+    up(&b->dnu, b->nu.data(), nprob);
+    up(&b->dorder, order.data(), nprob);
+    up(&b->dknot, knot_prob.data(), knot_prob.size());
+    up(&b->doff_nn, b->off_nn.data(), nprob + 1);
+    up(&b->doff_nu, b->off_nu.data(), nprob + 1);
+    up(&b->doff_uu, b->off_uu.data(), nprob + 1);
+    up(&b->doff_v, b->off_v.data(), nprob + 1);
+    up(&b->dkoff, b->koff.data(), nprob + 1);
+    if (rc == SSP_OK) {
+        const size_t nn = b->off_nn[nprob], uu = b->off_uu[nprob], nv = b->off_v[nprob];
+        if (dalloc(&b->Qinv, nn) != hipSuccess || dalloc(&b->Rinv, uu) != hipSuccess ||
+            dalloc(&b->L64, nn) != hipSuccess || dalloc(&b->Dinv64, nn) != hipSuccess ||
+            dalloc(&b->r64, nv) != hipSuccess || dalloc(&b->douter, (size_t)nprob) != hipSuccess)
+            rc = SSP_ERR_ALLOC;
+    }
+    if (rc != SSP_OK) {
+        if (rc == SSP_ERR_ALLOC) g_last_error = "hipMalloc of batch metadata/workspace failed";
+        ssp_batch_destroy(b);
+        return rc;
+    }
+    *out = b;
+    return SSP_OK;
+}
+
+ssp_status ssp_batch_destroy(ssp_batch *b) {
+    if (!b) return SSP_OK;
+    {
+        DevGuard g(b->device);
+        (void)hipDeviceSynchronize();
+        free_storage(b);
+        for (void *p : {(void *)b->dN, (void *)b->dnx, (void *)b->dnu, (void *)b->dorder, (void *)b->dknot,
+                        (void *)b->doff_nn, (void *)b->doff_nu, (void *)b->doff_uu, (void *)b->doff_v,
+                        (void *)b->dkoff, (void *)b->Qinv, (void *)b->Rinv, (void *)b->L64, (void *)b->Dinv64,
+                        (void *)b->r64, (void *)b->douter})
+            if (p) (void)hipFree(p);
+    }
+    delete b;
+    return SSP_OK;
+}
+
+ssp_status ssp_layout(const ssp_batch *b, int64_t *off_nn, int64_t *off_nu, int64_t *off_uu, int64_t *off_v) {
+    if (!b) return SSP_ERR_ARG;
+    const size_t cnt = (size_t)b->P + 1;
+    if (off_nn) std::memcpy(off_nn, b->off_nn.data(), cnt * sizeof(int64_t));
+    if (off_nu) std::memcpy(off_nu, b->off_nu.data(), cnt * sizeof(int64_t));
+    if (off_uu) std::memcpy(off_uu, b->off_uu.data(), cnt * sizeof(int64_t));
+    if (off_v) std::memcpy(off_v, b->off_v.data(), cnt * sizeof(int64_t));
+    return SSP_OK;
+}
+
+ssp_status ssp_set_mapping(ssp_batch *b, int32_t threads, int32_t lds_bytes) {
+    if (!b) return SSP_ERR_ARG;
+    if (threads != 64 && threads != 128 && threads != 256 && threads != 512) return SSP_ERR_ARG;
+    if (lds_bytes < 0 || lds_bytes > 160 * 1024) return SSP_ERR_ARG;
+    if (lds_bytes > 0 && lds_bytes < ssp::pcg_min_lds(b->nx_max, true)) return SSP_ERR_ARG;
+    b->threads = threads;
+    b->lds_bytes = lds_bytes;
+    return SSP_OK;
+}
+
+ssp_status ssp_build(ssp_batch *b, ssp_precon pc, ssp_precision prec, const double *A, const double *B,
+                     const double *Q, const double *R, int32_t *prob_status, void *stream) {
+    if (!b || !A || !Q || !prob_status) return SSP_ERR_ARG;
+    if (b->nu_max > 0 && (!B || !R)) return SSP_ERR_ARG;
+    if (pc < SSP_PC_BLOCK_JACOBI || pc > SSP_PC_SYM_STAIR) return SSP_ERR_ARG;
+    if (prec < SSP_FP64 || prec > SSP_FP32_REFINE64) return SSP_ERR_ARG;
+    DevGuard g(b->device);
+    hipStream_t s = (hipStream_t)stream;
+    const bool fp32 = prec != SSP_FP64;
+    ssp_status rc = alloc_storage(b, fp32);
+    if (rc != SSP_OK) return rc;
+    b->built = false;
+    SSP_HIP(ssp::launch_fill_i32(prob_status, 0, b->P, s));
+    ssp::BuildArgs a{};
+    a.N = b->dN;
+    a.nx = b->dnx;
+    a.nu = b->dnu;
+    a.off_nn = b->doff_nn;
+    a.off_nu = b->doff_nu;
+    a.off_uu = b->doff_uu;
+    a.knot_prob = b->dknot;
+    a.koff = b->dkoff;
+    a.A = A;
+    a.B = B;
+    a.Q = Q;
+    a.R = R;
+    a.Qinv = b->Qinv;
+    a.Rinv = b->Rinv;
+    a.L64 = b->L64;
+    a.Dinv64 = b->Dinv64;
+    a.SD = b->SD;
+    a.SL = b->SL;
+    a.SDlo = fp32 ? b->SDlo : nullptr;
+    a.SLlo = fp32 ? b->SLlo : nullptr;
+    a.PD = b->PD;
+    a.PM = pc == SSP_PC_BLOCK_JACOBI ? nullptr : b->PM;
+    a.status = prob_status;
+    a.pc = (int)pc;
+    a.mx = std::max(b->nx_max, b->nu_max);
+    SSP_HIP(ssp::launch_build(a, b->knots, b->nx_max, b->nu_max, fp32, s));
+    b->pc = pc;
+    b->prec = prec;
+    b->built = true;
+    return SSP_OK;
+}
+
+ssp_status ssp_solve(ssp_batch *b, double rel_tol, int32_t max_iter, const double *gamma, double *lambda,
+                     int use_lambda0, int32_t *iters, double *relres, int32_t *prob_status, void *stream) {
+    if (!b || !gamma || !lambda || !iters || !relres || !prob_status) return SSP_ERR_ARG;
+    if (!(rel_tol >= 0.0)) return SSP_ERR_ARG;
+    if (!b->built) return SSP_ERR_STATE;
+    DevGuard g(b->device);
+    hipStream_t s = (hipStream_t)stream;
+    ssp::SolveArgs a{};
+    a.order = b->dorder;
+    a.N = b->dN;
+    a.nx = b->dnx;
+    a.off_nn = b->doff_nn;
+    a.off_v = b->doff_v;
+    a.status = prob_status;
+    a.SD = b->SD;
+    a.SL = b->SL;
+    a.SDlo = b->fp32 ? b->SDlo : nullptr;
+    a.SLlo = b->fp32 ? b->SLlo : nullptr;
+    a.PD = b->PD;
+    a.PM = b->pc == SSP_PC_BLOCK_JACOBI ? nullptr : b->PM;
+    a.gamma = gamma;
+    a.lambda = lambda;
+    a.use_lambda0 = use_lambda0 ? 1 : 0;
+    a.tol = rel_tol;
+    a.max_iter = max_iter;
+    a.refine = b->prec == SSP_FP32_REFINE64 ? 1 : 0;
+    a.max_outer = a.refine ? 5 : 1;
+    a.theta = 0.5;
+    a.tau_min = 1e-6;
+    a.iters = iters;
+    a.outer = b->douter;
+    a.relres = relres;
+    a.work = b->work;
+    a.r64 = b->r64;
+    a.tot_v = b->off_v[b->P];
+    a.lds_bytes = effective_lds(b);
+    SSP_HIP(ssp::launch_pcg(a, b->P, b->fp32, b->threads, s));
+    return SSP_OK;
+}
+
+ssp_status ssp_solve_outer(const ssp_batch *b, int32_t *outer, void *stream) {
+    if (!b || !outer) return SSP_ERR_ARG;
+    if (!b->built) return SSP_ERR_STATE;
+    DevGuard g(b->device);
+    SSP_HIP(hipMemcpyAsync(outer, b->douter, sizeof(int32_t) * b->P, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+    return SSP_OK;
+}
+
+ssp_status ssp_export(const ssp_batch *b, int which, double *diag, double *off, void *stream) {
+    if (!b || !diag || !off || which < 0 || which > 2) return SSP_ERR_ARG;
+    if (!b->built) return SSP_ERR_STATE;
+    DevGuard g(b->device);
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t nn = b->off_nn[b->P];
+    if (which == 1) {
+        SSP_HIP(ssp::launch_export(b->PD, nullptr, b->fp32, diag, nn, s));
+        if (b->pc == SSP_PC_BLOCK_JACOBI)
+            SSP_HIP(ssp::launch_fill_f64(off, 0.0, nn, s));
+        else
+            SSP_HIP(ssp::launch_export(b->PM, nullptr, b->fp32, off, nn, s));
+    } else {
+        const bool lo = which == 0 && b->fp32;
+        SSP_HIP(ssp::launch_export(b->SD, lo ? b->SDlo : nullptr, b->fp32, diag, nn, s));
+        SSP_HIP(ssp::launch_export(b->SL, lo ? b->SLlo : nullptr, b->fp32, off, nn, s));
+    }
+    return SSP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,72 @@
+// Device-side helpers shared by the library's kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ssp {
+
+constexpr int kWave = 64;
+
+// Per-problem status codes (numerically equal to the public SSP_P_* values).
+constexpr int kOk = 0, kNotSpd = 1, kMaxIter = 2, kNonFinite = 3, kBreakdown = 4;
+
+// Butterfly sum over the 64 lanes of a wavefront.  Every lane ends with the
+// same bits: each stage adds the same two operands on both partner lanes.
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+// Workgroup sum in a fixed order (wave butterflies, then waves 0..W-1 in
+// sequence), returned to every thread.  `red` holds BLOCK/64 entries of LDS.
+template <int BLOCK, typename T>
+__device__ __forceinline__ T block_sum(T v, T *red) {
+    v = wave_sum(v);
+    if constexpr (BLOCK == kWave) {
+        return v;
+    } else {
+        const int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
+        if (l == 0) red[w] = v;
+        __syncthreads();
+        T s = red[0];
+#pragma unroll
+        for (int i = 1; i < BLOCK / kWave; ++i) s += red[i];
+        __syncthreads();
+        return s;
+    }
+}
+
+// Two sums in one pass over the LDS scratch (2 * BLOCK/64 entries).
+template <int BLOCK, typename T>
+__device__ __forceinline__ void block_sum2(T &a, T &b, T *red) {
+    a = wave_sum(a);
+    b = wave_sum(b);
+    if constexpr (BLOCK > kWave) {
+        constexpr int W = BLOCK / kWave;
+        const int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
+        if (l == 0) {
+            red[w] = a;
+            red[W + w] = b;
+        }
+        __syncthreads();
+        T sa = red[0], sb = red[W];
+#pragma unroll
+        for (int i = 1; i < W; ++i) {
+            sa += red[i];
+            sb += red[W + i];
+        }
+        __syncthreads();
+        a = sa;
+        b = sb;
+    }
+}
+
+// e / d for 0 <= e < 2^31 / d: (e * m) >> 32 with m = ceil(2^32 / d) (exact
+// because e * (m d - 2^32) < e d < 2^32).
+__host__ __device__ inline uint64_t div_magic(int d) { return ((1ull << 32) + (uint64_t)d - 1) / (uint64_t)d; }
+__device__ __forceinline__ int fast_div(int e, uint64_t m) { return (int)(((uint64_t)(uint32_t)e * m) >> 32); }
+
+}  // namespace ssp

@@ -26,7 +26,9 @@ Per problem the draws happen in the order G, B, (W | c, U), gamma from
 """
 from __future__ import annotations
 
+import concurrent.futures as cf
 import dataclasses
+import os
 from typing import Sequence
 
 import numpy as np
@@ -155,11 +157,19 @@ def batch(P: int, seed: int, N_range=(32, 256), nx_choices=(6, 14, 26),
     Ns = srng.integers(N_range[0], N_range[1] + 1, size=P)
     nxs = np.asarray(nx_choices)[srng.integers(0, len(nx_choices), size=P)]
     count = P - first if count is None else count
-    probs = []
-    for i in range(first, first + count):
+
+    def one(i):
         rng = np.random.default_rng(children[i])
         n, x = int(Ns[i]), int(nxs[i])
-        probs.append(draw_problem(rng, n, x, x // 2, qmode, qcond_max))
+        return draw_problem(rng, n, x, x // 2, qmode, qcond_max)
+
+    idx = range(first, first + count)
+    if count >= 64:
+        # each problem owns its generator, so threads do not change the draws
+        with cf.ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+            probs = list(ex.map(one, idx))
+    else:
+        probs = [one(i) for i in idx]
     return pack(probs)
 
 

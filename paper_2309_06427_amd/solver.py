@@ -1,0 +1,136 @@
+"""Thin Python binding over the C ABI: torch supplies device memory and the
+stream, every computation runs in the HIP library.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib
+from ._lib import PC, PREC, check
+
+
+def _ptr(t) -> int:
+    return t.data_ptr() if t is not None else 0
+
+
+def _stream(stream) -> int:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+class BatchSolver:
+    """Handle over ``ssp_batch``: sizes are fixed at construction."""
+
+    def __init__(self, N, nx, nu, device: int = 0):
+        L = _lib.load()
+        N = np.ascontiguousarray(N, dtype=np.int32)
+        nx = np.ascontiguousarray(nx, dtype=np.int32)
+        nu = np.ascontiguousarray(nu, dtype=np.int32)
+        self.P = int(N.shape[0])
+        self.device = device
+        h = C.c_void_p()
+        p32 = lambda a: a.ctypes.data_as(C.POINTER(C.c_int32))
+        check(L.ssp_batch_create(self.P, p32(N), p32(nx), p32(nu), device, C.byref(h)), "ssp_batch_create")
+        self._h = h
+        offs = [np.zeros(self.P + 1, dtype=np.int64) for _ in range(4)]
+        p64 = lambda a: a.ctypes.data_as(C.POINTER(C.c_int64))
+        check(L.ssp_layout(h, *(p64(o) for o in offs)), "ssp_layout")
+        self.off_nn, self.off_nu, self.off_uu, self.off_v = offs
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.load().ssp_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_mapping(self, threads: int, lds_bytes: int = 0):
+        check(_lib.load().ssp_set_mapping(self._h, threads, lds_bytes), "ssp_set_mapping")
+
+    def build(self, pc: str, precision: str, A, B, Q, R, status, stream=None):
+        check(_lib.load().ssp_build(self._h, PC[pc], PREC[precision], _ptr(A), _ptr(B), _ptr(Q), _ptr(R),
+                                    _ptr(status), _stream(stream)), "ssp_build")
+
+    def solve(self, tol: float, max_iter: int, gamma, lam, use_lambda0: bool, iters, relres, status,
+              stream=None):
+        check(_lib.load().ssp_solve(self._h, float(tol), int(max_iter), _ptr(gamma), _ptr(lam),
+                                    int(bool(use_lambda0)), _ptr(iters), _ptr(relres), _ptr(status),
+                                    _stream(stream)), "ssp_solve")
+
+    def solve_outer(self, outer, stream=None):
+        check(_lib.load().ssp_solve_outer(self._h, _ptr(outer), _stream(stream)), "ssp_solve_outer")
+
+    def export(self, which: int, diag, off, stream=None):
+        check(_lib.load().ssp_export(self._h, which, _ptr(diag), _ptr(off), _stream(stream)), "ssp_export")
+
+
+class DeviceBatch:
+    """A packed input batch (see :mod:`paper_2309_06427_amd.inputs`) resident on
+    the GPU, with output buffers, ready for repeated build + solve."""
+
+    def __init__(self, batch, device: int = 0):
+        import torch
+        self.batch = batch
+        dev = torch.device("cuda", device)
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev)
+        self.A, self.B, self.Q, self.R, self.gamma = (t(x) for x in (batch.A, batch.B, batch.Q, batch.R,
+                                                                      batch.gamma))
+        self.solver = BatchSolver(batch.N, batch.nx, batch.nu, device)
+        for mine, theirs in ((self.solver.off_nn, batch.off_nn), (self.solver.off_v, batch.off_v),
+                             (self.solver.off_nu, batch.off_nu), (self.solver.off_uu, batch.off_uu)):
+            if not np.array_equal(mine, theirs):
+                raise ValueError("batch packing does not match the library layout")
+        P = batch.P
+        self.lam = torch.zeros_like(self.gamma)
+        self.iters = torch.zeros(P, dtype=torch.int32, device=dev)
+        self.relres = torch.zeros(P, dtype=torch.float64, device=dev)
+        self.status = torch.zeros(P, dtype=torch.int32, device=dev)
+        self.outer = torch.zeros(P, dtype=torch.int32, device=dev)
+
+    def build(self, pc: str = "sym", precision: str = "fp32_refine64", stream=None):
+        self.solver.build(pc, precision, self.A, self.B, self.Q, self.R, self.status, stream)
+
+    def solve(self, tol: float = 1e-6, max_iter: int = 0, lam0=None, stream=None):
+        if lam0 is not None:
+            self.lam.copy_(lam0)
+        self.solver.solve(tol, max_iter, self.gamma, self.lam, lam0 is not None, self.iters, self.relres,
+                          self.status, stream)
+        self.solver.solve_outer(self.outer, stream)
+
+    def results(self) -> dict:
+        import torch
+        torch.cuda.synchronize()
+        return dict(lam=self.lam.cpu().numpy(), iters=self.iters.cpu().numpy(),
+                    relres=self.relres.cpu().numpy(), status=self.status.cpu().numpy(),
+                    outer=self.outer.cpu().numpy())
+
+    def export(self, which: int):
+        import torch
+        n = int(self.solver.off_nn[-1])
+        d = torch.empty(n, dtype=torch.float64, device=self.gamma.device)
+        o = torch.empty(n, dtype=torch.float64, device=self.gamma.device)
+        self.solver.export(which, d, o)
+        torch.cuda.synchronize()
+        return d.cpu().numpy(), o.cpu().numpy()
+
+
+def solve(batch, pc: str = "sym", precision: str = "fp32_refine64", tol: float = 1e-6, max_iter: int = 0,
+          lam0=None, device: int = 0) -> dict:
+    """Build and solve a packed batch on the GPU; returns numpy results."""
+    db = DeviceBatch(batch, device)
+    db.build(pc, precision)
+    lam0_t = None
+    if lam0 is not None:
+        import torch
+        lam0_t = torch.from_numpy(np.ascontiguousarray(lam0, dtype=np.float64)).to(db.gamma.device)
+    db.solve(tol, max_iter, lam0_t)
+    out = db.results()
+    db.solver.close()
+    return out

@@ -1,0 +1,46 @@
+"""The C-ABI library loads and exports every function the public header declares."""
+import os
+import re
+
+import pytest
+
+from paper_2309_06427_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "symstair.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ssp_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_binding_set():
+    assert declared_functions() == sorted(_lib.SIGNATURES)
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.fail("libsymstair.so is not built (run __graft_entry__.build())")
+    L = _lib.load()
+    for name in declared_functions():
+        assert hasattr(L, name), name
+
+
+def test_status_strings_without_gpu():
+    L = _lib.load()
+    assert L.ssp_status_str(0) == b"ok"
+    assert L.ssp_status_str(1) == b"invalid argument"
+
+
+def test_create_rejects_bad_sizes_without_touching_memory():
+    import ctypes as C
+    import numpy as np
+    L = _lib.load()
+    h = C.c_void_p()
+    z = np.zeros(1, dtype=np.int32)
+    p = z.ctypes.data_as(C.POINTER(C.c_int32))
+    # nprob = 0 is rejected before any device call
+    assert L.ssp_batch_create(0, p, p, p, 0, C.byref(h)) == _lib.SSP_ERR_ARG
+    assert L.ssp_batch_create(1, None, p, p, 0, C.byref(h)) == _lib.SSP_ERR_ARG

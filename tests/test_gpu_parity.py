@@ -1,0 +1,183 @@
+"""GPU parity: the HIP library (through the C ABI) against the CPU oracle.
+
+Tolerances
+  * FP64 build: every stored block of S and Phi^-1 within 1e-12 of the
+    oracle's (relative to the largest entry of the problem); both sides use
+    different elimination orders for the SPD inverses, so agreement is to
+    rounding, ~kappa(block) * eps.
+  * FP64 solve to tol 1e-8: true relative residual <= 1.0001e-8 and
+    ||lam - lam_oracle|| / ||lam_oracle|| <= 1e-10 (both sides run the same
+    recurrences; their iterates differ by rounding only), iterations within
+    +-1 of the oracle's.
+  * FP32 storage with FP64 refinement to tol 1e-6: true FP64 relative
+    residual <= 1e-6 on every problem, and ||lam - lam*|| / ||lam*|| <=
+    kappa_2(S) * 1e-6 against the oracle's direct solve.
+"""
+import functools
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2309_06427_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def solve_gpu(b, pc, prec, tol, max_iter=0, lam0=None, threads=None, lds=0):
+    from paper_2309_06427_amd import solver
+    db = solver.DeviceBatch(b)
+    if threads:
+        db.solver.set_mapping(threads, lds)
+    db.build(pc, prec)
+    l0 = None if lam0 is None else torch.from_numpy(lam0).cuda()
+    db.solve(tol, max_iter, l0)
+    out = db.results()
+    out["db"] = db
+    return out
+
+
+def seg(b, v, i):
+    return v[b.off_v[i]:b.off_v[i + 1]]
+
+
+def blocks(b, flat, i):
+    n, x = int(b.N[i]), int(b.nx[i])
+    return flat[b.off_nn[i]:b.off_nn[i + 1]].reshape(n, x, x)
+
+
+@pytest.mark.parametrize("pc", ["bj", "add", "sym"])
+def test_build_fp64_matches_oracle(pc):
+    b = inputs.batch(6, seed=5, N_range=(3, 40), nx_choices=(1, 5, 14, 26))
+    out = solve_gpu(b, pc, "fp64", 1e-8)
+    assert (out["status"] == 0).all()
+    Sd, So = out["db"].export(0)
+    Pd, Po = out["db"].export(1)
+    for i in range(b.P):
+        p = b.problem(i)
+        st, D, L, Di, M = oracle.build(p["A"], p["B"], p["Q"], p["R"], pc)
+        assert st == oracle.OK
+        for got, want in ((blocks(b, Sd, i), D), (blocks(b, So, i), L), (blocks(b, Pd, i), Di),
+                          (blocks(b, Po, i), M)):
+            scale = max(np.abs(want).max(), 1e-300)
+            assert np.abs(got - want).max() <= 1e-12 * scale
+
+
+@pytest.mark.parametrize("pc", ["bj", "add", "sym"])
+def test_plain_single_solve_fp64(pc):
+    """N = 50, nx = 14, nu = 7, seed 0, FP64 to 1e-8."""
+    b = inputs.make("single_n50_nx14")
+    out = solve_gpu(b, pc, "fp64", 1e-8)
+    ref = oracle.solve_batch(b, pc, "fp64", tol=1e-8)
+    assert out["status"][0] == 0
+    assert out["relres"][0] <= 1.0001e-8
+    assert abs(int(out["iters"][0]) - int(ref["iters"][0])) <= 1
+    err = np.linalg.norm(out["lam"] - ref["lam"]) / np.linalg.norm(ref["lam"])
+    assert err <= 1e-10
+
+
+def test_iterations_ordered_sym_add_bj():
+    b = inputs.make("single_n50_nx14")
+    its = {pc: int(solve_gpu(b, pc, "fp64", 1e-8)["iters"][0]) for pc in ("bj", "add", "sym")}
+    assert its["sym"] < its["add"] < its["bj"]
+
+
+@pytest.mark.parametrize("prec", ["fp32_refine64", "fp64"])
+@pytest.mark.parametrize("threads", [64, 128, 256, 512])
+def test_ragged_batch_parity(prec, threads):
+    """Ragged batch (uneven N and nx, several chunks per sweep and a ragged tail)."""
+    b = inputs.batch(24, seed=7, N_range=(1, 90), nx_choices=(6, 14, 26))
+    tol = 1e-6 if prec != "fp64" else 1e-9
+    out = solve_gpu(b, "sym", prec, tol, threads=threads)
+    assert (out["status"] == 0).all(), out["status"]
+    assert out["relres"].max() <= tol * 1.0001
+    ref = oracle.solve_batch(b, "sym", prec, tol=tol)
+    exact = _exact(24, 7)
+    for i in range(b.P):
+        x, kappa = exact[i]
+        err = np.linalg.norm(seg(b, out["lam"], i) - x) / np.linalg.norm(x)
+        assert err <= kappa * tol * 1.01
+    # same algorithm: iteration counts agree up to rounding effects
+    assert np.abs(out["iters"].astype(int) - ref["iters"].astype(int)).max() <= 3
+
+
+@functools.lru_cache(maxsize=None)
+def _exact(P, seed):
+    """Direct-solve solution and 2-norm condition number of each problem."""
+    b = inputs.batch(P, seed=seed, N_range=(1, 90), nx_choices=(6, 14, 26))
+    res = []
+    for i in range(b.P):
+        p = b.problem(i)
+        _, D, L, _, _ = oracle.build(p["A"], p["B"], p["Q"], p["R"], "sym")
+        _, x = oracle.direct(D, L, p["gamma"])
+        ev = np.linalg.eigvalsh(_dense(D, L))
+        res.append((x, ev[-1] / ev[0]))
+    return res
+
+
+def _dense(D, L):
+    N, nx = D.shape[0], D.shape[1]
+    T = np.zeros((N * nx, N * nx))
+    for k in range(N):
+        T[k * nx:(k + 1) * nx, k * nx:(k + 1) * nx] = D[k]
+        if k:
+            T[k * nx:(k + 1) * nx, (k - 1) * nx:k * nx] = L[k]
+            T[(k - 1) * nx:k * nx, k * nx:(k + 1) * nx] = L[k].T
+    return T
+
+
+def test_fp32_alone_stalls_refinement_recovers():
+    b = inputs.make("batch1024_n128_nx26_cond1e6", P=8)
+    r32 = solve_gpu(b, "sym", "fp32", 1e-6)
+    rr = solve_gpu(b, "sym", "fp32_refine64", 1e-6)
+    assert (rr["status"] == 0).all()
+    assert rr["relres"].max() <= 1e-6
+    assert r32["relres"].max() > 1e-6
+    assert (rr["outer"] >= 2).any()
+
+
+def test_deterministic_replays():
+    b = inputs.batch(16, seed=9, N_range=(20, 120))
+    db = solve_gpu(b, "sym", "fp32_refine64", 1e-6)["db"]
+    first = db.results()["lam"].copy()
+    for _ in range(2):
+        db.solve(1e-6)
+        assert np.array_equal(db.results()["lam"], first)
+
+
+def test_edge_cases():
+    probs = [inputs.draw_problem(np.random.default_rng(s), N, nx, nu)
+             for s, (N, nx, nu) in enumerate([(1, 6, 3), (1, 1, 0), (5, 1, 1), (7, 3, 0), (64, 64, 8)])]
+    b = inputs.pack(probs)
+    for prec, tol in (("fp64", 1e-10), ("fp32_refine64", 1e-6)):
+        out = solve_gpu(b, "sym", prec, tol)
+        assert (out["status"] == 0).all()
+        assert out["relres"].max() <= tol * 1.0001
+        assert out["iters"][0] == 1          # N = 1: Phi^-1 = S^-1
+
+
+def test_status_codes():
+    probs = [inputs.draw_problem(np.random.default_rng(s), 12, 5, 2) for s in range(5)]
+    probs[1]["Q"][4] = -np.eye(5)            # indefinite Q_k
+    probs[2]["gamma"][3] = np.nan            # non-finite right-hand side
+    probs[3]["gamma"][:] = 0.0               # zero right-hand side
+    b = inputs.pack(probs)
+    out = solve_gpu(b, "sym", "fp64", 1e-12, max_iter=3)
+    assert list(out["status"]) == [2, 1, 3, 0, 2]   # MAXITER, NOT_SPD, NONFINITE, OK, MAXITER
+    assert out["iters"][3] == 0 and not seg(b, out["lam"], 3).any()
+    ref = oracle.solve_batch(b, "sym", "fp64", tol=1e-12, max_iter=3)
+    assert list(ref["status"]) == list(out["status"])
+
+
+def test_warm_start_with_solution_takes_no_iterations():
+    b = inputs.batch(4, seed=3, N_range=(10, 30))
+    ref = oracle.solve_batch(b, "sym", "fp64", tol=1e-12)
+    out = solve_gpu(b, "sym", "fp64", 1e-8, lam0=ref["lam"])
+    assert (out["iters"] == 0).all() and (out["status"] == 0).all()
