@@ -24,19 +24,28 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 
 
-def algorithmic_bytes(b, iters, outer, pc: str, precision: str) -> np.ndarray:
+def algorithmic_bytes(b, iters, outer, pc: str, precision: str, kernel: int = 0) -> np.ndarray:
     """Bytes the solve kernel must stream per problem: every stored block it
-    reads in each sweep (each element once per sweep), plus gamma in and
-    lambda out once.  L_0 and Phi^-1[0][-1] do not exist and are not counted."""
+    reads in each pass (each element once per pass), plus gamma in and lambda
+    out once.  L_0 and Phi^-1[0][-1] do not exist and are not counted.
+
+    fused kernel (0): each inner solve makes iters + 1 passes over D, L and
+    D^-1 ((3N - 1) nx^2 elements); explicit kernel (1): iters passes over S
+    and Phi^-1 plus one initial Phi^-1 pass.  Every refinement step and the
+    final check read S in FP64 (or FP32 hi + FP32 lo): 8 (2N - 1) nx^2 bytes.
+    """
     N = b.N.astype(np.float64)
     nn = b.nx.astype(np.float64) ** 2
     e = 8.0 if precision == "fp64" else 4.0
     nbS = nn * (2 * N - 1)
-    nbP = nn * N if pc == "bj" else nbS
-    res_elem = 8.0  # FP64 S, or FP32 hi + FP32 lo
     it = iters.astype(np.float64)
     st = outer.astype(np.float64)
-    return e * (it * (nbS + nbP) + st * nbP) + res_elem * (st + 1) * nbS + 16.0 * N * b.nx
+    if kernel == 0:
+        inner = e * nn * (3 * N - 1) * (it + st)
+    else:
+        nbP = nn * N if pc == "bj" else nbS
+        inner = e * (it * (nbS + nbP) + st * nbP)
+    return inner + 8.0 * (st + 1) * nbS + 16.0 * N * b.nx
 
 
 def cpu_baseline(b, pc, precision, tol, sample: int, min_seconds: float = 10.0) -> dict:
@@ -66,9 +75,13 @@ def main() -> int:
     ap.add_argument("--precision", default=None, choices=[None, "fp64", "fp32", "fp32_refine64"])
     ap.add_argument("--threads", type=int, default=0)
     ap.add_argument("--lds", type=int, default=0)
+    ap.add_argument("--kernel", type=int, default=0, help="0 fused single sweep, 1 explicit two sweeps")
     ap.add_argument("--cpu-sample", type=int, default=512)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true")
+    ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB (counter calibration "
+                         "and measured copy bandwidth), print one JSON line and exit")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -84,6 +97,24 @@ def main() -> int:
     if not torch.cuda.is_available():
         print("bench.py: no GPU visible", file=sys.stderr)
         return 1
+    if args.copy_calib:
+        n = args.copy_calib * (1 << 20) // 4
+        x = torch.ones(n, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 10
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            y.copy_(x)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "launches": reps + 3,
+                          "ms": ms, "GBps_read_plus_write": 2 * n * 4 / ms / 1e6}), flush=True)
+        return 0
     w = inputs.WORKLOADS[args.workload]
     precision = args.precision or w.get("precision", "fp32_refine64")
     tol = w["tol"]
@@ -93,8 +124,8 @@ def main() -> int:
     print(f"[bench] generated {args.workload}: {b.P} problems in {gen_s:.1f} s", file=sys.stderr, flush=True)
 
     db = solver.DeviceBatch(b)
-    if args.threads:
-        db.solver.set_mapping(args.threads, args.lds)
+    if args.threads or args.kernel:
+        db.solver.set_mapping(args.threads or 128, args.lds, args.kernel)
     stream = torch.cuda.current_stream()
 
     def step():
@@ -124,7 +155,7 @@ def main() -> int:
     print(f"[bench] timed {args.steps} steps: {wall:.2f} s", file=sys.stderr, flush=True)
 
     ok = bool((res["status"] == 0).all() and res["relres"].max() <= tol)
-    bytes_solve = float(algorithmic_bytes(b, res["iters"], res["outer"], args.pc, precision).sum())
+    bytes_solve = float(algorithmic_bytes(b, res["iters"], res["outer"], args.pc, precision, args.kernel).sum())
     solve_avg_s = float(solve_ms.mean()) / 1e3
     achieved = bytes_solve / solve_avg_s / 1e9
     value = b.P * args.steps / wall
@@ -166,6 +197,7 @@ def main() -> int:
             "precision": precision,
             "tol": tol,
             "warm_start": "zero",
+            "kernel": "fused" if args.kernel == 0 else "explicit",
             "step": "build (FP64 assembly) + solve",
         },
         "valid": ok,
@@ -180,7 +212,7 @@ def main() -> int:
             "compare": compare,
         },
         "roofline": {
-            "kernel": "k_pcg",
+            "kernel": "k_pcg2" if args.kernel == 0 else "k_pcg",
             "bound": "hbm",
             "achieved": round(achieved, 2),
             "peak": HBM_PEAK_GBS,

@@ -123,14 +123,20 @@ ssp_status ssp_solve_outer(const ssp_batch *b, int32_t *outer, void *stream);
  * nx x nx per problem at offsets off_nn): which = 0 -> S (diag = D_k,
  * off = L_k, FP32 storage returns hi + lo), which = 1 -> Phi^-1 (diag =
  * D_k^-1, off = Phi^-1[k][k-1], zero for block-Jacobi), which = 2 -> S as the
- * PCG reads it (the FP32 hi part only under FP32 storage). */
-ssp_status ssp_export(const ssp_batch *b, int which, double *diag, double *off, void *stream);
+ * PCG reads it (the FP32 hi part only under FP32 storage).  which = 1
+ * computes the explicit stair blocks if the last build did not. */
+ssp_status ssp_export(ssp_batch *b, int which, double *diag, double *off, void *stream);
 
 /* Kernel-mapping knobs of the batched PCG kernel (the autotuner sets them):
- * threads per workgroup (64, 128, 256 or 512) and the LDS staging budget in
- * bytes per workgroup (0 = library default).  Returns SSP_ERR_ARG if the
- * budget cannot hold one knot of the largest nx. */
-ssp_status ssp_set_mapping(ssp_batch *b, int32_t threads, int32_t lds_bytes);
+ * threads per workgroup (64, 128, 256 or 512), the LDS staging budget in
+ * bytes per workgroup (0 = library default) and the kernel: 0 = fused single
+ * sweep per iteration applying Phi^-1 = c1 D^-1 - c2 D^-1 S D^-1 from the
+ * stored D^-1 and S (default), 1 = two sweeps per iteration over the
+ * explicitly stored stair blocks.  The fused kernel is built for 128 and 256
+ * threads and for knots that fit its LDS rings; otherwise the explicit kernel
+ * runs.  Returns SSP_ERR_ARG for an unknown value or a budget that cannot
+ * hold one knot of the largest nx. */
+ssp_status ssp_set_mapping(ssp_batch *b, int32_t threads, int32_t lds_bytes, int32_t kernel);
 
 /* Human-readable text of a call-level status, and of the last HIP error seen
  * by this thread (static storage, never NULL). */

@@ -324,6 +324,10 @@ static int pcg_f32(int N, int nx, const float *D, const float *L, const float *D
  *     tau_j = clamp(theta * tol * ||gamma|| / ||r_j||, tau_min, 1);
  *   lam_{j+1} = lam_j + d in FP64.
  * refine = 0 runs one inner solve only (plain FP32 mode).
+ * Under refinement an inner breakdown (p^T S p <= 0 or r^T z <= 0 in float,
+ * a loss of float accuracy for an SPD S) ends that inner solve; the step
+ * still updates lam and the loop goes on, and BREAKDOWN is reported only if
+ * the next FP64 residual is not smaller than the one before that step.
  * *iters is the total number of inner S-products, *outer the refinement
  * steps taken. */
 int ssp_oracle_pcg_mixed(int N, int nx, const double *D, const double *L, const double *Dinv,
@@ -334,7 +338,8 @@ int ssp_oracle_pcg_mixed(int N, int nx, const double *D, const double *L, const 
     float *Df = malloc(sizeof(float) * nb), *Lf = malloc(sizeof(float) * nb);
     float *DIf = malloc(sizeof(float) * nb), *Mf = malloc(sizeof(float) * nb);
     double *r = malloc(sizeof(double) * n), *d = malloc(sizeof(double) * n);
-    int st = OR_OK, total = 0, steps = 0;
+    int st = OR_OK, total = 0, steps = 0, broke = 0;
+    double prev = INFINITY;
     for (size_t e = 0; e < nb; ++e) {
         Df[e] = (float)D[e]; Lf[e] = (float)L[e]; DIf[e] = (float)Dinv[e]; Mf[e] = (float)M[e];
     }
@@ -350,7 +355,9 @@ int ssp_oracle_pcg_mixed(int N, int nx, const double *D, const double *L, const 
         if (!isfinite(rnorm)) { st = OR_NONFINITE; break; }
         if (rnorm <= tol * gnorm) break;
         if (steps > 0 && !refine) break;
+        if (broke && !(rnorm < prev)) { st = OR_BREAKDOWN; break; }
         if (steps >= max_outer) { st = OR_MAXITER; break; }
+        prev = rnorm;
         double tau = refine ? theta * tol * gnorm / rnorm : tol * gnorm / rnorm;
         if (refine && tau < tau_min) tau = tau_min;
         if (tau > 1.0) tau = 1.0;
@@ -359,7 +366,8 @@ int ssp_oracle_pcg_mixed(int N, int nx, const double *D, const double *L, const 
         total += it;
         ++steps;
         for (size_t i = 0; i < n; ++i) lam[i] += d[i];
-        if (ist == OR_NONFINITE || ist == OR_BREAKDOWN) { st = ist; break; }
+        broke = refine && ist == OR_BREAKDOWN;
+        if (ist == OR_NONFINITE || (ist == OR_BREAKDOWN && !refine)) { st = ist; break; }
         if (ist == OR_MAXITER) { st = OR_MAXITER; break; }
     }
 done:

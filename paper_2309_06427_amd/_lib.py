@@ -29,7 +29,7 @@ SIGNATURES = {
     "ssp_solve": (C.c_int, [_vp, _d, _i32, _vp, _vp, C.c_int, _vp, _vp, _vp, _vp]),
     "ssp_export": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp]),
     "ssp_solve_outer": (C.c_int, [_vp, _vp, _vp]),
-    "ssp_set_mapping": (C.c_int, [_vp, _i32, _i32]),
+    "ssp_set_mapping": (C.c_int, [_vp, _i32, _i32, _i32]),
     "ssp_status_str": (C.c_char_p, [C.c_int]),
     "ssp_last_error": (C.c_char_p, []),
 }

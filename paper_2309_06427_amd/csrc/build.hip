@@ -14,6 +14,7 @@
 // pivot flags the matrix as not positive definite.
 #include "ssp_device.h"
 #include "ssp_host.h"
+#include "ssp_sweep.h"
 
 namespace ssp {
 
@@ -123,6 +124,9 @@ __global__ __launch_bounds__(T) void k_build_S(BuildArgs a) {
     const int nx = a.nx[p], nu = a.nu[p];
     const int nn = nx * nx;
     const int64_t o = a.off_nn[p] + (int64_t)k * nn;
+    const int bs = block_stride(nx, sizeof(TM));
+    const int64_t os = a.off_blk[p] + (int64_t)k * bs;          // remainder arrays
+    TM *blk = (TM *)a.B3 + 3 * a.off_blk[p] + (int64_t)k * 3 * bs;  // D_k, L_k, D_k^-1
     double *Dm = sm, *Am = Dm + nn, *Qp = Am + nn, *T1 = Qp + nn, *Bm = T1 + nn;
     double *Rm = Bm + nx * nu, *BR = Rm + nu * nu, *col = BR + nx * nu;
     team_load(Dm, a.Qinv + o, nn);
@@ -153,12 +157,12 @@ __global__ __launch_bounds__(T) void k_build_S(BuildArgs a) {
             }
         }
         __syncthreads();
-        store_split((TM *)a.SL + o, a.SLlo ? a.SLlo + o : nullptr, T1, nn, -1.0);
+        store_split(blk + bs, a.SLlo ? a.SLlo + os : nullptr, T1, nn, -1.0);
         team_store(a.L64 + o, T1, nn);  // L64 holds +phi; phase 3 applies the sign
     } else {
         for (int e = threadIdx.x; e < nn; e += T) {
-            ((TM *)a.SL)[o + e] = (TM)0;
-            if (a.SLlo) a.SLlo[o + e] = 0.f;
+            blk[bs + e] = (TM)0;
+            if (a.SLlo) a.SLlo[os + e] = 0.f;
             a.L64[o + e] = 0.0;
         }
     }
@@ -173,14 +177,16 @@ __global__ __launch_bounds__(T) void k_build_S(BuildArgs a) {
         }
     }
     __syncthreads();
-    store_split((TM *)a.SD + o, a.SDlo ? a.SDlo + o : nullptr, Dm, nn, 1.0);
+    store_split(blk, a.SDlo ? a.SDlo + os : nullptr, Dm, nn, 1.0);
     __syncthreads();
     const bool ok = team_spd_inverse(Dm, col, nx);
     team_store(a.Dinv64 + o, Dm, nn);
+    store_split(blk + 2 * bs, (float *)nullptr, Dm, nn, 1.0);
     if (!ok && threadIdx.x == 0) atomicOr(a.status + p, kNotSpd);
 }
 
-// Phase 3: Phi^-1 blocks in TM.
+// Phase 3 (explicit stair blocks, built only when asked for): the
+// sub-diagonal blocks of Phi^-1 in TM.
 template <typename TM>
 __global__ __launch_bounds__(T) void k_build_phi(BuildArgs a) {
     extern __shared__ double sm[];
@@ -189,29 +195,33 @@ __global__ __launch_bounds__(T) void k_build_phi(BuildArgs a) {
     const int nx = a.nx[p];
     const int nn = nx * nx;
     const int64_t o = a.off_nn[p] + (int64_t)k * nn;
+    const int64_t os = a.off_blk[p] + (int64_t)k * block_stride(nx, sizeof(TM));
     double *Di = sm, *Lm = Di + nn, *Dp = Lm + nn, *T1 = Dp + nn, *T2 = T1 + nn;
-    team_load(Di, a.Dinv64 + o, nn);
-    __syncthreads();
-    store_split((TM *)a.PD + o, (float *)nullptr, Di, nn, 1.0);
-    if (a.PM == nullptr) return;  // block-Jacobi: no off-diagonal blocks
-    if (k == 0) {
-        for (int e = threadIdx.x; e < nn; e += T) ((TM *)a.PM)[o + e] = (TM)0;
+    if (k == 0 || a.pc == 0) {
+        for (int e = threadIdx.x; e < nn; e += T) ((TM *)a.PM)[os + e] = (TM)0;
         return;
     }
+    team_load(Di, a.Dinv64 + o, nn);
     team_load(Lm, a.L64 + o, nn);          // +phi = -L_k
     team_load(Dp, a.Dinv64 + o - nn, nn);  // D_{k-1}^-1
     __syncthreads();
     team_gemm(nx, nx, nx, Di, Lm, false, T1);
     team_gemm(nx, nx, nx, T1, Dp, false, T2);
     // -D_k^-1 L_k D_{k-1}^-1 = +D_k^-1 phi D_{k-1}^-1 ; additive stair halves it
-    store_split((TM *)a.PM + o, (float *)nullptr, T2, nn, a.pc == 1 ? 0.5 : 1.0);
+    store_split((TM *)a.PM + os, (float *)nullptr, T2, nn, a.pc == 1 ? 0.5 : 1.0);
 }
 
-// Export kernel: dst[e] = hi[e] (+ lo[e]) as FP64.
+// Export kernel: one workgroup per knot copies hi (+ lo) from the stored
+// (padded) layout to the caller's packed FP64 layout.
 template <typename TM>
-__global__ void k_export(const TM *hi, const float *lo, double *dst, int64_t n) {
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
-        dst[e] = (double)hi[e] + (lo ? (double)lo[e] : 0.0);
+__global__ void k_export(BuildArgs a, const TM *hi, int mult, int sub, const float *lo, double *dst) {
+    int p, k;
+    knot_of(a, p, k);
+    const int nx = a.nx[p], nn = nx * nx, bs = block_stride(nx, sizeof(TM));
+    const int64_t o = a.off_nn[p] + (int64_t)k * nn;
+    const int64_t oh = mult * a.off_blk[p] + (int64_t)k * mult * bs + sub * bs;
+    const int64_t ol = a.off_blk[p] + (int64_t)k * bs;
+    for (int e = threadIdx.x; e < nn; e += T) dst[o + e] = (double)hi[oh + e] + (lo ? (double)lo[ol + e] : 0.0);
 }
 
 __global__ void k_fill_i32(int32_t *dst, int32_t v, int64_t n) {
@@ -233,39 +243,43 @@ static size_t lds_phase3(int nx) { return sizeof(double) * 5 * nx * nx; }
 hipError_t launch_build(const BuildArgs &a, int64_t knots, int nx_max, int nu_max, bool fp32, hipStream_t s) {
     if (knots == 0) return hipSuccess;
     const dim3 grid((unsigned)knots), block(T);
-    size_t l1 = lds_phase1(a.mx), l2 = lds_phase2(nx_max, nu_max), l3 = lds_phase3(nx_max);
+    const size_t l1 = lds_phase1(a.mx), l2 = lds_phase2(nx_max, nu_max);
     hipError_t e;
     if ((e = hipFuncSetAttribute((const void *)k_build_inv, hipFuncAttributeMaxDynamicSharedMemorySize, (int)l1)))
         return e;
     hipLaunchKernelGGL(k_build_inv, grid, block, l1, s, a);
     if ((e = hipGetLastError())) return e;
-    if (fp32) {
-        if ((e = hipFuncSetAttribute((const void *)k_build_S<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)l2)))
-            return e;
-        if ((e = hipFuncSetAttribute((const void *)k_build_phi<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)l3)))
-            return e;
+    const void *f2 = fp32 ? (const void *)k_build_S<float> : (const void *)k_build_S<double>;
+    if ((e = hipFuncSetAttribute(f2, hipFuncAttributeMaxDynamicSharedMemorySize, (int)l2))) return e;
+    if (fp32)
         hipLaunchKernelGGL(k_build_S<float>, grid, block, l2, s, a);
-        if ((e = hipGetLastError())) return e;
-        hipLaunchKernelGGL(k_build_phi<float>, grid, block, l3, s, a);
-    } else {
-        if ((e = hipFuncSetAttribute((const void *)k_build_S<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)l2)))
-            return e;
-        if ((e = hipFuncSetAttribute((const void *)k_build_phi<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)l3)))
-            return e;
+    else
         hipLaunchKernelGGL(k_build_S<double>, grid, block, l2, s, a);
-        if ((e = hipGetLastError())) return e;
-        hipLaunchKernelGGL(k_build_phi<double>, grid, block, l3, s, a);
-    }
     return hipGetLastError();
 }
 
-hipError_t launch_export(const void *hi, const float *lo, bool fp32, double *dst, int64_t n, hipStream_t s) {
-    if (n == 0) return hipSuccess;
-    const int blocks = (int)((n + 255) / 256 < 65536 ? (n + 255) / 256 : 65536);
+hipError_t launch_build_phi(const BuildArgs &a, int64_t knots, int nx_max, bool fp32, hipStream_t s) {
+    if (knots == 0) return hipSuccess;
+    const size_t l3 = lds_phase3(nx_max);
+    const void *f3 = fp32 ? (const void *)k_build_phi<float> : (const void *)k_build_phi<double>;
+    hipError_t e = hipFuncSetAttribute(f3, hipFuncAttributeMaxDynamicSharedMemorySize, (int)l3);
+    if (e) return e;
     if (fp32)
-        hipLaunchKernelGGL(k_export<float>, dim3(blocks), dim3(256), 0, s, (const float *)hi, lo, dst, n);
+        hipLaunchKernelGGL(k_build_phi<float>, dim3((unsigned)knots), dim3(T), l3, s, a);
     else
-        hipLaunchKernelGGL(k_export<double>, dim3(blocks), dim3(256), 0, s, (const double *)hi, lo, dst, n);
+        hipLaunchKernelGGL(k_build_phi<double>, dim3((unsigned)knots), dim3(T), l3, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_export(const BuildArgs &a, const void *hi, int mult, int sub, const float *lo, bool fp32,
+                         double *dst, int64_t knots, hipStream_t s) {
+    if (knots == 0) return hipSuccess;
+    if (fp32)
+        hipLaunchKernelGGL(k_export<float>, dim3((unsigned)knots), dim3(T), 0, s, a, (const float *)hi, mult, sub, lo,
+                           dst);
+    else
+        hipLaunchKernelGGL(k_export<double>, dim3((unsigned)knots), dim3(T), 0, s, a, (const double *)hi, mult, sub,
+                           lo, dst);
     return hipGetLastError();
 }
 

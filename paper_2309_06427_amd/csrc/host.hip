@@ -11,6 +11,7 @@
 
 #include "../../include/symstair.h"
 #include "ssp_host.h"
+#include "ssp_sweep.h"
 
 namespace {
 
@@ -52,17 +53,20 @@ struct ssp_batch {
     int P = 0;
     std::vector<int32_t> N, nx, nu;
     std::vector<int64_t> off_nn, off_nu, off_uu, off_v, koff;
+    std::vector<int64_t> off_blk32, off_blk64;  // stored-block offsets (padded stride)
     int nx_max = 1, nu_max = 0;
     int64_t knots = 0;
     // device metadata
     int32_t *dN = nullptr, *dnx = nullptr, *dnu = nullptr, *dorder = nullptr, *dknot = nullptr;
     int64_t *doff_nn = nullptr, *doff_nu = nullptr, *doff_uu = nullptr, *doff_v = nullptr, *dkoff = nullptr;
+    int64_t *doff_blk32 = nullptr, *doff_blk64 = nullptr;
     // FP64 build workspaces
     double *Qinv = nullptr, *Rinv = nullptr, *L64 = nullptr, *Dinv64 = nullptr;
     // stored matrices
     bool fp32 = false;
     bool have_storage = false;
-    void *SD = nullptr, *SL = nullptr, *PD = nullptr, *PM = nullptr;
+    void *B3 = nullptr;  // per knot: D_k, L_k, D_k^-1 (storage type, padded stride bs each)
+    void *PM = nullptr;  // explicit stair blocks, built on demand
     float *SDlo = nullptr, *SLlo = nullptr;
     // solve workspace
     void *work = nullptr;
@@ -70,34 +74,36 @@ struct ssp_batch {
     int32_t *douter = nullptr;
     // state
     bool built = false;
+    bool m_valid = false;  // explicit stair blocks PM match the last build
     ssp_precon pc = SSP_PC_SYM_STAIR;
     ssp_precision prec = SSP_FP64;
-    int threads = 256;
+    int threads = 128;
     int lds_bytes = 0;  // 0: default
+    int kernel = 0;     // 0 fused single-sweep, 1 explicit two-sweep
 };
 
 namespace {
 
 void free_storage(ssp_batch *b) {
-    for (void *p : {b->SD, b->SL, b->PD, b->PM, (void *)b->SDlo, (void *)b->SLlo, b->work})
+    for (void *p : {b->B3, b->PM, (void *)b->SDlo, (void *)b->SLlo, b->work})
         if (p) (void)hipFree(p);
-    b->SD = b->SL = b->PD = b->PM = b->work = nullptr;
+    b->B3 = b->PM = b->work = nullptr;
     b->SDlo = b->SLlo = nullptr;
     b->have_storage = false;
+    b->m_valid = false;
 }
 
 ssp_status alloc_storage(ssp_batch *b, bool fp32) {
-    if (b->have_storage && b->fp32 == fp32 && b->PM) return SSP_OK;
+    if (b->have_storage && b->fp32 == fp32) return SSP_OK;
     free_storage(b);
     const size_t elem = fp32 ? sizeof(float) : sizeof(double);
-    const size_t nn = (size_t)b->off_nn[b->P];
+    const size_t nn = (size_t)(fp32 ? b->off_blk32 : b->off_blk64)[b->P];
     const size_t nv = (size_t)b->off_v[b->P];
-    for (void **p : {&b->SD, &b->SL, &b->PD, &b->PM})
-        if (hipMalloc(p, std::max<size_t>(nn, 1) * elem) != hipSuccess) {
-            free_storage(b);
-            g_last_error = "hipMalloc of matrix storage failed";
-            return SSP_ERR_ALLOC;
-        }
+    if (hipMalloc(&b->B3, std::max<size_t>(3 * nn, 1) * elem) != hipSuccess) {
+        free_storage(b);
+        g_last_error = "hipMalloc of matrix storage failed";
+        return SSP_ERR_ALLOC;
+    }
     if (fp32) {
         if (dalloc(&b->SDlo, nn) != hipSuccess || dalloc(&b->SLlo, nn) != hipSuccess) {
             free_storage(b);
@@ -115,9 +121,65 @@ ssp_status alloc_storage(ssp_batch *b, bool fp32) {
     return SSP_OK;
 }
 
-int effective_lds(const ssp_batch *b) {
+
+// LDS bytes for the fused kernel, or 0 if the largest knot does not fit its
+// registers or LDS under the current mapping (the explicit kernel runs then).
+int fused_lds(const ssp_batch *b) {
+    if (!ssp::pcg2_threads_ok(b->threads)) return 0;
+    const int need = ssp::pcg2_lds(b->nx_max, b->fp32, b->threads);
+    if (need == 0) return 0;
+    const int lds = b->lds_bytes > 0 ? std::max(b->lds_bytes, ssp::bt_sweep_min_lds(b->nx_max, true, 8)) : need;
+    if (lds > 160 * 1024) return 0;
+    // knots per step decrease with nx, so the largest nx decides
+    if (ssp::pcg2_steps_for(b->nx_max, b->fp32, b->threads, lds) < 1) return 0;
+    return lds;
+}
+
+int explicit_lds(const ssp_batch *b) {
     if (b->lds_bytes > 0) return b->lds_bytes;
     return ssp::pcg_default_lds(b->nx_max, b->fp32, b->threads);
+}
+
+ssp::BuildArgs build_args(const ssp_batch *b) {
+    ssp::BuildArgs a{};
+    a.N = b->dN;
+    a.nx = b->dnx;
+    a.nu = b->dnu;
+    a.off_nn = b->doff_nn;
+    a.off_nu = b->doff_nu;
+    a.off_uu = b->doff_uu;
+    a.off_blk = b->fp32 ? b->doff_blk32 : b->doff_blk64;
+    a.knot_prob = b->dknot;
+    a.koff = b->dkoff;
+    a.Qinv = b->Qinv;
+    a.Rinv = b->Rinv;
+    a.L64 = b->L64;
+    a.Dinv64 = b->Dinv64;
+    a.B3 = b->B3;
+    a.SDlo = b->fp32 ? b->SDlo : nullptr;
+    a.SLlo = b->fp32 ? b->SLlo : nullptr;
+    a.PM = b->PM;
+    a.pc = (int)b->pc;
+    a.mx = std::max(b->nx_max, b->nu_max);
+    return a;
+}
+
+// explicit stair blocks, built on demand from the FP64 build workspaces
+ssp_status ensure_m(ssp_batch *b, hipStream_t s) {
+    if (b->m_valid) return SSP_OK;
+    if (!b->PM) {
+        const size_t elem = b->fp32 ? sizeof(float) : sizeof(double);
+        const size_t nn = (size_t)(b->fp32 ? b->off_blk32 : b->off_blk64)[b->P];
+        if (hipMalloc(&b->PM, std::max<size_t>(nn, 1) * elem) != hipSuccess) {
+            b->PM = nullptr;
+            g_last_error = "hipMalloc of explicit preconditioner blocks failed";
+            return SSP_ERR_ALLOC;
+        }
+    }
+    ssp::BuildArgs a = build_args(b);
+    SSP_HIP(ssp::launch_build_phi(a, b->knots, b->nx_max, b->fp32, s));
+    b->m_valid = true;
+    return SSP_OK;
 }
 
 }  // namespace
@@ -170,6 +232,12 @@ ssp_status ssp_batch_create(int32_t nprob, const int32_t *N, const int32_t *nx, 
         b->nx_max = std::max(b->nx_max, (int)x);
         b->nu_max = std::max(b->nu_max, (int)u);
     }
+    b->off_blk32.assign(nprob + 1, 0);
+    b->off_blk64.assign(nprob + 1, 0);
+    for (int p = 0; p < nprob; ++p) {
+        b->off_blk32[p + 1] = b->off_blk32[p] + (int64_t)N[p] * ssp::block_stride(nx[p], 4);
+        b->off_blk64[p + 1] = b->off_blk64[p] + (int64_t)N[p] * ssp::block_stride(nx[p], 8);
+    }
     b->knots = b->koff[nprob];
     // the per-knot FP64 assembly keeps 4 nx^2 + 2 nx nu + nu^2 + nx doubles in LDS
     const int64_t asm_bytes = 8 * (4ll * b->nx_max * b->nx_max + 2ll * b->nx_max * b->nu_max +
@@ -209,6 +277,8 @@ ssp_status ssp_batch_create(int32_t nprob, const int32_t *N, const int32_t *nx, 
     up(&b->doff_uu, b->off_uu.data(), nprob + 1);
     up(&b->doff_v, b->off_v.data(), nprob + 1);
     up(&b->dkoff, b->koff.data(), nprob + 1);
+    up(&b->doff_blk32, b->off_blk32.data(), nprob + 1);
+    up(&b->doff_blk64, b->off_blk64.data(), nprob + 1);
     if (rc == SSP_OK) {
         const size_t nn = b->off_nn[nprob], uu = b->off_uu[nprob], nv = b->off_v[nprob];
         if (dalloc(&b->Qinv, nn) != hipSuccess || dalloc(&b->Rinv, uu) != hipSuccess ||
@@ -233,7 +303,7 @@ ssp_status ssp_batch_destroy(ssp_batch *b) {
         free_storage(b);
         for (void *p : {(void *)b->dN, (void *)b->dnx, (void *)b->dnu, (void *)b->dorder, (void *)b->dknot,
                         (void *)b->doff_nn, (void *)b->doff_nu, (void *)b->doff_uu, (void *)b->doff_v,
-                        (void *)b->dkoff, (void *)b->Qinv, (void *)b->Rinv, (void *)b->L64, (void *)b->Dinv64,
+                        (void *)b->dkoff, (void *)b->doff_blk32, (void *)b->doff_blk64, (void *)b->Qinv, (void *)b->Rinv, (void *)b->L64, (void *)b->Dinv64,
                         (void *)b->r64, (void *)b->douter})
             if (p) (void)hipFree(p);
     }
@@ -251,13 +321,15 @@ ssp_status ssp_layout(const ssp_batch *b, int64_t *off_nn, int64_t *off_nu, int6
     return SSP_OK;
 }
 
-ssp_status ssp_set_mapping(ssp_batch *b, int32_t threads, int32_t lds_bytes) {
+ssp_status ssp_set_mapping(ssp_batch *b, int32_t threads, int32_t lds_bytes, int32_t kernel) {
     if (!b) return SSP_ERR_ARG;
     if (threads != 64 && threads != 128 && threads != 256 && threads != 512) return SSP_ERR_ARG;
     if (lds_bytes < 0 || lds_bytes > 160 * 1024) return SSP_ERR_ARG;
+    if (kernel != 0 && kernel != 1) return SSP_ERR_ARG;
     if (lds_bytes > 0 && lds_bytes < ssp::pcg_min_lds(b->nx_max, true)) return SSP_ERR_ARG;
     b->threads = threads;
     b->lds_bytes = lds_bytes;
+    b->kernel = kernel;
     return SSP_OK;
 }
 
@@ -273,36 +345,17 @@ ssp_status ssp_build(ssp_batch *b, ssp_precon pc, ssp_precision prec, const doub
     ssp_status rc = alloc_storage(b, fp32);
     if (rc != SSP_OK) return rc;
     b->built = false;
+    b->m_valid = false;
+    b->pc = pc;
+    b->prec = prec;
     SSP_HIP(ssp::launch_fill_i32(prob_status, 0, b->P, s));
-    ssp::BuildArgs a{};
-    a.N = b->dN;
-    a.nx = b->dnx;
-    a.nu = b->dnu;
-    a.off_nn = b->doff_nn;
-    a.off_nu = b->doff_nu;
-    a.off_uu = b->doff_uu;
-    a.knot_prob = b->dknot;
-    a.koff = b->dkoff;
+    ssp::BuildArgs a = build_args(b);
     a.A = A;
     a.B = B;
     a.Q = Q;
     a.R = R;
-    a.Qinv = b->Qinv;
-    a.Rinv = b->Rinv;
-    a.L64 = b->L64;
-    a.Dinv64 = b->Dinv64;
-    a.SD = b->SD;
-    a.SL = b->SL;
-    a.SDlo = fp32 ? b->SDlo : nullptr;
-    a.SLlo = fp32 ? b->SLlo : nullptr;
-    a.PD = b->PD;
-    a.PM = pc == SSP_PC_BLOCK_JACOBI ? nullptr : b->PM;
     a.status = prob_status;
-    a.pc = (int)pc;
-    a.mx = std::max(b->nx_max, b->nu_max);
     SSP_HIP(ssp::launch_build(a, b->knots, b->nx_max, b->nu_max, fp32, s));
-    b->pc = pc;
-    b->prec = prec;
     b->built = true;
     return SSP_OK;
 }
@@ -318,15 +371,13 @@ ssp_status ssp_solve(ssp_batch *b, double rel_tol, int32_t max_iter, const doubl
     a.order = b->dorder;
     a.N = b->dN;
     a.nx = b->dnx;
-    a.off_nn = b->doff_nn;
+    a.off_blk = b->fp32 ? b->doff_blk32 : b->doff_blk64;
     a.off_v = b->doff_v;
     a.status = prob_status;
-    a.SD = b->SD;
-    a.SL = b->SL;
+    a.B3 = b->B3;
     a.SDlo = b->fp32 ? b->SDlo : nullptr;
     a.SLlo = b->fp32 ? b->SLlo : nullptr;
-    a.PD = b->PD;
-    a.PM = b->pc == SSP_PC_BLOCK_JACOBI ? nullptr : b->PM;
+    a.pc = (int)b->pc;
     a.gamma = gamma;
     a.lambda = lambda;
     a.use_lambda0 = use_lambda0 ? 1 : 0;
@@ -342,8 +393,21 @@ ssp_status ssp_solve(ssp_batch *b, double rel_tol, int32_t max_iter, const doubl
     a.work = b->work;
     a.r64 = b->r64;
     a.tot_v = b->off_v[b->P];
-    a.lds_bytes = effective_lds(b);
-    SSP_HIP(ssp::launch_pcg(a, b->P, b->fp32, b->threads, s));
+    const int lds2 = b->kernel == 0 ? fused_lds(b) : 0;
+    if (lds2 > 0) {
+        a.lds_bytes = lds2;
+        SSP_HIP(ssp::launch_pcg2(a, b->P, b->fp32, b->threads, s));
+    } else {
+        // explicit stored stair blocks (also the fallback when a knot does not
+        // fit the fused kernel's registers or LDS)
+        if (b->pc != SSP_PC_BLOCK_JACOBI) {
+            ssp_status rc = ensure_m(b, s);
+            if (rc != SSP_OK) return rc;
+            a.PM = b->PM;
+        }
+        a.lds_bytes = explicit_lds(b);
+        SSP_HIP(ssp::launch_pcg(a, b->P, b->fp32, b->threads, s));
+    }
     return SSP_OK;
 }
 
@@ -355,22 +419,22 @@ ssp_status ssp_solve_outer(const ssp_batch *b, int32_t *outer, void *stream) {
     return SSP_OK;
 }
 
-ssp_status ssp_export(const ssp_batch *b, int which, double *diag, double *off, void *stream) {
+ssp_status ssp_export(ssp_batch *b, int which, double *diag, double *off, void *stream) {
     if (!b || !diag || !off || which < 0 || which > 2) return SSP_ERR_ARG;
     if (!b->built) return SSP_ERR_STATE;
     DevGuard g(b->device);
     hipStream_t s = (hipStream_t)stream;
-    const int64_t nn = b->off_nn[b->P];
+    ssp::BuildArgs a = build_args(b);
     if (which == 1) {
-        SSP_HIP(ssp::launch_export(b->PD, nullptr, b->fp32, diag, nn, s));
-        if (b->pc == SSP_PC_BLOCK_JACOBI)
-            SSP_HIP(ssp::launch_fill_f64(off, 0.0, nn, s));
-        else
-            SSP_HIP(ssp::launch_export(b->PM, nullptr, b->fp32, off, nn, s));
+        SSP_HIP(ssp::launch_export(a, b->B3, 3, 2, nullptr, b->fp32, diag, b->knots, s));
+        ssp_status rc = ensure_m(b, s);
+        if (rc != SSP_OK) return rc;
+        a = build_args(b);
+        SSP_HIP(ssp::launch_export(a, b->PM, 1, 0, nullptr, b->fp32, off, b->knots, s));
     } else {
         const bool lo = which == 0 && b->fp32;
-        SSP_HIP(ssp::launch_export(b->SD, lo ? b->SDlo : nullptr, b->fp32, diag, nn, s));
-        SSP_HIP(ssp::launch_export(b->SL, lo ? b->SLlo : nullptr, b->fp32, off, nn, s));
+        SSP_HIP(ssp::launch_export(a, b->B3, 3, 0, lo ? b->SDlo : nullptr, b->fp32, diag, b->knots, s));
+        SSP_HIP(ssp::launch_export(a, b->B3, 3, 1, lo ? b->SLlo : nullptr, b->fp32, off, b->knots, s));
     }
     return SSP_OK;
 }

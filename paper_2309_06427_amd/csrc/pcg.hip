@@ -1,4 +1,5 @@
-// Batched preconditioned conjugate gradient on S lambda = gamma.
+// Batched preconditioned conjugate gradient on S lambda = gamma, explicit form:
+// the preconditioner's stored blocks are streamed in a sweep of their own.
 //
 // One workgroup owns one problem for the whole solve (largest problems are
 // dispatched first).  Every product with S or Phi^-1 is a sweep over the
@@ -16,115 +17,16 @@
 // the true residual r = gamma - S lambda in FP64 (S = hi + lo under FP32
 // storage), stops at ||r|| <= tol ||gamma||, else solves S d = r / ||r|| with
 // the inner PCG in the storage precision and adds ||r|| d to lambda in FP64.
-// FP64 and plain FP32 modes run exactly one inner solve.
+// FP64 and plain FP32 modes run exactly one inner solve.  Under refinement
+// a float breakdown (p^T S p <= 0 or r^T z <= 0) only ends the inner solve;
+// it is reported when the next FP64 residual has not decreased.
 #include <math.h>
 
 #include "ssp_device.h"
 #include "ssp_host.h"
+#include "ssp_sweep.h"
 
 namespace ssp {
-
-namespace {
-
-// Staging geometry of one sweep.  Rows of a staged block are padded to
-// nx + 1 elements (odd for even nx) so that row-wise LDS reads by
-// consecutive lanes fall in distinct banks.
-struct Geo {
-    int nx, ldx, blk, nn, C;
-    uint64_t mg;  // magic for division by nx
-};
-
-template <typename TS>
-__device__ __forceinline__ Geo make_geo(int nx, bool has_sub, int lds_bytes, int block) {
-    Geo g;
-    g.nx = nx;
-    g.ldx = nx + 1;
-    g.blk = nx * g.ldx;
-    g.nn = nx * nx;
-    g.mg = div_magic(nx);
-    const int per_knot = (has_sub ? 2 : 1) * g.blk + nx;
-    const int fixed = (has_sub ? g.blk : 0) + 2 * nx;
-    int C = block / nx;
-    const int Cl = (lds_bytes / (int)sizeof(TS) - fixed) / per_knot;
-    if (Cl < C) C = Cl;
-    g.C = C < 1 ? 1 : C;
-    return g;
-}
-
-// One block-tridiagonal product over a problem of N knots.
-//   Dg, Sb: diagonal and sub-diagonal blocks (storage TM, row-major, Sb[0]
-//   ignored); Dlo/Slo optional FP32 remainders added during staging.
-//   xval(row): value of the input vector at a row of the problem (it may be
-//   called for halo rows owned by other threads).
-//   epi(row, y, x): called once per row by the row's owner with the product
-//   row y and the staged input x.
-template <typename TS, typename TM, int BLOCK, typename XF, typename EF>
-__device__ __forceinline__ void bt_sweep(int N, const Geo &g, const TM *__restrict__ Dg,
-                                         const float *__restrict__ Dlo, const TM *__restrict__ Sb,
-                                         const float *__restrict__ Slo, bool has_sub, TS *smem, XF &&xval,
-                                         EF &&epi) {
-    const int tid = threadIdx.x;
-    const int nx = g.nx, ldx = g.ldx, blk = g.blk, nn = g.nn, C = g.C;
-    TS *Ds = smem;
-    TS *Ss = Ds + C * blk;
-    TS *xs = Ss + (has_sub ? (C + 1) * blk : 0);
-    for (int k0 = 0; k0 < N; k0 += C) {
-        const int kc = min(C, N - k0);
-        __syncthreads();
-        {
-            const TM *src = Dg + (int64_t)k0 * nn;
-            const float *srl = Dlo ? Dlo + (int64_t)k0 * nn : nullptr;
-            const int cnt = kc * nn;
-            for (int e = tid; e < cnt; e += BLOCK) {
-                TS v = (TS)src[e];
-                if (srl) v += (TS)srl[e];
-                Ds[e + fast_div(e, g.mg)] = v;
-            }
-        }
-        if (has_sub) {
-            const int ks = min(kc + 1, N - k0);
-            const TM *src = Sb + (int64_t)k0 * nn;
-            const float *srl = Slo ? Slo + (int64_t)k0 * nn : nullptr;
-            const int cnt = ks * nn;
-            for (int e = tid; e < cnt; e += BLOCK) {
-                TS v = (TS)src[e];
-                if (srl) v += (TS)srl[e];
-                Ss[e + fast_div(e, g.mg)] = v;
-            }
-        }
-        {
-            const int cnt = (kc + 2) * nx;
-            const int base = (k0 - 1) * nx;
-            for (int t = tid; t < cnt; t += BLOCK) {
-                const int row = base + t;
-                xs[t] = (row >= 0 && row < N * nx) ? xval(row) : TS(0);
-            }
-        }
-        __syncthreads();
-        if (tid < kc * nx) {
-            const int kk = fast_div(tid, g.mg), i = tid - kk * nx, k = k0 + kk;
-            const TS *dcol = Ds + kk * blk + i;  // column i of the symmetric Dg_k
-            const TS *xk = xs + (kk + 1) * nx;
-            TS y = TS(0);
-            for (int j = 0; j < nx; ++j) y += dcol[j * ldx] * xk[j];
-            if (has_sub) {
-                if (k > 0) {
-                    const TS *lrow = Ss + kk * blk + i * ldx;  // row i of Sb_k
-                    const TS *xm = xs + kk * nx;
-                    for (int j = 0; j < nx; ++j) y += lrow[j] * xm[j];
-                }
-                if (k + 1 < N) {
-                    const TS *lcol = Ss + (kk + 1) * blk + i;  // column i of Sb_{k+1}
-                    const TS *xp = xs + (kk + 2) * nx;
-                    for (int j = 0; j < nx; ++j) y += lcol[j * ldx] * xp[j];
-                }
-            }
-            epi(k * nx + i, y, xk[i]);
-        }
-    }
-}
-
-}  // namespace
 
 template <typename TI, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_pcg(SolveArgs a) {
@@ -136,7 +38,8 @@ __global__ __launch_bounds__(BLOCK) void k_pcg(SolveArgs a) {
     const int p = a.order[blockIdx.x];
     const int N = a.N[p], nx = a.nx[p];
     const int n = N * nx;
-    const int64_t onn = a.off_nn[p], ov = a.off_v[p];
+    const int64_t onn = a.off_blk[p], ov = a.off_v[p];
+    const int bs = block_stride(nx, sizeof(TM));
     double *lam = a.lambda + ov;
     const double *gam = a.gamma + ov;
     double *r64 = a.r64 + ov;
@@ -152,9 +55,10 @@ __global__ __launch_bounds__(BLOCK) void k_pcg(SolveArgs a) {
         return;
     }
     const bool has_M = a.PM != nullptr;
-    const TM *SD = (const TM *)a.SD + onn, *SL = (const TM *)a.SL + onn;
+    const TM *SD = (const TM *)a.B3 + 3 * onn, *SL = SD + bs, *PD = SD + 2 * bs;  // knot stride 3 bs
+    const int ks3 = 3 * bs;
     const float *SDlo = a.SDlo ? a.SDlo + onn : nullptr, *SLlo = a.SLlo ? a.SLlo + onn : nullptr;
-    const TM *PD = (const TM *)a.PD + onn, *PM = has_M ? (const TM *)a.PM + onn : nullptr;
+    const TM *PM = has_M ? (const TM *)a.PM + onn : nullptr;
     TI *W = (TI *)a.work;
     TI *R[2] = {W + 0 * a.tot_v + ov, W + 1 * a.tot_v + ov};
     TI *Pv[2] = {W + 2 * a.tot_v + ov, W + 3 * a.tot_v + ov};
@@ -182,15 +86,17 @@ __global__ __launch_bounds__(BLOCK) void k_pcg(SolveArgs a) {
     } else if (gg == 0.0) {
         for (int row = tid; row < n; row += BLOCK) lam[row] = 0.0;
     } else {
-        const Geo g64 = make_geo<double>(nx, true, a.lds_bytes, BLOCK);
-        const Geo gS = make_geo<TI>(nx, true, a.lds_bytes, BLOCK);
-        const Geo gP = make_geo<TI>(nx, has_M, a.lds_bytes, BLOCK);
+        const Geo g64 = make_geo<double>(nx, bs, true, a.lds_bytes, BLOCK);
+        const Geo gS = make_geo<TI>(nx, bs, true, a.lds_bytes, BLOCK);
+        const Geo gP = make_geo<TI>(nx, bs, has_M, a.lds_bytes, BLOCK);
         int pending = kOk;
+        bool broke = false;  // last inner solve ended in a float breakdown (refinement only)
+        double prev = INFINITY;
         for (;;) {
             // true residual r = gamma - S lambda in FP64
             double rr64 = 0.0;
-            bt_sweep<double, TM, BLOCK>(
-                N, g64, SD, SDlo, SL, SLlo, true, (double *)smem_raw, [&](int row) { return lam[row]; },
+            bt_sweep<double, TM, BLOCK, 0>(
+                N, g64, SD, ks3, SDlo, SL, ks3, SLlo, true, (double *)smem_raw, [&](int row) { return lam[row]; },
                 [&](int row, double y, double) {
                     const double r = gam[row] - y;
                     r64[row] = r;
@@ -208,10 +114,15 @@ __global__ __launch_bounds__(BLOCK) void k_pcg(SolveArgs a) {
             }
             if (rnorm <= a.tol * gnorm) break;
             if (steps > 0 && !a.refine) break;
+            if (broke && !(rnorm < prev)) {
+                st = kBreakdown;
+                break;
+            }
             if (steps >= a.max_outer) {
                 st = kMaxIter;
                 break;
             }
+            prev = rnorm;
             double tau = (a.refine ? a.theta : 1.0) * a.tol * gnorm / rnorm;
             if (a.refine && tau < a.tau_min) tau = a.tau_min;
             if (tau > 1.0) tau = 1.0;
@@ -220,8 +131,8 @@ __global__ __launch_bounds__(BLOCK) void k_pcg(SolveArgs a) {
             // inner PCG on S d = r / ||r|| from d = 0
             int rc = 0, pc = 0, it = 0, ist = kOk;
             TI rz = TI(0), rr = TI(0), beta = TI(0), alpha = TI(0);
-            bt_sweep<TI, TM, BLOCK>(
-                N, gP, PD, nullptr, PM, nullptr, has_M, (TI *)smem_raw,
+            bt_sweep<TI, TM, BLOCK, 0>(
+                N, gP, PD, ks3, nullptr, PM, bs, nullptr, has_M, (TI *)smem_raw,
                 [&](int row) { return (TI)(r64[row] * inv_s); },
                 [&](int row, TI y, TI x) {
                     Zv[row] = y;
@@ -248,8 +159,8 @@ __global__ __launch_bounds__(BLOCK) void k_pcg(SolveArgs a) {
                 TI pq = TI(0);
                 const bool first = (it == 0);
                 TI *Pold = Pv[pc], *Pnew = Pv[pc ^ 1];
-                bt_sweep<TI, TM, BLOCK>(
-                    N, gS, SD, nullptr, SL, nullptr, true, (TI *)smem_raw,
+                bt_sweep<TI, TM, BLOCK, 0>(
+                    N, gS, SD, ks3, nullptr, SL, ks3, nullptr, true, (TI *)smem_raw,
                     [&](int row) { return first ? Zv[row] : Zv[row] + beta * Pold[row]; },
                     [&](int row, TI y, TI x) {
                         Qv[row] = y;
@@ -268,8 +179,8 @@ __global__ __launch_bounds__(BLOCK) void k_pcg(SolveArgs a) {
                 TI rzn = TI(0);
                 rr = TI(0);
                 TI *Rold = R[rc], *Rnew = R[rc ^ 1], *Pcur = Pv[pc];
-                bt_sweep<TI, TM, BLOCK>(
-                    N, gP, PD, nullptr, PM, nullptr, has_M, (TI *)smem_raw,
+                bt_sweep<TI, TM, BLOCK, 0>(
+                    N, gP, PD, ks3, nullptr, PM, bs, nullptr, has_M, (TI *)smem_raw,
                     [&](int row) { return Rold[row] - alpha * Qv[row]; },
                     [&](int row, TI y, TI x) {
                         Zv[row] = y;
@@ -287,7 +198,9 @@ __global__ __launch_bounds__(BLOCK) void k_pcg(SolveArgs a) {
             ++steps;
             __syncthreads();
             for (int row = tid; row < n; row += BLOCK) lam[row] += rnorm * (double)Dv[row];
-            if (ist != kOk) pending = ist;
+            // under refinement a float breakdown only ends the inner solve
+            broke = a.refine && ist == kBreakdown;
+            if (ist != kOk && !broke) pending = ist;
         }
     }
     if (tid == 0) {
@@ -298,12 +211,7 @@ __global__ __launch_bounds__(BLOCK) void k_pcg(SolveArgs a) {
     }
 }
 
-int pcg_min_lds(int nx_max, bool has_sub) {
-    const int blk = nx_max * (nx_max + 1);
-    const int per_knot = (has_sub ? 2 : 1) * blk + nx_max;
-    const int fixed = (has_sub ? blk : 0) + 2 * nx_max;
-    return (int)sizeof(double) * (per_knot + fixed);
-}
+int pcg_min_lds(int nx_max, bool has_sub) { return bt_sweep_min_lds(nx_max, has_sub, sizeof(double)); }
 
 int pcg_default_lds(int nx_max, bool fp32, int threads) {
     const int blk = nx_max * (nx_max + 1);

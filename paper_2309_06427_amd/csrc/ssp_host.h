@@ -8,14 +8,15 @@ namespace ssp {
 
 struct BuildArgs {
     const int32_t *N, *nx, *nu;
-    const int64_t *off_nn, *off_nu, *off_uu;
-    const int32_t *knot_prob;  // global knot index -> problem
-    const int64_t *koff;       // problem -> first global knot
+    const int64_t *off_nn, *off_nu, *off_uu;  // input (caller) layout
+    const int64_t *off_blk;                   // stored-block layout (padded block stride)
+    const int32_t *knot_prob;                 // global knot index -> problem
+    const int64_t *koff;                      // problem -> first global knot
     const double *A, *B, *Q, *R;
     double *Qinv, *Rinv, *L64, *Dinv64;  // FP64 workspaces (layout of A/Q, R)
-    void *SD, *SL;                       // S diagonal / sub-diagonal blocks (storage type)
-    float *SDlo, *SLlo;                  // FP64 remainders under FP32 storage (else null)
-    void *PD, *PM;                       // Phi^-1 diagonal / sub-diagonal (PM null: block-Jacobi)
+    void *B3;           // per knot k: D_k, L_k, D_k^-1 blocks, each bs elements (storage type)
+    float *SDlo, *SLlo;  // FP64 remainders of D_k, L_k under FP32 storage (stride bs; else null)
+    void *PM;           // explicit Phi^-1[k][k-1] blocks (stride bs; null: not built)
     int32_t *status;
     int pc;  // 0 block-Jacobi, 1 additive stair, 2 symmetric stair
     int mx;  // max(nx, nu) over the batch
@@ -24,11 +25,12 @@ struct BuildArgs {
 struct SolveArgs {
     const int32_t *order;  // workgroup -> problem (largest first)
     const int32_t *N, *nx;
-    const int64_t *off_nn, *off_v;
+    const int64_t *off_blk, *off_v;
     int32_t *status;
-    const void *SD, *SL;
-    const float *SDlo, *SLlo;
-    const void *PD, *PM;
+    const void *B3;            // interleaved D, L, D^-1 blocks (3 bs per knot)
+    const float *SDlo, *SLlo;  // FP64 remainders of D, L (bs per knot)
+    const void *PM;            // explicit sub-diagonal blocks (explicit kernel only)
+    int pc;               // 0 block-Jacobi, 1 additive stair, 2 symmetric stair
     const double *gamma;
     double *lambda;
     int use_lambda0;
@@ -46,15 +48,26 @@ struct SolveArgs {
 };
 
 hipError_t launch_build(const BuildArgs &a, int64_t knots, int nx_max, int nu_max, bool fp32, hipStream_t s);
-hipError_t launch_export(const void *hi, const float *lo, bool fp32, double *dst, int64_t n, hipStream_t s);
+hipError_t launch_build_phi(const BuildArgs &a, int64_t knots, int nx_max, bool fp32, hipStream_t s);
+// Copy one stored block array to the caller's packed FP64 layout: block k of
+// problem p sits at mult * off_blk[p] + k * mult * bs + sub * bs of `hi`
+// (mult = 3 for the interleaved array, 1 otherwise), plus `lo` (stride bs).
+hipError_t launch_export(const BuildArgs &a, const void *hi, int mult, int sub, const float *lo, bool fp32,
+                         double *dst, int64_t knots, hipStream_t s);
 hipError_t launch_fill_i32(int32_t *dst, int32_t v, int64_t n, hipStream_t s);
 hipError_t launch_fill_f64(double *dst, double v, int64_t n, hipStream_t s);
-hipError_t launch_pcg(const SolveArgs &a, int nprob, bool fp32, int threads, hipStream_t s);
 
-// Smallest LDS budget the PCG kernel accepts for a batch whose largest state
-// size is nx_max (one knot staged in FP64 plus the neighbour blocks).
+// Explicit two-sweep PCG (stored Phi^-1 blocks).
+hipError_t launch_pcg(const SolveArgs &a, int nprob, bool fp32, int threads, hipStream_t s);
 int pcg_min_lds(int nx_max, bool has_sub);
-// Default LDS budget for a mapping.
 int pcg_default_lds(int nx_max, bool fp32, int threads);
+
+// Fused single-sweep PCG with the preconditioner applied from D^-1 and S.
+hipError_t launch_pcg2(const SolveArgs &a, int nprob, bool fp32, int threads, hipStream_t s);
+int pcg2_lds(int nx_max, bool fp32, int threads);  // 0 if the mapping cannot hold one knot
+// Knots per step the fused kernel uses for state size nx (< 1: cannot run).
+int pcg2_steps_for(int nx, bool fp32, int threads, int lds_bytes);
+// Workgroup sizes the fused kernel is compiled for (128, 256).
+bool pcg2_threads_ok(int threads);
 
 }  // namespace ssp

@@ -191,6 +191,13 @@ WORKLOADS = {
                              tol=1e-6, precision="fp32_refine64"),
     "batch1024_n128_nx26_cond1e6": dict(kind="uniform", P=1024, N=128, nx=26, nu=12, seed=3,
                                         qmode="logcond", qcond_max=1e6, tol=1e-6),
+    # one state size at a time (the ragged batch's classes at its mean horizon)
+    "batch1365_n144_nx26": dict(kind="uniform", P=1365, N=144, nx=26, nu=13, seed=5, qmode="wishart",
+                                tol=1e-6, precision="fp32_refine64"),
+    "batch1365_n144_nx14": dict(kind="uniform", P=1365, N=144, nx=14, nu=7, seed=6, qmode="wishart",
+                                tol=1e-6, precision="fp32_refine64"),
+    "batch1365_n144_nx6": dict(kind="uniform", P=1365, N=144, nx=6, nu=3, seed=7, qmode="wishart",
+                               tol=1e-6, precision="fp32_refine64"),
 }
 
 

@@ -51,8 +51,8 @@ class BatchSolver:
         except Exception:
             pass
 
-    def set_mapping(self, threads: int, lds_bytes: int = 0):
-        check(_lib.load().ssp_set_mapping(self._h, threads, lds_bytes), "ssp_set_mapping")
+    def set_mapping(self, threads: int, lds_bytes: int = 0, kernel: int = 0):
+        check(_lib.load().ssp_set_mapping(self._h, threads, lds_bytes, kernel), "ssp_set_mapping")
 
     def build(self, pc: str, precision: str, A, B, Q, R, status, stream=None):
         check(_lib.load().ssp_build(self._h, PC[pc], PREC[precision], _ptr(A), _ptr(B), _ptr(Q), _ptr(R),
