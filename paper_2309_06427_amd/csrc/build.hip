@@ -8,7 +8,9 @@
 //      D^-1 is the block-Jacobi inverse, Eq. (jacobi))
 //   3. Phi^-1[k][k-1] = -D_k^-1 L_k D_{k-1}^-1 (symmetric stair, Sec. IV),
 //      half of it for the additive stair (Sec. III), nothing for block-Jacobi.
-// One 64-lane workgroup handles one knot with its matrices in LDS.  SPD
+// Phases 1 and 2 here are the generic form for any state size: one 64-lane
+// workgroup per knot with its matrices in LDS (the compiled state sizes use
+// the register-resident kernels instead).  Phase 3 reads the stored blocks.  SPD
 // inverses use Gauss-Jordan elimination without pivoting: for an SPD matrix
 // every pivot is a positive Schur-complement diagonal, so a non-positive
 // pivot flags the matrix as not positive definite.
@@ -93,13 +95,25 @@ __device__ __forceinline__ void knot_of(const BuildArgs &a, int &p, int &k) {
     k = g - (int)a.koff[p];
 }
 
+// knot of a generic-assembly workgroup
+__device__ __forceinline__ void listed_knot_of(const BuildArgs &a, int &p, int &k) {
+    const int g = a.knot_list[blockIdx.x];
+    p = a.knot_prob[g];
+    k = g - (int)a.koff[p];
+}
+
+template <typename TM>
+__device__ void team_load_lo(double *dst, const TM *src, const float *lo, int cnt, double scale) {
+    for (int e = threadIdx.x; e < cnt; e += T) dst[e] = scale * ((double)src[e] + (lo ? (double)lo[e] : 0.0));
+}
+
 }  // namespace
 
 // Phase 1: Q_k^-1 (every knot) and R_k^-1 (k < N-1).
 __global__ __launch_bounds__(T) void k_build_inv(BuildArgs a) {
     extern __shared__ double sm[];
     int p, k;
-    knot_of(a, p, k);
+    listed_knot_of(a, p, k);
     const int N = a.N[p], nx = a.nx[p], nu = a.nu[p];
     double *m = sm, *col = sm + a.mx * a.mx;
     team_load(m, a.Q + a.off_nn[p] + (int64_t)k * nx * nx, nx * nx);
@@ -115,12 +129,12 @@ __global__ __launch_bounds__(T) void k_build_inv(BuildArgs a) {
 }
 
 // Phase 2: D_k, L_k (stored in TM, plus the FP32 remainder for FP32 storage)
-// and D_k^-1 into the FP64 workspace.
+// and D_k^-1.
 template <typename TM>
 __global__ __launch_bounds__(T) void k_build_S(BuildArgs a) {
     extern __shared__ double sm[];
     int p, k;
-    knot_of(a, p, k);
+    listed_knot_of(a, p, k);
     const int nx = a.nx[p], nu = a.nu[p];
     const int nn = nx * nx;
     const int64_t o = a.off_nn[p] + (int64_t)k * nn;
@@ -158,12 +172,10 @@ __global__ __launch_bounds__(T) void k_build_S(BuildArgs a) {
         }
         __syncthreads();
         store_split(blk + bs, a.SLlo ? a.SLlo + os : nullptr, T1, nn, -1.0);
-        team_store(a.L64 + o, T1, nn);  // L64 holds +phi; phase 3 applies the sign
     } else {
         for (int e = threadIdx.x; e < nn; e += T) {
             blk[bs + e] = (TM)0;
             if (a.SLlo) a.SLlo[os + e] = 0.f;
-            a.L64[o + e] = 0.0;
         }
     }
     __syncthreads();
@@ -180,30 +192,30 @@ __global__ __launch_bounds__(T) void k_build_S(BuildArgs a) {
     store_split(blk, a.SDlo ? a.SDlo + os : nullptr, Dm, nn, 1.0);
     __syncthreads();
     const bool ok = team_spd_inverse(Dm, col, nx);
-    team_store(a.Dinv64 + o, Dm, nn);
     store_split(blk + 2 * bs, (float *)nullptr, Dm, nn, 1.0);
     if (!ok && threadIdx.x == 0) atomicOr(a.status + p, kNotSpd);
 }
 
 // Phase 3 (explicit stair blocks, built only when asked for): the
-// sub-diagonal blocks of Phi^-1 in TM.
+// sub-diagonal blocks of Phi^-1 in TM, from the stored D^-1 and L (with
+// L's FP32 remainder), multiplied in FP64.
 template <typename TM>
 __global__ __launch_bounds__(T) void k_build_phi(BuildArgs a) {
     extern __shared__ double sm[];
     int p, k;
     knot_of(a, p, k);
     const int nx = a.nx[p];
-    const int nn = nx * nx;
-    const int64_t o = a.off_nn[p] + (int64_t)k * nn;
-    const int64_t os = a.off_blk[p] + (int64_t)k * block_stride(nx, sizeof(TM));
+    const int nn = nx * nx, bs = block_stride(nx, sizeof(TM));
+    const int64_t os = a.off_blk[p] + (int64_t)k * bs;
+    const TM *blk = (const TM *)a.B3 + 3 * a.off_blk[p] + (int64_t)k * 3 * bs;  // D_k, L_k, D_k^-1
     double *Di = sm, *Lm = Di + nn, *Dp = Lm + nn, *T1 = Dp + nn, *T2 = T1 + nn;
     if (k == 0 || a.pc == 0) {
         for (int e = threadIdx.x; e < nn; e += T) ((TM *)a.PM)[os + e] = (TM)0;
         return;
     }
-    team_load(Di, a.Dinv64 + o, nn);
-    team_load(Lm, a.L64 + o, nn);          // +phi = -L_k
-    team_load(Dp, a.Dinv64 + o - nn, nn);  // D_{k-1}^-1
+    team_load_lo(Di, blk + 2 * bs, (const float *)nullptr, nn, 1.0);
+    team_load_lo(Lm, blk + bs, a.SLlo ? a.SLlo + os : nullptr, nn, -1.0);  // +phi = -L_k
+    team_load_lo(Dp, blk - bs, (const float *)nullptr, nn, 1.0);            // D_{k-1}^-1
     __syncthreads();
     team_gemm(nx, nx, nx, Di, Lm, false, T1);
     team_gemm(nx, nx, nx, T1, Dp, false, T2);

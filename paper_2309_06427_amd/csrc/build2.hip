@@ -1,0 +1,310 @@
+// Assembly of S and Phi^-1 with the matrices held in registers, one lane
+// per matrix row, for state sizes compiled in (nx = 6, 14, 26, 36).
+//
+// A wavefront holds kw = floor(64 / nx) knots; lane l works on row l % nx of
+// knot l / nx, so all rows of a knot live in one wave and exchange data
+// through a per-knot LDS buffer under wave-local ordering only.  Workgroups
+// walk a list of (problem, first knot) items of one state size.
+//
+// Phase 1: Q_k^-1, R_k^-1 (Sec. II-A block entries).
+// Phase 2: L_k = -A_{k-1} Q_{k-1}^-1,
+//          D_k = Q_k^-1 + A_{k-1} Q_{k-1}^-1 A_{k-1}^T + B_{k-1} R_{k-1}^-1 B_{k-1}^T
+//          (negated Eq. (schur) blocks), D_k^-1 (the block-Jacobi inverse,
+//          Eq. (jacobi)), stored interleaved per knot as D_k, L_k, D_k^-1.
+// SPD inverses are Gauss-Jordan eliminations without pivoting: for an SPD
+// matrix every pivot is a positive Schur-complement diagonal, so a
+// non-positive pivot flags the matrix as not positive definite.
+#include "ssp_device.h"
+#include "ssp_host.h"
+#include "ssp_sweep.h"
+
+namespace ssp {
+
+namespace {
+
+constexpr int kThreads = 128;
+
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+
+// per-lane place in the knot mapping
+template <int NX>
+struct Lane {
+    static constexpr int KW = 64 / NX;       // knots per wave
+    static constexpr int NP = (NX + 1) & ~1;  // LDS row pitch (16-byte rows)
+    int g, i, knot;                           // knot slot in the workgroup, row, knot index
+    bool row;                                 // this lane holds a row of a real knot
+};
+
+template <int NX>
+__device__ __forceinline__ Lane<NX> lane_of(int k0, int N) {
+    Lane<NX> L;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int kl = lane / NX;
+    // the spare lanes at the top of a wave (kl == KW) share the wave's last
+    // knot buffer: they never write LDS or memory and their flags are unused
+    L.g = w * Lane<NX>::KW + (kl < Lane<NX>::KW ? kl : Lane<NX>::KW - 1);
+    L.i = lane - kl * NX;
+    L.knot = k0 + L.g;
+    L.row = kl < Lane<NX>::KW && L.knot < N;
+    return L;
+}
+
+// LDS of one knot: an NX x NX matrix (row pitch NP) and a pivot row.
+template <int NX>
+constexpr int knot_lds_doubles() {
+    return NX * Lane<NX>::NP + Lane<NX>::NP;
+}
+
+// Read n = NX doubles of an LDS row (16-byte aligned) into registers.
+template <int NX>
+__device__ __forceinline__ void lds_row(const double *p, double (&r)[NX]) {
+    static_for<0, NX / 2>([&](auto hc) {
+        constexpr int j = 2 * decltype(hc)::value;
+        const f64x2 v = *(const f64x2 *)(p + j);
+        r[j] = v.x;
+        r[j + 1] = v.y;
+    });
+    if constexpr (NX % 2) r[NX - 1] = p[NX - 1];
+}
+
+template <int NX>
+__device__ __forceinline__ void lds_put_row(double *p, const double (&r)[NX]) {
+    static_for<0, NX / 2>([&](auto hc) {
+        constexpr int j = 2 * decltype(hc)::value;
+        f64x2 v;
+        v.x = r[j];
+        v.y = r[j + 1];
+        *(f64x2 *)(p + j) = v;
+    });
+    if constexpr (NX % 2) p[NX - 1] = r[NX - 1];
+}
+
+// Gauss-Jordan inverse of the n x n SPD matrix (n <= NX) whose row i this
+// lane holds in a[] (lanes i >= n of the knot only take part in the
+// ordering).  M: the knot's LDS buffer, used for the pivot row.  Returns
+// false if a pivot is not positive.
+template <int NX>
+__device__ __forceinline__ bool gj_inverse(double (&a)[NX], int i, bool row, int n, double *M) {
+    constexpr int NP = Lane<NX>::NP;
+    double *prow = M + NX * NP;
+    bool ok = true;
+    static_for<0, NX>([&](auto kc) {
+        constexpr int k = decltype(kc)::value;
+        if (k < n) {
+            if (row && i == k) lds_put_row<NX>(prow, a);
+            wave_sync();
+            double pr[NX];
+            lds_row<NX>(prow, pr);
+            wave_sync();  // the pivot row is read before the next one is written
+            const double inv = 1.0 / pr[k];
+            if (!(pr[k] > 0.0)) ok = false;
+            if (i == k) {
+                static_for<0, NX>([&](auto jc) {
+                    constexpr int j = decltype(jc)::value;
+                    a[j] = j == k ? inv : pr[j] * inv;
+                });
+            } else {
+                const double f = a[k];
+                static_for<0, NX>([&](auto jc) {
+                    constexpr int j = decltype(jc)::value;
+                    a[j] = j == k ? -f * inv : a[j] - f * (pr[j] * inv);
+                });
+            }
+        }
+    });
+    return ok;
+}
+
+// out = x M (M: n x NX in LDS, rows of pitch NP), x: this lane's row.
+template <int NX>
+__device__ __forceinline__ void row_times(const double (&x)[NX], const double *M, int n, double (&out)[NX]) {
+    constexpr int NP = Lane<NX>::NP;
+    static_for<0, NX>([&](auto jc) { out[decltype(jc)::value] = 0.0; });
+    static_for<0, NX>([&](auto lc) {
+        constexpr int l = decltype(lc)::value;
+        if (l < n) {
+            double m[NX];
+            lds_row<NX>(M + l * NP, m);
+            static_for<0, NX>([&](auto jc) {
+                constexpr int j = decltype(jc)::value;
+                out[j] += x[l] * m[j];
+            });
+        }
+    });
+}
+
+// out[j] += sum_{l < n} x[l] M[j][l] for j < NX (x M^T, M: NX x n in LDS).
+template <int NX>
+__device__ __forceinline__ void row_times_t(const double (&x)[NX], const double *M, int n, double (&out)[NX]) {
+    constexpr int NP = Lane<NX>::NP;
+    static_for<0, NX>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        double m[NX];
+        lds_row<NX>(M + j * NP, m);
+        double s = 0.0;
+        static_for<0, NX>([&](auto lc) {
+            constexpr int l = decltype(lc)::value;
+            if (l < n) s += x[l] * m[l];
+        });
+        out[j] += s;
+    });
+}
+
+// Replace a[] (row i of a matrix that should be symmetric) by row i of
+// (M + M^T) / 2 through the knot's LDS buffer.
+template <int NX>
+__device__ __forceinline__ void symmetrise(double (&a)[NX], int i, bool row, double *M) {
+    constexpr int NP = Lane<NX>::NP;
+    wave_sync();
+    if (row) lds_put_row<NX>(M + i * NP, a);
+    wave_sync();
+    static_for<0, NX>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        a[j] = 0.5 * (a[j] + M[j * NP + i]);
+    });
+    wave_sync();
+}
+
+// Load n entries of a global row into registers (entries >= n set to 0).
+template <int NX>
+__device__ __forceinline__ void load_row(const double *__restrict__ src, int n, double (&r)[NX]) {
+    static_for<0, NX>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        r[j] = j < n ? src[j] : 0.0;
+    });
+}
+
+template <int NX>
+__device__ __forceinline__ void store_row(double *__restrict__ dst, int n, const double (&r)[NX]) {
+    static_for<0, NX>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        if (j < n) dst[j] = r[j];
+    });
+}
+
+// Store a row in the storage type (scale applied), with its FP32 remainder.
+template <typename TM, int NX>
+__device__ __forceinline__ void store_split_row(TM *__restrict__ hi, float *__restrict__ lo, const double (&r)[NX],
+                                                double scale) {
+    static_for<0, NX>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        const double v = scale * r[j];
+        const TM h = (TM)v;
+        hi[j] = h;
+        if (lo) lo[j] = (float)(v - (double)h);
+    });
+}
+
+}  // namespace
+
+// Phase 1 for one state size: Q_k^-1 for every knot and R_k^-1 for k < N-1
+// (requires nu <= NX).
+template <int NX>
+__global__ __launch_bounds__(kThreads) void k_build_inv_nx(BuildArgs a, const int2 *items) {
+    constexpr int KN = (kThreads / 64) * Lane<NX>::KW;  // knots per workgroup
+    __shared__ __align__(16) double sm[KN * knot_lds_doubles<NX>()];
+    const int2 it = items[blockIdx.x];
+    const int p = it.x, N = a.N[p], nu = a.nu[p];
+    const Lane<NX> ln = lane_of<NX>(it.y, N);
+    double *M = sm + ln.g * knot_lds_doubles<NX>();
+    const int nn = NX * NX;
+    bool ok = true;
+    double r[NX];
+    const int64_t oq = a.off_nn[p] + (int64_t)ln.knot * nn + ln.i * NX;
+    if (ln.row) load_row<NX>(a.Q + oq, NX, r);
+    ok = gj_inverse<NX>(r, ln.i, ln.row, NX, M) && ok;
+    if (ln.row) store_row<NX>(a.Qinv + oq, NX, r);
+    if (nu > 0) {
+        const bool rrow = ln.row && ln.knot < N - 1 && ln.i < nu;
+        const int64_t orr = a.off_uu[p] + (int64_t)ln.knot * nu * nu + ln.i * nu;
+        if (rrow) load_row<NX>(a.R + orr, nu, r);
+        const bool okr = gj_inverse<NX>(r, ln.i, rrow, nu, M);
+        if (ln.knot < N - 1) ok = okr && ok;
+        if (rrow) store_row<NX>(a.Rinv + orr, nu, r);
+    }
+    if (ln.row && !ok) atomicOr(a.status + p, kNotSpd);
+}
+
+// Phase 2 for one state size: D_k, L_k (storage type, FP32 remainder under
+// FP32 storage) and D_k^-1, interleaved per knot.
+template <typename TM, int NX>
+__global__ __launch_bounds__(kThreads) void k_build_asm_nx(BuildArgs a, const int2 *items) {
+    constexpr int KN = (kThreads / 64) * Lane<NX>::KW;
+    constexpr int NP = Lane<NX>::NP;
+    __shared__ __align__(16) double sm[KN * knot_lds_doubles<NX>()];
+    const int2 it = items[blockIdx.x];
+    const int p = it.x, N = a.N[p], nu = a.nu[p];
+    const Lane<NX> ln = lane_of<NX>(it.y, N);
+    double *M = sm + ln.g * knot_lds_doubles<NX>();
+    const int nn = NX * NX, k = ln.knot, i = ln.i;
+    const int bs = block_stride(NX, sizeof(TM));
+    TM *blk = (TM *)a.B3 + 3 * a.off_blk[p] + (int64_t)k * 3 * bs;  // D_k, L_k, D_k^-1
+    const int64_t ol = a.off_blk[p] + (int64_t)k * bs;            // remainder arrays
+    const bool prev = ln.row && k > 0;
+
+    double d[NX], t[NX];
+    if (ln.row) load_row<NX>(a.Qinv + a.off_nn[p] + (int64_t)k * nn + i * NX, NX, d);  // Q_k^-1
+    // L_k = -A_{k-1} Q_{k-1}^-1 ; D_k += A_{k-1} Q_{k-1}^-1 A_{k-1}^T
+    wave_sync();
+    if (prev) store_row<NX>(M + i * NP, NX, *(const double(*)[NX])(a.Qinv + a.off_nn[p] + (int64_t)(k - 1) * nn +
+                                                                       i * NX));
+    wave_sync();
+    double x[NX];
+    if (prev) load_row<NX>(a.A + a.off_nn[p] + (int64_t)(k - 1) * nn + i * NX, NX, x);
+    row_times<NX>(x, M, NX, t);  // t = row i of A Q^-1 (= phi)
+    if (!prev) static_for<0, NX>([&](auto jc) { t[decltype(jc)::value] = 0.0; });  // L_0 = 0
+    wave_sync();
+    if (prev) lds_put_row<NX>(M + i * NP, x);  // rows of A_{k-1}
+    wave_sync();
+    if (prev) row_times_t<NX>(t, M, NX, d);
+    if (ln.row) store_split_row<TM, NX>(blk + bs + i * NX, a.SLlo ? a.SLlo + ol + i * NX : nullptr, t, -1.0);
+    // D_k += B_{k-1} R_{k-1}^-1 B_{k-1}^T
+    if (nu > 0) {
+        wave_sync();
+        if (prev && i < nu)
+            store_row<NX>(M + i * NP, nu,
+                          *(const double(*)[NX])(a.Rinv + a.off_uu[p] + (int64_t)(k - 1) * nu * nu + i * nu));
+        wave_sync();
+        if (prev) load_row<NX>(a.B + a.off_nu[p] + (int64_t)(k - 1) * NX * nu + i * nu, nu, x);
+        row_times<NX>(x, M, nu, t);  // t = row i of B R^-1 (first nu entries)
+        wave_sync();
+        if (prev) lds_put_row<NX>(M + i * NP, x);  // rows of B_{k-1} (nu entries each)
+        wave_sync();
+        if (prev) row_times_t<NX>(t, M, nu, d);
+    }
+    symmetrise<NX>(d, i, ln.row, M);  // the PCG kernels read D by columns
+    if (ln.row) store_split_row<TM, NX>(blk + i * NX, a.SDlo ? a.SDlo + ol + i * NX : nullptr, d, 1.0);
+    const bool ok = gj_inverse<NX>(d, i, ln.row, NX, M);
+    symmetrise<NX>(d, i, ln.row, M);
+    if (ln.row) store_split_row<TM, NX>(blk + 2 * bs + i * NX, (float *)nullptr, d, 1.0);
+    if (ln.row && !ok) atomicOr(a.status + p, kNotSpd);
+}
+
+template <int NX>
+static hipError_t launch_nx(const BuildArgs &a, const int2 *items, int nitems, bool fp32, hipStream_t s) {
+    if (nitems == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_build_inv_nx<NX>, dim3(nitems), dim3(kThreads), 0, s, a, items);
+    hipError_t e = hipGetLastError();
+    if (e) return e;
+    if (fp32)
+        hipLaunchKernelGGL((k_build_asm_nx<float, NX>), dim3(nitems), dim3(kThreads), 0, s, a, items);
+    else
+        hipLaunchKernelGGL((k_build_asm_nx<double, NX>), dim3(nitems), dim3(kThreads), 0, s, a, items);
+    return hipGetLastError();
+}
+
+const int kBuildSizes[kBuildClasses] = {6, 14, 26, 36};
+
+int build_knots_per_item(int nx) { return (kThreads / 64) * (64 / nx); }
+
+hipError_t launch_build_class(int cls, const BuildArgs &a, const int2 *items, int nitems, bool fp32, hipStream_t s) {
+    switch (cls) {
+        case 0: return launch_nx<6>(a, items, nitems, fp32, s);
+        case 1: return launch_nx<14>(a, items, nitems, fp32, s);
+        case 2: return launch_nx<26>(a, items, nitems, fp32, s);
+        case 3: return launch_nx<36>(a, items, nitems, fp32, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace ssp

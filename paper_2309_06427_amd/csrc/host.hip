@@ -58,10 +58,17 @@ struct ssp_batch {
     int64_t knots = 0;
     // device metadata
     int32_t *dN = nullptr, *dnx = nullptr, *dnu = nullptr, *dorder = nullptr, *dknot = nullptr;
+    // assembly work lists: per compiled state size, (problem, first knot)
+    // items at ditems + item_off[c]; knots of the other problems in dgeneric
+    int2 *ditems = nullptr;
+    int32_t *dgeneric = nullptr;
+    int item_off[ssp::kBuildClasses + 1] = {};
+    int64_t n_generic = 0;
+    int gen_nx_max = 1, gen_nu_max = 0;
     int64_t *doff_nn = nullptr, *doff_nu = nullptr, *doff_uu = nullptr, *doff_v = nullptr, *dkoff = nullptr;
     int64_t *doff_blk32 = nullptr, *doff_blk64 = nullptr;
     // FP64 build workspaces
-    double *Qinv = nullptr, *Rinv = nullptr, *L64 = nullptr, *Dinv64 = nullptr;
+    double *Qinv = nullptr, *Rinv = nullptr;
     // stored matrices
     bool fp32 = false;
     bool have_storage = false;
@@ -151,10 +158,9 @@ ssp::BuildArgs build_args(const ssp_batch *b) {
     a.off_blk = b->fp32 ? b->doff_blk32 : b->doff_blk64;
     a.knot_prob = b->dknot;
     a.koff = b->dkoff;
+    a.knot_list = b->dgeneric;
     a.Qinv = b->Qinv;
     a.Rinv = b->Rinv;
-    a.L64 = b->L64;
-    a.Dinv64 = b->Dinv64;
     a.B3 = b->B3;
     a.SDlo = b->fp32 ? b->SDlo : nullptr;
     a.SLlo = b->fp32 ? b->SLlo : nullptr;
@@ -164,7 +170,7 @@ ssp::BuildArgs build_args(const ssp_batch *b) {
     return a;
 }
 
-// explicit stair blocks, built on demand from the FP64 build workspaces
+// explicit stair blocks, built on demand from the stored D^-1 and L
 ssp_status ensure_m(ssp_batch *b, hipStream_t s) {
     if (b->m_valid) return SSP_OK;
     if (!b->PM) {
@@ -255,6 +261,26 @@ ssp_status ssp_batch_create(int32_t nprob, const int32_t *N, const int32_t *nx, 
     std::vector<int32_t> knot_prob((size_t)b->knots);
     for (int p = 0; p < nprob; ++p)
         std::fill(knot_prob.begin() + b->koff[p], knot_prob.begin() + b->koff[p + 1], p);
+    // assembly work lists (largest problems first within a class)
+    std::vector<int2> items;
+    std::vector<int32_t> generic;
+    for (int c = 0; c < ssp::kBuildClasses; ++c) {
+        b->item_off[c] = (int)items.size();
+        const int X = ssp::kBuildSizes[c], per = ssp::build_knots_per_item(X);
+        for (int32_t p : order)
+            if (nx[p] == X && nu[p] <= X)
+                for (int k0 = 0; k0 < N[p]; k0 += per) items.push_back(make_int2(p, k0));
+    }
+    b->item_off[ssp::kBuildClasses] = (int)items.size();
+    for (int p = 0; p < nprob; ++p) {
+        bool cls = false;
+        for (int c = 0; c < ssp::kBuildClasses; ++c) cls = cls || (nx[p] == ssp::kBuildSizes[c] && nu[p] <= nx[p]);
+        if (cls) continue;
+        for (int64_t g = b->koff[p]; g < b->koff[p + 1]; ++g) generic.push_back((int32_t)g);
+        b->gen_nx_max = std::max(b->gen_nx_max, (int)nx[p]);
+        b->gen_nu_max = std::max(b->gen_nu_max, (int)nu[p]);
+    }
+    b->n_generic = (int64_t)generic.size();
 
     DevGuard g(device);
     ssp_status rc = SSP_OK;
@@ -264,6 +290,7 @@ ssp_status ssp_batch_create(int32_t nprob, const int32_t *N, const int32_t *nx, 
             rc = SSP_ERR_ALLOC;
             return;
         }
+        if (cnt == 0) return;
         hipError_t e = hipMemcpy(*dst, src, cnt * sizeof(**dst), hipMemcpyHostToDevice);
         if (e != hipSuccess) rc = hip_fail(e, "hipMemcpy metadata");
     };
@@ -272,6 +299,8 @@ ssp_status ssp_batch_create(int32_t nprob, const int32_t *N, const int32_t *nx, 
     up(&b->dnu, b->nu.data(), nprob);
     up(&b->dorder, order.data(), nprob);
     up(&b->dknot, knot_prob.data(), knot_prob.size());
+    up(&b->ditems, items.data(), items.size());
+    up(&b->dgeneric, generic.data(), generic.size());
     up(&b->doff_nn, b->off_nn.data(), nprob + 1);
     up(&b->doff_nu, b->off_nu.data(), nprob + 1);
     up(&b->doff_uu, b->off_uu.data(), nprob + 1);
@@ -282,7 +311,6 @@ ssp_status ssp_batch_create(int32_t nprob, const int32_t *N, const int32_t *nx, 
     if (rc == SSP_OK) {
         const size_t nn = b->off_nn[nprob], uu = b->off_uu[nprob], nv = b->off_v[nprob];
         if (dalloc(&b->Qinv, nn) != hipSuccess || dalloc(&b->Rinv, uu) != hipSuccess ||
-            dalloc(&b->L64, nn) != hipSuccess || dalloc(&b->Dinv64, nn) != hipSuccess ||
             dalloc(&b->r64, nv) != hipSuccess || dalloc(&b->douter, (size_t)nprob) != hipSuccess)
             rc = SSP_ERR_ALLOC;
     }
@@ -302,8 +330,8 @@ ssp_status ssp_batch_destroy(ssp_batch *b) {
         (void)hipDeviceSynchronize();
         free_storage(b);
         for (void *p : {(void *)b->dN, (void *)b->dnx, (void *)b->dnu, (void *)b->dorder, (void *)b->dknot,
-                        (void *)b->doff_nn, (void *)b->doff_nu, (void *)b->doff_uu, (void *)b->doff_v,
-                        (void *)b->dkoff, (void *)b->doff_blk32, (void *)b->doff_blk64, (void *)b->Qinv, (void *)b->Rinv, (void *)b->L64, (void *)b->Dinv64,
+                        (void *)b->ditems, (void *)b->dgeneric, (void *)b->doff_nn, (void *)b->doff_nu, (void *)b->doff_uu, (void *)b->doff_v,
+                        (void *)b->dkoff, (void *)b->doff_blk32, (void *)b->doff_blk64, (void *)b->Qinv, (void *)b->Rinv,
                         (void *)b->r64, (void *)b->douter})
             if (p) (void)hipFree(p);
     }
@@ -355,7 +383,10 @@ ssp_status ssp_build(ssp_batch *b, ssp_precon pc, ssp_precision prec, const doub
     a.Q = Q;
     a.R = R;
     a.status = prob_status;
-    SSP_HIP(ssp::launch_build(a, b->knots, b->nx_max, b->nu_max, fp32, s));
+    for (int c = 0; c < ssp::kBuildClasses; ++c)
+        SSP_HIP(ssp::launch_build_class(c, a, b->ditems + b->item_off[c], b->item_off[c + 1] - b->item_off[c], fp32,
+                                        s));
+    SSP_HIP(ssp::launch_build(a, b->n_generic, b->gen_nx_max, b->gen_nu_max, fp32, s));
     b->built = true;
     return SSP_OK;
 }

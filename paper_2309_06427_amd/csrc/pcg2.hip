@@ -43,17 +43,6 @@ namespace {
 template <typename TM>
 constexpr int prefetch_slots() { return sizeof(TM) == 4 ? 16 : 8; }
 
-// Calls f(std::integral_constant<int, I>) for I = B .. E-1, so that arrays
-// indexed by I are addressed with constants from the start (and live in
-// registers rather than scratch).
-template <int B, int E, typename F>
-__device__ __forceinline__ void static_for(F &&f) {
-    if constexpr (B < E) {
-        f(std::integral_constant<int, B>{});
-        static_for<B + 1, E>(f);
-    }
-}
-
 // The six recurrence vectors of a problem.
 template <typename TI>
 struct Vecs {
@@ -170,15 +159,6 @@ __device__ __forceinline__ int slot_of(int sb, int d, int R) {
     if (s >= R) s -= R;
     if (s >= R) s -= R;
     return s;
-}
-
-// Wave-local LDS ordering: all rows of a knot live in one wavefront, whose
-// LDS operations execute in program order; this only stops the compiler
-// from moving LDS accesses across the point.
-__device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // Dot products of a column (stride NX) or a row of an NX x NX LDS block with

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace ssp {
 
 constexpr int kWave = 64;
@@ -68,5 +70,25 @@ __device__ __forceinline__ void block_sum2(T &a, T &b, T *red) {
 // because e * (m d - 2^32) < e d < 2^32).
 __host__ __device__ inline uint64_t div_magic(int d) { return ((1ull << 32) + (uint64_t)d - 1) / (uint64_t)d; }
 __device__ __forceinline__ int fast_div(int e, uint64_t m) { return (int)(((uint64_t)(uint32_t)e * m) >> 32); }
+
+// Calls f(std::integral_constant<int, I>) for I = B .. E-1, so that arrays
+// indexed by I are addressed with constants from the start (and live in
+// registers rather than scratch).
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F &&f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
+}
+
+// Wave-local LDS ordering: a wavefront's LDS operations execute in program
+// order, so when every thread involved belongs to one wave this only has to
+// stop the compiler from moving LDS accesses across the point.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 }  // namespace ssp

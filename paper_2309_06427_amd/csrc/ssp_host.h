@@ -12,8 +12,9 @@ struct BuildArgs {
     const int64_t *off_blk;                   // stored-block layout (padded block stride)
     const int32_t *knot_prob;                 // global knot index -> problem
     const int64_t *koff;                      // problem -> first global knot
+    const int32_t *knot_list;                 // generic assembly: workgroup -> global knot
     const double *A, *B, *Q, *R;
-    double *Qinv, *Rinv, *L64, *Dinv64;  // FP64 workspaces (layout of A/Q, R)
+    double *Qinv, *Rinv;  // FP64 workspaces (layout of Q, R)
     void *B3;           // per knot k: D_k, L_k, D_k^-1 blocks, each bs elements (storage type)
     float *SDlo, *SLlo;  // FP64 remainders of D_k, L_k under FP32 storage (stride bs; else null)
     void *PM;           // explicit Phi^-1[k][k-1] blocks (stride bs; null: not built)
@@ -47,7 +48,16 @@ struct SolveArgs {
     int lds_bytes;
 };
 
+// Generic assembly (any nx <= 64), one 64-lane workgroup per knot of
+// a.knot_list[0 .. knots).
 hipError_t launch_build(const BuildArgs &a, int64_t knots, int nx_max, int nu_max, bool fp32, hipStream_t s);
+// Register-resident assembly for the state sizes kBuildSizes (nu <= nx):
+// work item (problem, first knot) covers build_knots_per_item(nx) knots.
+constexpr int kBuildClasses = 4;
+extern const int kBuildSizes[kBuildClasses];
+int build_knots_per_item(int nx);
+hipError_t launch_build_class(int cls, const BuildArgs &a, const int2 *items, int nitems, bool fp32, hipStream_t s);
+// Explicit stair blocks from the stored D^-1 and L (every knot of the batch).
 hipError_t launch_build_phi(const BuildArgs &a, int64_t knots, int nx_max, bool fp32, hipStream_t s);
 // Copy one stored block array to the caller's packed FP64 layout: block k of
 // problem p sits at mult * off_blk[p] + k * mult * bs + sub * bs of `hi`
