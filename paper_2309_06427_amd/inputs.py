@@ -215,3 +215,20 @@ def make(name: str, **over) -> Batch:
         return uniform_batch(w["P"], w["N"], w["nx"], w["nu"], w["seed"], w["qmode"],
                              w.get("qcond_max", 1e4))
     raise ValueError(kind)
+
+
+def mlp_init(nx: int, hidden: int = 128, seed: int = 0) -> np.ndarray:
+    """Initial weights of the per-knot warm-start network (random draws only).
+
+    Flat FP64 vector W1 (n_in x H), b1, W2 (H x H), b2, W3 (H x nx), b3 with
+    n_in = 2 nx^2 + nx: weights Uniform(-1/sqrt(fan_in), 1/sqrt(fan_in)),
+    biases zero.
+    """
+    rng = np.random.default_rng(seed)
+    ni, H = 2 * nx * nx + nx, hidden
+    parts = []
+    for fan_in, fan_out in ((ni, H), (H, H), (H, nx)):
+        a = 1.0 / np.sqrt(fan_in)
+        parts.append(rng.uniform(-a, a, size=fan_in * fan_out))
+        parts.append(np.zeros(fan_out))
+    return np.concatenate(parts)
