@@ -68,6 +68,20 @@ def algorithmic_bytes(b, iters, outer, pc: str, precision: str, kernel: int = 0)
     return inner + 8.0 * (st + 1) * nbS + 16.0 * N * b.nx
 
 
+def load_nets(b, warm: str) -> list:
+    """Trained warm-start networks for the state sizes in the batch."""
+    from paper_2309_06427_amd.train_warmstart import weights_path
+    from paper_2309_06427_amd.warmstart import WarmStartNet
+    nets = []
+    for nx in sorted(set(int(x) for x in b.nx)):
+        path = weights_path(nx)
+        if os.path.exists(path):
+            nets.append(WarmStartNet.load(path))
+        elif warm == "learned":
+            raise SystemExit(f"bench.py: no trained warm-start weights for nx={nx} ({path})")
+    return nets
+
+
 def cpu_baseline(b, pc, precision, tol, sample: int, min_seconds: float = 10.0) -> dict:
     import oracle
     sub = b.subset(range(min(sample, b.P)))
@@ -99,6 +113,11 @@ def main() -> int:
     ap.add_argument("--cpu-sample", type=int, default=512)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true")
+    ap.add_argument("--warm", default="auto", choices=["auto", "zero", "learned"],
+                    help="learned: also run the step with the trained warm-start networks "
+                         "(auto: when their weights are present)")
+    ap.add_argument("--no-graph", dest="graph", action="store_false",
+                    help="time eager launches only (default: also replay the step as a HIP graph)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (counter calibration "
                          "and measured copy bandwidth), print one JSON line and exit")
@@ -147,40 +166,85 @@ def main() -> int:
     if args.threads or args.kernel:
         db.solver.set_mapping(args.threads or 128, args.lds, args.kernel)
     stream = torch.cuda.current_stream()
+    nets = load_nets(b, args.warm) if args.warm != "zero" else []
+    modes = ["plain"] + (["learned"] if nets else [])
 
-    def step():
+    def step(mode, ev=None):
+        if ev:
+            ev[0].record(stream)
         db.build(args.pc, precision)
-        db.solve(tol)
+        if ev:
+            ev[1].record(stream)
+        if mode == "learned":
+            db.lam.zero_()
+            for net in nets:
+                net.predict(db)
+            if ev:
+                ev[2].record(stream)
+            db.solve(tol, warm_in_place=True, fallback=True)
+        else:
+            if ev:
+                ev[2].record(stream)
+            db.solve(tol)
+        if ev:
+            ev[3].record(stream)
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    print(f"[bench] warmup {args.warmup} done", file=sys.stderr, flush=True)
+    runs = {}
+    for mode in modes:
+        for _ in range(args.warmup):
+            step(mode)
+        torch.cuda.synchronize()
+        # eager steps with per-phase events
+        ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        for k in range(args.steps):
+            step(mode, ev[k])
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t_start
+        ph = np.array([[e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2]), e[2].elapsed_time(e[3])] for e in ev])
+        res = db.results()
+        run = dict(wall=wall, build_ms=ph[:, 0], predict_ms=ph[:, 1], solve_ms=ph[:, 2], res=res)
+        if args.graph:
+            # the same step captured once into a HIP graph and replayed
+            g = torch.cuda.CUDAGraph()
+            side = torch.cuda.Stream()
+            side.wait_stream(stream)
+            with torch.cuda.stream(side):
+                step(mode)  # allocations and lazily built lists happen outside the capture
+            stream.wait_stream(side)
+            torch.cuda.synchronize()
+            with torch.cuda.graph(g):
+                step(mode)
+            g.replay()
+            torch.cuda.synchronize()
+            t_start = time.perf_counter()
+            for k in range(args.steps):
+                g.replay()
+            torch.cuda.synchronize()
+            run["graph_wall"] = time.perf_counter() - t_start
+            gres = db.results()
+            run["graph_matches_eager"] = bool(np.array_equal(gres["lam"], res["lam"]) and
+                                              np.array_equal(gres["iters"], res["iters"]))
+            del g
+        runs[mode] = run
+        print(f"[bench] {mode}: {args.steps} steps eager {wall:.3f} s"
+              + (f", graph {run['graph_wall']:.3f} s" if args.graph else ""), file=sys.stderr, flush=True)
 
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    for k in range(args.steps):
-        ev[k][0].record(stream)
-        db.build(args.pc, precision)
-        ev[k][1].record(stream)
-        db.solve(tol)
-        ev[k][2].record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t_start
-    build_ms = np.array([e[0].elapsed_time(e[1]) for e in ev])
-    solve_ms = np.array([e[1].elapsed_time(e[2]) for e in ev])
-    step_ms = build_ms + solve_ms
-    res = db.results()
-    print(f"[bench] timed {args.steps} steps: {wall:.2f} s", file=sys.stderr, flush=True)
-
-    ok = bool((res["status"] == 0).all() and res["relres"].max() <= tol)
+    plain = runs["plain"]
+    res = plain["res"]
+    head = runs["learned"] if "learned" in runs else plain
+    head_wall = head.get("graph_wall", head["wall"])
+    ok = bool(all(((r["res"]["status"] & ~8) == 0).all() and r["res"]["relres"].max() <= tol
+                  for r in runs.values()))
+    if args.graph:
+        ok = ok and all(r["graph_matches_eager"] for r in runs.values())
     bytes_solve = float(algorithmic_bytes(b, res["iters"], res["outer"], args.pc, precision, args.kernel).sum())
     rec = MEASURED_TRAFFIC.get((args.workload, args.pc, precision, args.threads or 128, args.kernel))
     traffic = rec[1] if rec and rec[0] == solve_sources_hash() else None
-    solve_avg_s = float(solve_ms.mean()) / 1e3
+    solve_avg_s = float(plain["solve_ms"].mean()) / 1e3
     achieved = bytes_solve / solve_avg_s / 1e9
-    value = b.P * args.steps / wall
+    value = b.P * args.steps / head_wall
 
     compare = None
     if not args.no_compare:
@@ -198,6 +262,21 @@ def main() -> int:
         print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
         cpu = cpu_baseline(b, args.pc, precision, tol, args.cpu_sample)
 
+    def summary(r):
+        d = {"solves_per_s": round(b.P * args.steps / r.get("graph_wall", r["wall"]), 2),
+             "ms_per_step_eager": round(r["wall"] * 1e3 / args.steps, 4),
+             "build_ms": round(float(r["build_ms"].mean()), 4),
+             "predict_ms": round(float(r["predict_ms"].mean()), 4),
+             "solve_ms": round(float(r["solve_ms"].mean()), 4),
+             "iters_mean": round(float(r["res"]["iters"].mean()), 3),
+             "outer_mean": round(float(r["res"]["outer"].mean()), 3),
+             "max_relres": float(r["res"]["relres"].max()),
+             "fallbacks": int(((r["res"]["status"] & 8) != 0).sum())}
+        if "graph_wall" in r:
+            d["ms_per_step_graph"] = round(r["graph_wall"] * 1e3 / args.steps, 4)
+            d["graph_matches_eager"] = r["graph_matches_eager"]
+        return d
+
     out = {
         "metric": "PCG solves/sec & HBM GB/s at rel-res 1e-6, sym-stair, batched+learned vs plain",
         "value": round(value, 2),
@@ -205,7 +284,7 @@ def main() -> int:
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(wall * 1e3 / args.steps, 4),
+        "ms_per_step": round(head_wall * 1e3 / args.steps, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -218,18 +297,17 @@ def main() -> int:
             "preconditioner": args.pc,
             "precision": precision,
             "tol": tol,
-            "warm_start": "zero",
+            "warm_start": "learned (per-knot network, zero fallback)" if "learned" in runs else "zero",
             "kernel": "fused" if args.kernel == 0 else "explicit",
-            "step": "build (FP64 assembly) + solve",
+            "timing": "hipGraph replay of the whole step" if args.graph else "eager launches",
+            "step": ("build (FP64 assembly) + network inference + solve" if "learned" in runs
+                     else "build (FP64 assembly) + solve"),
         },
         "valid": ok,
         "detail": {
-            "build_ms": round(float(build_ms.mean()), 4),
-            "solve_ms": round(float(solve_ms.mean()), 4),
+            "plain": summary(plain),
+            "learned": summary(runs["learned"]) if "learned" in runs else None,
             "solve_only_solves_per_s": round(b.P / solve_avg_s, 2),
-            "iters_mean": round(float(res["iters"].mean()), 3),
-            "outer_mean": round(float(res["outer"].mean()), 3),
-            "max_relres": float(res["relres"].max()),
             "solve_algorithmic_bytes": bytes_solve,
             "compare": compare,
         },

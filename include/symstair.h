@@ -55,7 +55,9 @@ enum {
     SSP_P_NOT_SPD = 1,   /* a Q_k, R_k or D_k has a non-positive pivot */
     SSP_P_MAXITER = 2,   /* max_iter inner iterations or max refinement steps reached */
     SSP_P_NONFINITE = 3, /* NaN/Inf in gamma, lambda0 or a recurrence scalar */
-    SSP_P_BREAKDOWN = 4  /* p^T S p <= 0 or r^T z <= 0 inside PCG */
+    SSP_P_BREAKDOWN = 4, /* p^T S p <= 0 or r^T z <= 0 inside PCG */
+    SSP_P_WARM_FALLBACK = 8 /* bit OR-ed onto the status: the warm start did not
+                               reduce the residual and the solve started from 0 */
 };
 
 typedef enum {
@@ -104,6 +106,11 @@ ssp_status ssp_build(ssp_batch *b, ssp_precon pc, ssp_precision prec, const doub
  *   gamma:    device FP64 [off_v[nprob]] (read only)
  *   lambda:   device FP64, in = initial guess when use_lambda0 != 0,
  *             out = solution (always written)
+ *   use_lambda0: 0 = start from zero; 1 = start from lambda (a non-finite
+ *             entry gives SSP_P_NONFINITE); 2 = start from lambda unless its
+ *             FP64 residual is not smaller than ||gamma|| (or not finite),
+ *             in which case the solve starts from zero and the problem's
+ *             status carries SSP_P_WARM_FALLBACK
  *   iters:    device int32[nprob], inner PCG iterations (S-products)
  *   relres:   device FP64[nprob], final true relative residual in FP64
  *   prob_status: device int32[nprob], in = build status (problems that
@@ -137,6 +144,61 @@ ssp_status ssp_export(ssp_batch *b, int which, double *diag, double *off, void *
  * runs.  Returns SSP_ERR_ARG for an unknown value or a budget that cannot
  * hold one knot of the largest nx. */
 ssp_status ssp_set_mapping(ssp_batch *b, int32_t threads, int32_t lds_bytes, int32_t kernel);
+
+/* ---------------------------------------------------------------------------
+ * Learned warm start (per-knot network).
+ *
+ * For a knot k of a problem with state size nx the network reads
+ *   x_k = [vec D_k, vec L_k, gamma_k]   (2 nx^2 + nx inputs, row-major blocks
+ *                                        as stored by the last ssp_build,
+ *                                        L_0 = 0),
+ * standardises it, (x_k - mu) * inv_sd, applies two hidden layers of width H
+ * with the exact GELU and a linear output layer, and scales the output by
+ * y_scale to give lambda0_k.  FP32 throughout (matrix cores).  Parameters are
+ * one float vector: W1 (nin x H, row-major), b1 (H), W2 (H x H), b2, W3
+ * (H x nx), b3 (nx), nin = 2 nx^2 + nx.  Training minimises, over a range of
+ * problems, the mean of || S_p (lambda0_p - lambda*_p) ||^2, i.e. the squared
+ * residual of the warm start when lambda* is the exact solution; optimiser
+ * Adam.  One network serves one state size.  All pointers are device
+ * pointers unless stated; calls are asynchronous on `stream` unless stated.
+ * ------------------------------------------------------------------------- */
+typedef struct ssp_mlp ssp_mlp;
+
+/* Number of parameters for state size nx and hidden width H (-1 if invalid). */
+int64_t ssp_mlp_num_params(int32_t nx, int32_t hidden);
+/* New network for state size nx in [1, 64], hidden width a multiple of 16 in
+ * [16, 512]; parameters zero, mu = 0, inv_sd = 1, y_scale = 1. */
+ssp_status ssp_mlp_create(int32_t nx, int32_t hidden, int device, ssp_mlp **out);
+ssp_status ssp_mlp_destroy(ssp_mlp *m);
+/* Copy parameters in (resets the Adam moments and step count) / out.
+ * get_params copies the parameters and/or the last gradient (either may be
+ * NULL, not both). */
+ssp_status ssp_mlp_set_params(ssp_mlp *m, const float *theta, void *stream);
+ssp_status ssp_mlp_get_params(const ssp_mlp *m, float *theta, float *grad, void *stream);
+/* Standardisation: mu, inv_sd: float[nin]; y_scale > 0 (host value). */
+ssp_status ssp_mlp_set_scaling(ssp_mlp *m, const float *mu, const float *inv_sd, float y_scale, void *stream);
+ssp_status ssp_mlp_get_scaling(const ssp_mlp *m, float *mu, float *inv_sd, float *y_scale, void *stream);
+/* Fit the standardisation to every knot of the batch's problems with this
+ * network's nx: per-input mean and 1 / max(population std, 1e-6), and
+ * y_scale = root mean square of lambda_star there.  The batch must be built;
+ * gamma, lambda_star: FP64 vector layout.  Synchronises the stream. */
+ssp_status ssp_mlp_fit_scaling(ssp_mlp *m, ssp_batch *b, const double *gamma, const double *lambda_star,
+                               void *stream);
+/* Write lambda0 (FP64 vector layout) at every knot of the batch's problems
+ * with this network's nx; other problems' entries are left untouched.  Pass
+ * lambda0 to ssp_solve with use_lambda0 = 2 to keep zero as the fallback. */
+ssp_status ssp_mlp_predict(ssp_mlp *m, ssp_batch *b, const double *gamma, double *lambda0, void *stream);
+/* Loss and gradient over problems [p0, p1) of a built batch (all of this
+ * network's nx): the gradient stays in the handle for ssp_mlp_adam; loss
+ * (FP64[1], may be NULL) receives the mean squared warm-start residual. */
+ssp_status ssp_mlp_loss_grad(ssp_mlp *m, ssp_batch *b, int32_t p0, int32_t p1, const double *gamma,
+                             const double *lambda_star, double *loss, void *stream);
+/* One Adam step (Kingma & Ba, bias-corrected) with the last gradient. */
+ssp_status ssp_mlp_adam(ssp_mlp *m, float lr, float beta1, float beta2, float eps, void *stream);
+/* FP32 matrix-core GEMM the network uses, C = op(A) op(B) (row-major, op =
+ * transpose when trans_* != 0); exposed for tests. */
+ssp_status ssp_gemm_f32(int32_t M, int32_t N, int32_t K, const float *A, int32_t lda, int32_t trans_a,
+                        const float *B, int32_t ldb, int32_t trans_b, float *C, int32_t ldc, void *stream);
 
 /* Human-readable text of a call-level status, and of the last HIP error seen
  * by this thread (static storage, never NULL). */

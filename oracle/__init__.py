@@ -19,6 +19,7 @@ _SRC = os.path.join(_HERE, "ssp_oracle.c")
 _LIB = os.path.join(_HERE, "libssp_oracle.so")
 
 OK, NOT_SPD, MAXITER, NONFINITE, BREAKDOWN = 0, 1, 2, 3, 4
+WARM_FALLBACK = 8  # OR-ed onto a status: the warm start was replaced by zero
 PC = {"bj": 0, "add": 1, "sym": 2}
 PREC = {"fp64": 0, "fp32": 1, "fp32_refine64": 2}
 # refinement constants: inner tolerance tau_j = clamp(THETA*tol*|g|/|r_j|, TAU_MIN, 1)
@@ -58,7 +59,7 @@ def lib():
         L.ssp_oracle_direct.restype = i
         L.ssp_oracle_solve_batch.argtypes = [i, ip, ip, ip, i64, i64, i64, i64, d, d, d, d, d,
                                              i, i, C.c_double, i, i, C.c_double, C.c_double,
-                                             d, ip, ip, d, ip]
+                                             i, d, ip, ip, d, ip]
         _lib = L
     return _lib
 
@@ -139,11 +140,13 @@ def direct(D, L, gamma):
 
 def solve_batch(b, pc: str = "sym", precision: str = "fp64", tol: float = 1e-8,
                 max_iter: int | None = None, lam0=None, max_outer=MAX_OUTER, theta=THETA,
-                tau_min=TAU_MIN):
+                tau_min=TAU_MIN, fallback: bool = False):
     """Build + solve every problem of a packed batch (OpenMP over problems).
 
     Returns dict(lam, iters, outer, relres, status).  ``max_iter`` defaults to
     10 * N * nx per problem (the largest problem's value is used for all).
+    With ``fallback``, a start ``lam0`` whose residual is not below ||gamma||
+    is replaced by zero and the status carries WARM_FALLBACK.
     """
     P = b.P
     ip = lambda a: np.ascontiguousarray(a, dtype=np.int32).ctypes.data_as(C.POINTER(C.c_int))
@@ -158,6 +161,6 @@ def solve_batch(b, pc: str = "sym", precision: str = "fp64", tol: float = 1e-8,
     A, B, Q, R, g = map(_f64, (b.A, b.B, b.Q, b.R, b.gamma))
     lib().ssp_oracle_solve_batch(P, ip(N32), ip(nx32), ip(nu32), *(i64(o) for o in offs),
                                  _dp(A), _dp(B), _dp(Q), _dp(R), _dp(g), PC[pc], PREC[precision],
-                                 tol, max_iter, max_outer, theta, tau_min, _dp(lam), ip(iters),
+                                 tol, max_iter, max_outer, theta, tau_min, int(fallback), _dp(lam), ip(iters),
                                  ip(outer), _dp(rel), ip(status))
     return dict(lam=lam, iters=iters, outer=outer, relres=rel, status=status)

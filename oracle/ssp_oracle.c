@@ -42,6 +42,7 @@
 #define OR_MAXITER 2
 #define OR_NONFINITE 3
 #define OR_BREAKDOWN 4
+#define OR_WARM_FALLBACK 8 /* OR-ed: the warm start was replaced by zero */
 
 #define OR_PC_BJ 0
 #define OR_PC_ADD 1
@@ -464,7 +465,8 @@ void ssp_oracle_solve_batch(int P, const int *Ns, const int *nxs, const int *nus
                             const int64_t *off_v, const double *A, const double *B, const double *Q,
                             const double *R, const double *gamma, int pc, int precision,
                             double tol, int max_iter, int max_outer, double theta, double tau_min,
-                            double *lam, int *iters, int *outer, double *relres, int *status) {
+                            int warm_fallback, double *lam, int *iters, int *outer, double *relres,
+                            int *status) {
 #pragma omp parallel for schedule(dynamic, 1)
     for (int p = 0; p < P; ++p) {
         const int N = Ns[p], nx = nxs[p], nu = nus[p];
@@ -476,6 +478,15 @@ void ssp_oracle_solve_batch(int P, const int *Ns, const int *nxs, const int *nus
         int it = 0, ou = 0;
         int st = ssp_oracle_build(N, nx, nu, A + off_nn[p], B + off_nu[p], Q + off_nn[p],
                                   R + off_uu[p], pc, D, L, Di, M);
+        int fell_back = 0;
+        if (st == OR_OK && warm_fallback) {
+            /* a warm start whose residual is not below ||gamma|| is replaced by zero */
+            const double rr = ssp_oracle_relres(N, nx, D, L, g, x);
+            if (!(rr < 1.0)) {
+                memset(x, 0, sizeof(double) * (size_t)N * nx);
+                fell_back = OR_WARM_FALLBACK;
+            }
+        }
         if (st == OR_OK) {
             if (precision == OR_FP64) {
                 st = ssp_oracle_pcg(N, nx, D, L, Di, M, g, tol, max_iter, x, &it);
@@ -491,7 +502,7 @@ void ssp_oracle_solve_batch(int P, const int *Ns, const int *nxs, const int *nus
         }
         iters[p] = it;
         outer[p] = ou;
-        status[p] = st;
+        status[p] = st | fell_back;
         free(D); free(L); free(Di); free(M);
     }
 }

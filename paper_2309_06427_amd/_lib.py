@@ -12,6 +12,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsymstair
 
 SSP_OK, SSP_ERR_ARG, SSP_ERR_ALLOC, SSP_ERR_HIP, SSP_ERR_STATE = range(5)
 SSP_P_OK, SSP_P_NOT_SPD, SSP_P_MAXITER, SSP_P_NONFINITE, SSP_P_BREAKDOWN = range(5)
+SSP_P_WARM_FALLBACK = 8
 SSP_PC_BLOCK_JACOBI, SSP_PC_STAIR_ADD, SSP_PC_SYM_STAIR = range(3)
 SSP_FP64, SSP_FP32, SSP_FP32_REFINE64 = range(3)
 
@@ -19,7 +20,7 @@ PC = {"bj": SSP_PC_BLOCK_JACOBI, "add": SSP_PC_STAIR_ADD, "sym": SSP_PC_SYM_STAI
 PREC = {"fp64": SSP_FP64, "fp32": SSP_FP32, "fp32_refine64": SSP_FP32_REFINE64}
 
 # every symbol the header declares: name -> (restype, argtypes)
-_vp, _i32, _i64, _d = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+_vp, _i32, _i64, _d, _f = C.c_void_p, C.c_int32, C.c_int64, C.c_double, C.c_float
 _pi32, _pi64 = C.POINTER(C.c_int32), C.POINTER(C.c_int64)
 SIGNATURES = {
     "ssp_batch_create": (C.c_int, [_i32, _pi32, _pi32, _pi32, C.c_int, C.POINTER(_vp)]),
@@ -30,6 +31,18 @@ SIGNATURES = {
     "ssp_export": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp]),
     "ssp_solve_outer": (C.c_int, [_vp, _vp, _vp]),
     "ssp_set_mapping": (C.c_int, [_vp, _i32, _i32, _i32]),
+    "ssp_mlp_num_params": (_i64, [_i32, _i32]),
+    "ssp_mlp_create": (C.c_int, [_i32, _i32, C.c_int, C.POINTER(_vp)]),
+    "ssp_mlp_destroy": (C.c_int, [_vp]),
+    "ssp_mlp_set_params": (C.c_int, [_vp, _vp, _vp]),
+    "ssp_mlp_get_params": (C.c_int, [_vp, _vp, _vp, _vp]),
+    "ssp_mlp_set_scaling": (C.c_int, [_vp, _vp, _vp, _f, _vp]),
+    "ssp_mlp_get_scaling": (C.c_int, [_vp, _vp, _vp, C.POINTER(_f), _vp]),
+    "ssp_mlp_fit_scaling": (C.c_int, [_vp, _vp, _vp, _vp, _vp]),
+    "ssp_mlp_predict": (C.c_int, [_vp, _vp, _vp, _vp, _vp]),
+    "ssp_mlp_loss_grad": (C.c_int, [_vp, _vp, _i32, _i32, _vp, _vp, _vp, _vp]),
+    "ssp_mlp_adam": (C.c_int, [_vp, _f, _f, _f, _f, _vp]),
+    "ssp_gemm_f32": (C.c_int, [_i32, _i32, _i32, _vp, _i32, _i32, _vp, _i32, _i32, _vp, _i32, _vp]),
     "ssp_status_str": (C.c_char_p, [C.c_int]),
     "ssp_last_error": (C.c_char_p, []),
 }

@@ -10,84 +10,13 @@
 #include <vector>
 
 #include "../../include/symstair.h"
+#include "ssp_batch.h"
 #include "ssp_host.h"
 #include "ssp_sweep.h"
 
-namespace {
+using namespace ssp_host;
 
-thread_local std::string g_last_error = "no error";
-
-ssp_status hip_fail(hipError_t e, const char *what) {
-    g_last_error = std::string(what) + ": " + hipGetErrorString(e);
-    return SSP_ERR_HIP;
-}
-
-#define SSP_HIP(call)                                   \
-    do {                                                \
-        hipError_t e_ = (call);                         \
-        if (e_ != hipSuccess) return hip_fail(e_, #call); \
-    } while (0)
-
-struct DevGuard {
-    int prev = -1;
-    explicit DevGuard(int dev) {
-        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-        if (prev != dev) (void)hipSetDevice(dev);
-    }
-    ~DevGuard() {
-        if (prev >= 0) (void)hipSetDevice(prev);
-    }
-};
-
-template <typename T>
-hipError_t dalloc(T **p, size_t count) {
-    *p = nullptr;
-    if (count == 0) count = 1;
-    return hipMalloc((void **)p, count * sizeof(T));
-}
-
-}  // namespace
-
-struct ssp_batch {
-    int device = 0;
-    int P = 0;
-    std::vector<int32_t> N, nx, nu;
-    std::vector<int64_t> off_nn, off_nu, off_uu, off_v, koff;
-    std::vector<int64_t> off_blk32, off_blk64;  // stored-block offsets (padded stride)
-    int nx_max = 1, nu_max = 0;
-    int64_t knots = 0;
-    // device metadata
-    int32_t *dN = nullptr, *dnx = nullptr, *dnu = nullptr, *dorder = nullptr, *dknot = nullptr;
-    // assembly work lists: per compiled state size, (problem, first knot)
-    // items at ditems + item_off[c]; knots of the other problems in dgeneric
-    int2 *ditems = nullptr;
-    int32_t *dgeneric = nullptr;
-    int item_off[ssp::kBuildClasses + 1] = {};
-    int64_t n_generic = 0;
-    int gen_nx_max = 1, gen_nu_max = 0;
-    int64_t *doff_nn = nullptr, *doff_nu = nullptr, *doff_uu = nullptr, *doff_v = nullptr, *dkoff = nullptr;
-    int64_t *doff_blk32 = nullptr, *doff_blk64 = nullptr;
-    // FP64 build workspaces
-    double *Qinv = nullptr, *Rinv = nullptr;
-    // stored matrices
-    bool fp32 = false;
-    bool have_storage = false;
-    void *B3 = nullptr;  // per knot: D_k, L_k, D_k^-1 (storage type, padded stride bs each)
-    void *PM = nullptr;  // explicit stair blocks, built on demand
-    float *SDlo = nullptr, *SLlo = nullptr;
-    // solve workspace
-    void *work = nullptr;
-    double *r64 = nullptr;
-    int32_t *douter = nullptr;
-    // state
-    bool built = false;
-    bool m_valid = false;  // explicit stair blocks PM match the last build
-    ssp_precon pc = SSP_PC_SYM_STAIR;
-    ssp_precision prec = SSP_FP64;
-    int threads = 128;
-    int lds_bytes = 0;  // 0: default
-    int kernel = 0;     // 0 fused single-sweep, 1 explicit two-sweep
-};
+thread_local std::string ssp_host::g_last_error = "no error";
 
 namespace {
 
@@ -203,7 +132,7 @@ const char *ssp_status_str(ssp_status s) {
     return "unknown status";
 }
 
-const char *ssp_last_error(void) { return g_last_error.c_str(); }
+const char *ssp_last_error(void) { return ssp_host::g_last_error.c_str(); }
 
 ssp_status ssp_batch_create(int32_t nprob, const int32_t *N, const int32_t *nx, const int32_t *nu, int device,
                             ssp_batch **out) {
@@ -329,6 +258,8 @@ ssp_status ssp_batch_destroy(ssp_batch *b) {
         DevGuard g(b->device);
         (void)hipDeviceSynchronize();
         free_storage(b);
+        for (auto &kl : b->nx_knots)
+            if (kl.second.first) (void)hipFree(kl.second.first);
         for (void *p : {(void *)b->dN, (void *)b->dnx, (void *)b->dnu, (void *)b->dorder, (void *)b->dknot,
                         (void *)b->ditems, (void *)b->dgeneric, (void *)b->doff_nn, (void *)b->doff_nu, (void *)b->doff_uu, (void *)b->doff_v,
                         (void *)b->dkoff, (void *)b->doff_blk32, (void *)b->doff_blk64, (void *)b->Qinv, (void *)b->Rinv,
@@ -394,7 +325,7 @@ ssp_status ssp_build(ssp_batch *b, ssp_precon pc, ssp_precision prec, const doub
 ssp_status ssp_solve(ssp_batch *b, double rel_tol, int32_t max_iter, const double *gamma, double *lambda,
                      int use_lambda0, int32_t *iters, double *relres, int32_t *prob_status, void *stream) {
     if (!b || !gamma || !lambda || !iters || !relres || !prob_status) return SSP_ERR_ARG;
-    if (!(rel_tol >= 0.0)) return SSP_ERR_ARG;
+    if (!(rel_tol >= 0.0) || use_lambda0 < 0 || use_lambda0 > 2) return SSP_ERR_ARG;
     if (!b->built) return SSP_ERR_STATE;
     DevGuard g(b->device);
     hipStream_t s = (hipStream_t)stream;
@@ -411,7 +342,7 @@ ssp_status ssp_solve(ssp_batch *b, double rel_tol, int32_t max_iter, const doubl
     a.pc = (int)b->pc;
     a.gamma = gamma;
     a.lambda = lambda;
-    a.use_lambda0 = use_lambda0 ? 1 : 0;
+    a.use_lambda0 = use_lambda0;
     a.tol = rel_tol;
     a.max_iter = max_iter;
     a.refine = b->prec == SSP_FP32_REFINE64 ? 1 : 0;

@@ -70,14 +70,15 @@ __global__ __launch_bounds__(BLOCK) void k_pcg(SolveArgs a) {
     for (int row = tid; row < n; row += BLOCK) {
         const double gv = gam[row];
         gg += gv * gv;
-        if (a.use_lambda0) {
+        if (a.use_lambda0 == 1) {
             if (!isfinite(lam[row])) bad = 1.0;
-        } else {
+        } else if (a.use_lambda0 == 0) {
             lam[row] = 0.0;
         }
     }
     block_sum2<BLOCK>(gg, bad, red64);
     int total = 0, steps = 0;
+    bool fallback = false;  // the warm start was dropped for lambda = 0
     double rnorm = 0.0;
     const double gnorm = sqrt(gg);
     if (!isfinite(gnorm) || bad != 0.0) {
@@ -104,6 +105,16 @@ __global__ __launch_bounds__(BLOCK) void k_pcg(SolveArgs a) {
                 });
             rr64 = block_sum<BLOCK>(rr64, red64);
             rnorm = sqrt(rr64);
+            if (steps == 0 && a.use_lambda0 == 2 && !(rnorm < gnorm)) {
+                // a warm start that does not reduce the residual is replaced by zero
+                for (int row = tid; row < n; row += BLOCK) {
+                    lam[row] = 0.0;
+                    r64[row] = gam[row];
+                }
+                rnorm = gnorm;
+                fallback = true;
+                __syncthreads();
+            }
             if (!isfinite(rnorm)) {
                 st = kNonFinite;
                 break;
@@ -207,7 +218,7 @@ __global__ __launch_bounds__(BLOCK) void k_pcg(SolveArgs a) {
         a.iters[p] = total;
         a.outer[p] = steps;
         a.relres[p] = gg == 0.0 ? 0.0 : rnorm / gnorm;
-        a.status[p] = st;
+        a.status[p] = st | (fallback ? kWarmFallback : 0);
     }
 }
 

@@ -430,6 +430,7 @@ struct Prob {
 // Outcome of one problem's solve.
 struct Outcome {
     int st = kOk, total = 0, steps = 0;
+    bool fallback = false;  // the warm start was dropped for lambda = 0
     double rnorm = 0.0;
 };
 
@@ -469,6 +470,16 @@ __device__ __forceinline__ Outcome solve_problem(const SolveArgs &a, const Prob<
             });
         rr64 = block_sum<BLOCK>(rr64, red64);
         o.rnorm = sqrt(rr64);
+        if (o.steps == 0 && a.use_lambda0 == 2 && !(o.rnorm < q.gnorm)) {
+            // a warm start that does not reduce the residual is replaced by zero
+            for (int row = tid; row < n; row += BLOCK) {
+                q.lam[row] = 0.0;
+                q.r64[row] = q.gam[row];
+            }
+            o.rnorm = q.gnorm;
+            o.fallback = true;
+            __syncthreads();
+        }
         if (!isfinite(o.rnorm)) {
             o.st = kNonFinite;
             break;
@@ -590,9 +601,9 @@ __global__ __launch_bounds__(BLOCK, 2) void k_pcg2(SolveArgs a) {
     for (int row = tid; row < n; row += BLOCK) {
         const double gv = q.gam[row];
         gg += gv * gv;
-        if (a.use_lambda0) {
+        if (a.use_lambda0 == 1) {
             if (!isfinite(q.lam[row])) bad = 1.0;
-        } else {
+        } else if (a.use_lambda0 == 0) {
             q.lam[row] = 0.0;
         }
     }
@@ -617,7 +628,7 @@ __global__ __launch_bounds__(BLOCK, 2) void k_pcg2(SolveArgs a) {
         a.iters[p] = o.total;
         a.outer[p] = o.steps;
         a.relres[p] = gg == 0.0 ? 0.0 : o.rnorm / q.gnorm;
-        a.status[p] = o.st;
+        a.status[p] = o.st | (o.fallback ? kWarmFallback : 0);
     }
 }
 

@@ -1,0 +1,89 @@
+// Host-side state of a batch handle and helpers shared by the host sources.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/symstair.h"
+#include "ssp_host.h"
+
+namespace ssp_host {
+
+extern thread_local std::string g_last_error;
+
+inline ssp_status hip_fail(hipError_t e, const char *what) {
+    g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+    return SSP_ERR_HIP;
+}
+
+#define SSP_HIP(call)                                               \
+    do {                                                            \
+        hipError_t e_ = (call);                                     \
+        if (e_ != hipSuccess) return ssp_host::hip_fail(e_, #call); \
+    } while (0)
+
+struct DevGuard {
+    int prev = -1;
+    explicit DevGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DevGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+template <typename T>
+hipError_t dalloc(T **p, size_t count) {
+    *p = nullptr;
+    if (count == 0) count = 1;
+    return hipMalloc((void **)p, count * sizeof(T));
+}
+
+}  // namespace ssp_host
+
+struct ssp_batch {
+    int device = 0;
+    int P = 0;
+    std::vector<int32_t> N, nx, nu;
+    std::vector<int64_t> off_nn, off_nu, off_uu, off_v, koff;
+    std::vector<int64_t> off_blk32, off_blk64;  // stored-block offsets (padded stride)
+    int nx_max = 1, nu_max = 0;
+    int64_t knots = 0;
+    // device metadata
+    int32_t *dN = nullptr, *dnx = nullptr, *dnu = nullptr, *dorder = nullptr, *dknot = nullptr;
+    // assembly work lists: per compiled state size, (problem, first knot)
+    // items at ditems + item_off[c]; knots of the other problems in dgeneric
+    int2 *ditems = nullptr;
+    int32_t *dgeneric = nullptr;
+    int item_off[ssp::kBuildClasses + 1] = {};
+    int64_t n_generic = 0;
+    int gen_nx_max = 1, gen_nu_max = 0;
+    // global knot lists per state size (built on first use by the warm start)
+    std::vector<std::pair<int, std::pair<int32_t *, int64_t>>> nx_knots;
+    int64_t *doff_nn = nullptr, *doff_nu = nullptr, *doff_uu = nullptr, *doff_v = nullptr, *dkoff = nullptr;
+    int64_t *doff_blk32 = nullptr, *doff_blk64 = nullptr;
+    // FP64 build workspaces
+    double *Qinv = nullptr, *Rinv = nullptr;
+    // stored matrices
+    bool fp32 = false;
+    bool have_storage = false;
+    void *B3 = nullptr;  // per knot: D_k, L_k, D_k^-1 (storage type, padded stride bs each)
+    void *PM = nullptr;  // explicit stair blocks, built on demand
+    float *SDlo = nullptr, *SLlo = nullptr;
+    // solve workspace
+    void *work = nullptr;
+    double *r64 = nullptr;
+    int32_t *douter = nullptr;
+    // state
+    bool built = false;
+    bool m_valid = false;  // explicit stair blocks PM match the last build
+    ssp_precon pc = SSP_PC_SYM_STAIR;
+    ssp_precision prec = SSP_FP64;
+    int threads = 128;
+    int lds_bytes = 0;  // 0: default
+    int kernel = 0;     // 0 fused single-sweep, 1 explicit two-sweep
+};

@@ -58,10 +58,12 @@ class BatchSolver:
         check(_lib.load().ssp_build(self._h, PC[pc], PREC[precision], _ptr(A), _ptr(B), _ptr(Q), _ptr(R),
                                     _ptr(status), _stream(stream)), "ssp_build")
 
-    def solve(self, tol: float, max_iter: int, gamma, lam, use_lambda0: bool, iters, relres, status,
+    def solve(self, tol: float, max_iter: int, gamma, lam, use_lambda0: int, iters, relres, status,
               stream=None):
+        """use_lambda0: 0 zero start, 1 start from lam, 2 start from lam with
+        zero as the fallback when lam does not reduce the residual."""
         check(_lib.load().ssp_solve(self._h, float(tol), int(max_iter), _ptr(gamma), _ptr(lam),
-                                    int(bool(use_lambda0)), _ptr(iters), _ptr(relres), _ptr(status),
+                                    int(use_lambda0), _ptr(iters), _ptr(relres), _ptr(status),
                                     _stream(stream)), "ssp_solve")
 
     def solve_outer(self, outer, stream=None):
@@ -97,10 +99,16 @@ class DeviceBatch:
     def build(self, pc: str = "sym", precision: str = "fp32_refine64", stream=None):
         self.solver.build(pc, precision, self.A, self.B, self.Q, self.R, self.status, stream)
 
-    def solve(self, tol: float = 1e-6, max_iter: int = 0, lam0=None, stream=None):
+    def solve(self, tol: float = 1e-6, max_iter: int = 0, lam0=None, fallback: bool = False,
+              warm_in_place: bool = False, stream=None):
+        """Solve from zero, from ``lam0`` (copied in), or from what ``self.lam``
+        already holds (``warm_in_place``, e.g. written by a warm-start network);
+        with ``fallback`` a start that does not reduce the residual is dropped."""
         if lam0 is not None:
             self.lam.copy_(lam0)
-        self.solver.solve(tol, max_iter, self.gamma, self.lam, lam0 is not None, self.iters, self.relres,
+        warm = lam0 is not None or warm_in_place
+        use = (2 if fallback else 1) if warm else 0
+        self.solver.solve(tol, max_iter, self.gamma, self.lam, use, self.iters, self.relres,
                           self.status, stream)
         self.solver.solve_outer(self.outer, stream)
 

@@ -44,3 +44,20 @@ def test_create_rejects_bad_sizes_without_touching_memory():
     # nprob = 0 is rejected before any device call
     assert L.ssp_batch_create(0, p, p, p, 0, C.byref(h)) == _lib.SSP_ERR_ARG
     assert L.ssp_batch_create(1, None, p, p, 0, C.byref(h)) == _lib.SSP_ERR_ARG
+
+
+def test_mlp_param_count_matches_the_layout():
+    from oracle import mlp
+    L = _lib.load()
+    for nx, H in ((6, 128), (14, 128), (26, 128), (3, 16)):
+        assert L.ssp_mlp_num_params(nx, H) == mlp.n_params(nx, H)
+    assert L.ssp_mlp_num_params(0, 128) == -1
+
+
+def test_mlp_create_rejects_bad_sizes():
+    import ctypes as C
+    L = _lib.load()
+    h = C.c_void_p()
+    assert L.ssp_mlp_create(0, 128, 0, C.byref(h)) == _lib.SSP_ERR_ARG
+    assert L.ssp_mlp_create(6, 100, 0, C.byref(h)) == _lib.SSP_ERR_ARG
+    assert L.ssp_mlp_create(6, 128, 0, None) == _lib.SSP_ERR_ARG
