@@ -233,8 +233,12 @@ def main() -> int:
 
     plain = runs["plain"]
     res = plain["res"]
-    head = runs["learned"] if "learned" in runs else plain
-    head_wall = head.get("graph_wall", head["wall"])
+    # headline: the faster of the two ways to run the step (both are reported)
+    def step_wall(r):
+        return r.get("graph_wall", r["wall"])
+    head_mode = min(runs, key=lambda m: step_wall(runs[m]))
+    head = runs[head_mode]
+    head_wall = step_wall(head)
     ok = bool(all(((r["res"]["status"] & ~8) == 0).all() and r["res"]["relres"].max() <= tol
                   for r in runs.values()))
     if args.graph:
@@ -297,10 +301,10 @@ def main() -> int:
             "preconditioner": args.pc,
             "precision": precision,
             "tol": tol,
-            "warm_start": "learned (per-knot network, zero fallback)" if "learned" in runs else "zero",
+            "warm_start": "learned (per-knot network, zero fallback)" if head_mode == "learned" else "zero",
             "kernel": "fused" if args.kernel == 0 else "explicit",
             "timing": "hipGraph replay of the whole step" if args.graph else "eager launches",
-            "step": ("build (FP64 assembly) + network inference + solve" if "learned" in runs
+            "step": ("build (FP64 assembly) + network inference + solve" if head_mode == "learned"
                      else "build (FP64 assembly) + solve"),
         },
         "valid": ok,

@@ -173,9 +173,10 @@ __device__ __forceinline__ T block_dot(const T *__restrict__ blk, int i, const T
         static_assert(NX % 2 == 0, "compiled state sizes are even");
         using P2 = typename std::conditional<sizeof(T) == 4, f32x2, f64x2>::type;
         T s[4] = {T(0), T(0), T(0), T(0)};
-        static_for<0, (NX + kChunk - 1) / kChunk>([&](auto cc) {
-            constexpr int j0 = decltype(cc)::value * kChunk;
-            constexpr int jn = NX - j0 < kChunk ? NX - j0 : kChunk;
+        constexpr int CH = sizeof(T) == 4 ? kChunk : kChunk / 2;  // FP64: half the registers per chunk
+        static_for<0, (NX + CH - 1) / CH>([&](auto cc) {
+            constexpr int j0 = decltype(cc)::value * CH;
+            constexpr int jn = NX - j0 < CH ? NX - j0 : CH;
             T xr[jn], ar[jn];
             static_for<0, jn / 2>([&](auto hc) {
                 constexpr int j = 2 * decltype(hc)::value;
@@ -415,6 +416,133 @@ __device__ __forceinline__ Dots<TI> fused_pass(const Geo2 &g, int pc, bool init,
     return d;
 }
 
+// 16-byte prefetch registers of the residual pass per array (FP32 storage
+// loads hi and lo vectors, FP64 storage hi only)
+template <typename TM>
+constexpr int residual_slots() { return sizeof(TM) == 4 ? 8 : 16; }
+
+// Knots per step of the pipelined FP64 residual pass for a compiled state
+// size (< 1: it cannot run and the staged sweep is used).  LDS: a ring of
+// C + 1 knots of D and L in FP64 (2 bs doubles each) and a lambda window of
+// C + 2 knots.
+template <typename TM>
+__host__ __device__ inline int residual_knots_per_step(int nx, int block, int lds_bytes) {
+    const int V = 16 / (int)sizeof(TM);
+    const int bs = block_stride(nx, sizeof(TM));
+    const int nxp = (nx + 1) & ~1;
+    int C = (block / 64) * (64 / nx);
+    const int Cp = (residual_slots<TM>() * block * V) / (2 * bs);
+    if (Cp < C) C = Cp;
+    const int Cl = (lds_bytes / 8 - nxp) / (2 * bs + nxp) - 1;
+    if (Cl < C) C = Cl;
+    return C;
+}
+
+// r = gamma - S lambda in FP64 with S read as hi + lo (FP32 storage) or
+// FP64, pipelined like the fused pass: the next step's D and L blocks are
+// prefetched into registers while the current step computes, then stored
+// into an LDS ring as FP64.  Step c stores knots [k0, k1) and forms r one
+// knot behind (r_k needs L_{k+1}).  Writes r64, returns this thread's part of
+// ||r||^2.  The same wave mapping as the fused pass (lane -> knot, row).
+template <typename TM, int BLOCK, int NX>
+__device__ __forceinline__ double residual_pass(int N, int C, const TM *__restrict__ B3,
+                                                const float *__restrict__ Dlo, const float *__restrict__ Llo,
+                                                const double *__restrict__ lam, const double *__restrict__ gam,
+                                                double *__restrict__ r64, double *smem) {
+    using VT = typename Vec16<TM>::T;
+    constexpr int V = Vec16<TM>::V;
+    constexpr int KP = residual_slots<TM>();
+    constexpr bool LO = sizeof(TM) == 4;
+    constexpr int W = BLOCK / 64, KW = 64 / NX, NXP = (NX + 1) & ~1;
+    constexpr int BS = (NX * NX + V - 1) / V * V;  // block stride of the storage
+    constexpr int VPK = 2 * BS / V;                // 16-byte vectors of D and L per knot
+    const int R = C + 1, RL = C + 2, ss = 2 * BS;
+    double *ring = smem, *win = smem + R * ss;  // slot: D (BS doubles), then L
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int kloc = lane / NX, i = lane - kloc * NX;
+    const bool lane_ok = kloc < KW;
+    const int kme = wv * KW + kloc, group = W * KW;
+    VT hi[KP];
+    f32x4 lo[LO ? KP : 1];
+    double lamv = 0.0;
+
+    auto issue = [&](int k0, int kc) {
+        const int nvec = kc * VPK;
+        static_for<0, KP>([&](auto mc) {
+            constexpr int m = decltype(mc)::value;
+            int q = threadIdx.x + m * BLOCK;
+            if (q >= nvec) q = 0;  // surplus slots re-read the first vector
+            const int kk = q / VPK, e = (q - kk * VPK) * V;
+            const int64_t k = k0 + kk;
+            hi[m] = *(const VT *)(B3 + k * 3 * BS + e);
+            if constexpr (LO) {
+                const float *src = e < BS ? Dlo + k * BS + e : Llo + k * BS + (e - BS);
+                lo[m] = *(const f32x4 *)src;
+            }
+        });
+        const bool lead = lane_ok && kme < kc;
+        lamv = lam[lead ? (int64_t)(k0 + kme) * NX + i : 0];
+    };
+    auto store = [&](int kc, int sb) {
+        const int nvec = kc * VPK;
+        static_for<0, KP>([&](auto mc) {
+            constexpr int m = decltype(mc)::value;
+            const int q = threadIdx.x + m * BLOCK;
+            if (q < nvec) {
+                const int kk = q / VPK, e = (q - kk * VPK) * V;
+                int s = sb + kk;
+                if (s >= R) s -= R;
+                double *dst = ring + s * ss + e;
+                if constexpr (LO) {
+                    const f32x4 h = hi[m], l = lo[m];
+                    f64x2 a, b;
+                    a.x = (double)h.x + (double)l.x;
+                    a.y = (double)h.y + (double)l.y;
+                    b.x = (double)h.z + (double)l.z;
+                    b.y = (double)h.w + (double)l.w;
+                    *(f64x2 *)dst = a;
+                    *(f64x2 *)(dst + 2) = b;
+                } else {
+                    *(f64x2 *)dst = hi[m];
+                }
+            }
+        });
+    };
+
+    double rr = 0.0;
+    const int nsteps = (N + C - 1) / C;
+    __syncthreads();  // lambda rows were just updated by other threads
+    issue(0, min(C, N));
+    int sb = 0, sw = 0;  // ring slot and window slot of knot k0
+    for (int c = 0; c < nsteps; ++c) {
+        const int k0 = c * C, kc = min(C, N - k0), k1 = k0 + kc;
+        const bool last = k1 == N;
+        __syncthreads();  // every reader of the slots refilled below is done
+        store(kc, sb);
+        if (lane_ok && kme < kc) win[slot_of(sw, kme, RL) * NXP + i] = lamv;
+        if (!last) issue(k1, min(C, N - k1));
+        __syncthreads();
+        const int klo = max(k0 - 1, 0), khi = last ? N : k1 - 1;
+        for (int kk = kme; kk < khi - klo; kk += group) {
+            if (!lane_ok) break;
+            const int k = klo + kk, dk = k - k0;
+            const double *Dk = ring + slot_of(sb, dk, R) * ss;
+            double y = col_dot<NX>(Dk, i, win + slot_of(sw, dk, RL) * NXP, NX);  // D_k symmetric
+            if (k > 0) y += row_dot<NX>(Dk + BS, i, win + slot_of(sw, dk - 1, RL) * NXP, NX);
+            if (k + 1 < N)
+                y += col_dot<NX>(ring + slot_of(sb, dk + 1, R) * ss + BS, i, win + slot_of(sw, dk + 1, RL) * NXP, NX);
+            const double r = gam[(int64_t)k * NX + i] - y;
+            r64[(int64_t)k * NX + i] = r;
+            rr += r * r;
+        }
+        sb += C;
+        if (sb >= R) sb -= R;
+        sw += C;
+        if (sw >= RL) sw -= RL;
+    }
+    return rr;
+}
+
 // Pointers of one problem inside the batch buffers.
 template <typename TI>
 struct Prob {
@@ -454,22 +582,36 @@ __device__ __forceinline__ Outcome solve_problem(const SolveArgs &a, const Prob<
     g.R = g.C + 2;
     g.RU = g.C + 3;
     const Geo g64 = make_geo<double>(nx, q.bs, true, a.lds_bytes, BLOCK);
+    const int Cres = NX > 0 ? residual_knots_per_step<TM>(nx, BLOCK, a.lds_bytes) : 0;
     int pending = kOk;
     bool broke = false;  // last inner solve ended in a float breakdown (refinement only)
     double prev = INFINITY;
+    const double *rsrc = q.r64;  // where the next inner solve reads its right-hand side
     for (;;) {
-        // true residual r = gamma - S lambda in FP64
-        double rr64 = 0.0;
-        bt_sweep<double, TM, BLOCK, NX>(
-            N, g64, q.B3, 3 * q.bs, q.SDlo, q.B3 + q.bs, 3 * q.bs, q.SLlo, true, (double *)smem_raw,
-            [&](int row) { return q.lam[row]; },
-            [&](int row, double y, double) {
-                const double r = q.gam[row] - y;
-                q.r64[row] = r;
-                rr64 += r * r;
-            });
-        rr64 = block_sum<BLOCK>(rr64, red64);
-        o.rnorm = sqrt(rr64);
+        if (o.steps == 0 && a.use_lambda0 == 0) {
+            // lambda = 0: the residual is gamma itself, no sweep needed
+            rsrc = q.gam;
+            o.rnorm = q.gnorm;
+        } else {
+            // true residual r = gamma - S lambda in FP64
+            double rr64 = 0.0;
+            if (NX > 0 && Cres >= 1) {
+                rr64 = residual_pass<TM, BLOCK, (NX > 0 ? NX : 2)>(N, Cres, q.B3, q.SDlo, q.SLlo, q.lam, q.gam,
+                                                                   q.r64, (double *)smem_raw);
+            } else {
+                bt_sweep<double, TM, BLOCK, NX>(
+                    N, g64, q.B3, 3 * q.bs, q.SDlo, q.B3 + q.bs, 3 * q.bs, q.SLlo, true, (double *)smem_raw,
+                    [&](int row) { return q.lam[row]; },
+                    [&](int row, double y, double) {
+                        const double r = q.gam[row] - y;
+                        q.r64[row] = r;
+                        rr64 += r * r;
+                    });
+            }
+            rr64 = block_sum<BLOCK>(rr64, red64);
+            o.rnorm = sqrt(rr64);
+            rsrc = q.r64;
+        }
         if (o.steps == 0 && a.use_lambda0 == 2 && !(o.rnorm < q.gnorm)) {
             // a warm start that does not reduce the residual is replaced by zero
             for (int row = tid; row < n; row += BLOCK) {
@@ -478,6 +620,7 @@ __device__ __forceinline__ Outcome solve_problem(const SolveArgs &a, const Prob<
             }
             o.rnorm = q.gnorm;
             o.fallback = true;
+            rsrc = q.gam;
             __syncthreads();
         }
         if (!isfinite(o.rnorm)) {
@@ -506,7 +649,7 @@ __device__ __forceinline__ Outcome solve_problem(const SolveArgs &a, const Prob<
 
         // inner PCG on S d = r / ||r|| from d = 0
         int it = 0, ist = kOk;
-        Dots<TI> dt = fused_pass<TI, BLOCK, NX>(g, a.pc, true, false, TI(0), TI(0), inv_s, q.r64, q.B3, q.Rv, q.Uv,
+        Dots<TI> dt = fused_pass<TI, BLOCK, NX>(g, a.pc, true, false, TI(0), TI(0), inv_s, rsrc, q.B3, q.Rv, q.Uv,
                                                 q.Wv, q.Pv, q.Sv, q.Xv, (TI *)smem_raw);
         block_sum2<BLOCK>(dt.gam, dt.del, redT);
         dt.rho = block_sum<BLOCK>(dt.rho, redT + 2 * (BLOCK / kWave));
