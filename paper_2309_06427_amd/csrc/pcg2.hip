@@ -90,7 +90,7 @@ __host__ __device__ inline int pcg2_knots_per_step(int nx, int block, int lds_by
     const int Cp = (prefetch_slots<TM>() * block * V) / (3 * bs);
     if (Cp < C) C = Cp;
     const int per = (3 * bs + 4 * nxp) * (int)sizeof(TM);
-    const int Cl = (lds_bytes - nxp * (int)sizeof(TM)) / per - 2;
+    const int Cl = (lds_bytes - nxp * (int)sizeof(TM) - 16) / per - 2;  // + one u slot + 16-byte spot
     if (Cl < C) C = Cl;
     return C;  // may be < 1: the mapping cannot run this nx
 }
@@ -136,16 +136,20 @@ struct Prefetch {
     // Copy the prefetched chunk into the block ring (3 bs elements per slot,
     // in the same D, L, D^-1 order): register m lands at
     // (ring slot of k0) * 3 bs + its offset in the chunk, modulo the ring.
-    __device__ __forceinline__ void store(TM *ring, int kc, int sb, int bs, int R) const {
+    // Slots wholly past the chunk are skipped by a uniform branch; in the
+    // partial slot the surplus lanes write a 16-byte scratch spot (dummy)
+    // instead of branching.
+    __device__ __forceinline__ void store(TM *ring, int kc, int sb, int bs, int R, TM *dummy) const {
         const int nvec = 3 * kc * bs / V;
         const int wrap = R * 3 * bs;
+        const int base = sb * 3 * bs;
         static_for<0, kPF>([&](auto mc) {
             constexpr int m = decltype(mc)::value;
-            const int q = threadIdx.x + m * BLOCK;
-            if (q < nvec) {
-                int off = sb * 3 * bs + q * V;
+            if (m * BLOCK < nvec) {
+                const int q = threadIdx.x + m * BLOCK;
+                int off = base + q * V;
                 if (off >= wrap) off -= wrap;
-                *(VT *)(ring + off) = reg[m];
+                *(VT *)(q < nvec ? ring + off : dummy) = reg[m];
             }
         });
     }
@@ -291,7 +295,7 @@ __device__ __forceinline__ Dots<TI> fused_pass(const Geo2 &g, int pc, bool init,
         const int k0 = c * C, kc = min(C, N - k0), k1 = k0 + kc;
         const bool last = k1 == N;
         __syncthreads();  // every reader of the slots about to be refilled is done
-        pf.store(ring, kc, sb, bs, R);
+        pf.store(ring, kc, sb, bs, R, vu + RU * nxp);
         TM cur[6];
 #pragma unroll
         for (int v = 0; v < 6; ++v) cur[v] = pf.vec[v];
@@ -789,14 +793,14 @@ int pcg2_lds(int nx_max, bool fp32, int threads) {
     const int V = 16 / eb;
     const int bs = block_stride(nx_max, eb), nxp = (nx_max + V - 1) / V * V;
     const int per = (3 * bs + 4 * nxp) * eb;
-    int bytes = (C + 2) * per + nxp * eb;
+    int bytes = (C + 2) * per + nxp * eb + 16;
     const int res = bt_sweep_min_lds(nx_max, true, 8);
     if (bytes < res) bytes = res;
     if (bytes > 160 * 1024) {
         // shrink the step to the LDS limit
-        C = (160 * 1024 - nxp * eb) / per - 2;
+        C = (160 * 1024 - nxp * eb - 16) / per - 2;
         if (C < 1 || res > 160 * 1024) return 0;
-        bytes = (C + 2) * per + nxp * eb;
+        bytes = (C + 2) * per + nxp * eb + 16;
         if (bytes < res) bytes = res;
     }
     return bytes;
