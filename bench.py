@@ -116,6 +116,8 @@ def main() -> int:
     ap.add_argument("--warm", default="auto", choices=["auto", "zero", "learned"],
                     help="learned: also run the step with the trained warm-start networks "
                          "(auto: when their weights are present)")
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
+                    help="keep the default mapping instead of timing candidates per state size first")
     ap.add_argument("--no-graph", dest="graph", action="store_false",
                     help="time eager launches only (default: also replay the step as a HIP graph)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
@@ -166,6 +168,13 @@ def main() -> int:
     if args.threads or args.kernel:
         db.solver.set_mapping(args.threads or 128, args.lds, args.kernel)
     stream = torch.cuda.current_stream()
+    mapping = None
+    if args.autotune and not (args.threads or args.lds or args.kernel):
+        db.build(args.pc, precision)
+        mapping = db.autotune(tol)
+        print(f"[bench] autotuned mapping (nx, threads, lds, ms): {mapping}", file=sys.stderr, flush=True)
+    else:
+        mapping = db.solver.mapping()
     nets = load_nets(b, args.warm) if args.warm != "zero" else []
     modes = ["plain"] + (["learned"] if nets else [])
 
@@ -303,6 +312,7 @@ def main() -> int:
             "tol": tol,
             "warm_start": "learned (per-knot network, zero fallback)" if head_mode == "learned" else "zero",
             "kernel": "fused" if args.kernel == 0 else "explicit",
+            "mapping": [{"nx": m[0], "threads": m[1], "lds_bytes": m[2]} for m in mapping] if mapping else None,
             "timing": "hipGraph replay of the whole step" if args.graph else "eager launches",
             "step": ("build (FP64 assembly) + network inference + solve" if head_mode == "learned"
                      else "build (FP64 assembly) + solve"),

@@ -200,6 +200,26 @@ ssp_status ssp_mlp_adam(ssp_mlp *m, float lr, float beta1, float beta2, float ep
 ssp_status ssp_gemm_f32(int32_t M, int32_t N, int32_t K, const float *A, int32_t lda, int32_t trans_a,
                         const float *B, int32_t ldb, int32_t trans_b, float *C, int32_t ldc, void *stream);
 
+/* Autotuner of the fused kernel's mapping.  The batch's problems are solved
+ * in groups of one state size, each group launched on its own stream with its
+ * own workgroup size and LDS budget (the budget sets the knots per pipeline
+ * step, hence workgroups per CU).  ssp_autotune times every candidate
+ * mapping (128 or 256 threads; the largest step and two shorter ones) on
+ * each group alone with this batch's last build and keeps the fastest; it
+ * then solves the whole batch once, so the outputs (same meaning as in
+ * ssp_solve, zero start, max_iter = 10 N nx) hold valid results.  It
+ * synchronises the stream and must not be captured into a graph.
+ * ssp_set_mapping clears the tuned choice.  Does nothing for the explicit
+ * kernel. */
+ssp_status ssp_autotune(ssp_batch *b, double rel_tol, const double *gamma, double *lambda, int32_t *iters,
+                        double *relres, int32_t *prob_status, void *stream);
+/* The mapping in use per solve group (largest total work first): up to
+ * max_groups entries of state size, threads, LDS bytes and the autotuner's
+ * best time in ms (0 if not tuned), host arrays (any may be NULL); the group
+ * count goes to *ngroups. */
+ssp_status ssp_get_mapping(const ssp_batch *b, int32_t max_groups, int32_t *nx, int32_t *threads,
+                           int32_t *lds_bytes, float *tuned_ms, int32_t *ngroups);
+
 /* Human-readable text of a call-level status, and of the last HIP error seen
  * by this thread (static storage, never NULL). */
 const char *ssp_status_str(ssp_status s);

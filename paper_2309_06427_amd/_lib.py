@@ -43,6 +43,8 @@ SIGNATURES = {
     "ssp_mlp_loss_grad": (C.c_int, [_vp, _vp, _i32, _i32, _vp, _vp, _vp, _vp]),
     "ssp_mlp_adam": (C.c_int, [_vp, _f, _f, _f, _f, _vp]),
     "ssp_gemm_f32": (C.c_int, [_i32, _i32, _i32, _vp, _i32, _i32, _vp, _i32, _i32, _vp, _i32, _vp]),
+    "ssp_autotune": (C.c_int, [_vp, _d, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "ssp_get_mapping": (C.c_int, [_vp, _i32, _pi32, _pi32, _pi32, C.POINTER(_f), _pi32]),
     "ssp_status_str": (C.c_char_p, [C.c_int]),
     "ssp_last_error": (C.c_char_p, []),
 }

@@ -58,17 +58,30 @@ ssp_status alloc_storage(ssp_batch *b, bool fp32) {
 }
 
 
-// LDS bytes for the fused kernel, or 0 if the largest knot does not fit its
-// registers or LDS under the current mapping (the explicit kernel runs then).
-int fused_lds(const ssp_batch *b) {
-    if (!ssp::pcg2_threads_ok(b->threads)) return 0;
-    const int need = ssp::pcg2_lds(b->nx_max, b->fp32, b->threads);
-    if (need == 0) return 0;
-    const int lds = b->lds_bytes > 0 ? std::max(b->lds_bytes, ssp::bt_sweep_min_lds(b->nx_max, true, 8)) : need;
-    if (lds > 160 * 1024) return 0;
-    // knots per step decrease with nx, so the largest nx decides
-    if (ssp::pcg2_steps_for(b->nx_max, b->fp32, b->threads, lds) < 1) return 0;
-    return lds;
+// Workgroup size and LDS bytes of the fused kernel for one solve group, or
+// lds = 0 if its knots do not fit the fused kernel's registers or LDS.
+void group_mapping(const ssp_batch *b, const ssp_batch::Group &g, int *threads, int *lds) {
+    const int t = g.threads > 0 ? g.threads : b->threads;
+    *threads = t;
+    *lds = 0;
+    if (!ssp::pcg2_threads_ok(t)) return;
+    const int need = ssp::pcg2_lds(g.nx, b->fp32, t);
+    if (need == 0) return;
+    int l = g.lds > 0 ? g.lds : (b->lds_bytes > 0 ? b->lds_bytes : need);
+    l = std::max(l, ssp::bt_sweep_min_lds(g.nx, true, 8));
+    if (l > ssp::kFusedLdsCap) return;
+    if (ssp::pcg2_steps_for(g.nx, b->fp32, t, l) < 1) return;
+    *lds = l;
+}
+
+// every group can run the fused kernel
+bool fused_ok(const ssp_batch *b) {
+    for (const auto &g : b->groups) {
+        int t, l;
+        group_mapping(b, g, &t, &l);
+        if (l == 0) return false;
+    }
+    return true;
 }
 
 int explicit_lds(const ssp_batch *b) {
@@ -114,6 +127,86 @@ ssp_status ensure_m(ssp_batch *b, hipStream_t s) {
     ssp::BuildArgs a = build_args(b);
     SSP_HIP(ssp::launch_build_phi(a, b->knots, b->nx_max, b->fp32, s));
     b->m_valid = true;
+    return SSP_OK;
+}
+
+ssp::SolveArgs solve_args(const ssp_batch *b, double rel_tol, int32_t max_iter, const double *gamma,
+                          double *lambda, int use_lambda0, int32_t *iters, double *relres, int32_t *prob_status) {
+    ssp::SolveArgs a{};
+    a.order = b->dorder;
+    a.N = b->dN;
+    a.nx = b->dnx;
+    a.off_blk = b->fp32 ? b->doff_blk32 : b->doff_blk64;
+    a.off_v = b->doff_v;
+    a.status = prob_status;
+    a.B3 = b->B3;
+    a.SDlo = b->fp32 ? b->SDlo : nullptr;
+    a.SLlo = b->fp32 ? b->SLlo : nullptr;
+    a.pc = (int)b->pc;
+    a.gamma = gamma;
+    a.lambda = lambda;
+    a.use_lambda0 = use_lambda0;
+    a.tol = rel_tol;
+    a.max_iter = max_iter;
+    a.refine = b->prec == SSP_FP32_REFINE64 ? 1 : 0;
+    a.max_outer = a.refine ? 5 : 1;
+    a.theta = 0.5;
+    a.tau_min = 1e-6;
+    a.iters = iters;
+    a.outer = b->douter;
+    a.relres = relres;
+    a.work = b->work;
+    a.r64 = b->r64;
+    a.tot_v = b->off_v[b->P];
+    return a;
+}
+
+// Candidate LDS budgets of the autotuner for a group at `threads`: the
+// fused kernel's largest step and two shorter ones (more workgroups per CU).
+std::vector<int> lds_candidates(const ssp_batch *b, int nx, int threads) {
+    std::vector<int> out;
+    const int need = ssp::pcg2_lds(nx, b->fp32, threads);
+    if (need == 0) return out;
+    const int cmax = ssp::pcg2_steps_for(nx, b->fp32, threads, need);
+    const int eb = b->fp32 ? 4 : 8, V = 16 / eb;
+    const int bs = ssp::block_stride(nx, eb), nxp = (nx + V - 1) / V * V;
+    const int per = (3 * bs + 4 * nxp) * eb;
+    const int lo = ssp::bt_sweep_min_lds(nx, true, 8);
+    for (int c : {cmax, cmax - 1, (cmax + 1) / 2}) {
+        if (c < 1) continue;
+        const int l = std::max((c + 2) * per + nxp * eb + 16, lo);
+        if (l <= ssp::kFusedLdsCap && ssp::pcg2_steps_for(nx, b->fp32, threads, l) >= 1 &&
+            std::find(out.begin(), out.end(), l) == out.end())
+            out.push_back(l);
+    }
+    return out;
+}
+
+// Fused solve of every group (which < 0) or of group `which` alone, each
+// group on its own stream, forked from and joined back into s.
+ssp_status launch_groups(ssp_batch *b, ssp::SolveArgs a, int which, hipStream_t s) {
+    const int ng = (int)b->groups.size();
+    const bool fork = which < 0 && ng > 1;
+    if (fork) {
+        SSP_HIP(hipEventRecord(b->gevents[ng], s));
+        for (int i = 0; i < ng; ++i) SSP_HIP(hipStreamWaitEvent(b->gstreams[i], b->gevents[ng], 0));
+    }
+    for (int i = 0; i < ng; ++i) {
+        if (which >= 0 && i != which) continue;
+        const auto &g = b->groups[i];
+        int t, l;
+        group_mapping(b, g, &t, &l);
+        ssp::SolveArgs ga = a;
+        ga.order = b->dgorder + g.offset;
+        ga.lds_bytes = l;
+        SSP_HIP(ssp::launch_pcg2(ga, g.count, b->fp32, t, fork ? b->gstreams[i] : s));
+    }
+    if (fork) {
+        for (int i = 0; i < ng; ++i) {
+            SSP_HIP(hipEventRecord(b->gevents[i], b->gstreams[i]));
+            SSP_HIP(hipStreamWaitEvent(s, b->gevents[i], 0));
+        }
+    }
     return SSP_OK;
 }
 
@@ -187,6 +280,28 @@ ssp_status ssp_batch_create(int32_t nprob, const int32_t *N, const int32_t *nx, 
     std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t c) {
         return (int64_t)N[a] * nx[a] * nx[a] > (int64_t)N[c] * nx[c] * nx[c];
     });
+    // fused solve groups by state size, largest total work first
+    {
+        std::vector<int> sizes(b->nx.begin(), b->nx.end());
+        std::sort(sizes.begin(), sizes.end());
+        sizes.erase(std::unique(sizes.begin(), sizes.end()), sizes.end());
+        for (int x : sizes) {
+            ssp_batch::Group g;
+            g.nx = x;
+            for (int p = 0; p < nprob; ++p)
+                if (nx[p] == x) g.work += (double)N[p] * x * x;
+            b->groups.push_back(g);
+        }
+        std::stable_sort(b->groups.begin(), b->groups.end(),
+                         [](const ssp_batch::Group &u, const ssp_batch::Group &v) { return u.work > v.work; });
+    }
+    std::vector<int32_t> gorder;
+    for (auto &g : b->groups) {
+        g.offset = (int)gorder.size();
+        for (int32_t p : order)
+            if (nx[p] == g.nx) gorder.push_back(p);
+        g.count = (int)gorder.size() - g.offset;
+    }
     std::vector<int32_t> knot_prob((size_t)b->knots);
     for (int p = 0; p < nprob; ++p)
         std::fill(knot_prob.begin() + b->koff[p], knot_prob.begin() + b->koff[p + 1], p);
@@ -227,6 +342,26 @@ ssp_status ssp_batch_create(int32_t nprob, const int32_t *N, const int32_t *nx, 
     up(&b->dnx, b->nx.data(), nprob);
     up(&b->dnu, b->nu.data(), nprob);
     up(&b->dorder, order.data(), nprob);
+    up(&b->dgorder, gorder.data(), gorder.size());
+    if (rc == SSP_OK && b->groups.size() > 1) {
+        for (size_t i = 0; i < b->groups.size(); ++i) {
+            hipStream_t st;
+            if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+                rc = SSP_ERR_HIP;
+                break;
+            }
+            b->gstreams.push_back(st);
+        }
+        for (size_t i = 0; rc == SSP_OK && i <= b->groups.size(); ++i) {
+            hipEvent_t ev;
+            if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+                rc = SSP_ERR_HIP;
+                break;
+            }
+            b->gevents.push_back(ev);
+        }
+        if (rc != SSP_OK) g_last_error = "stream/event creation failed";
+    }
     up(&b->dknot, knot_prob.data(), knot_prob.size());
     up(&b->ditems, items.data(), items.size());
     up(&b->dgeneric, generic.data(), generic.size());
@@ -260,6 +395,9 @@ ssp_status ssp_batch_destroy(ssp_batch *b) {
         free_storage(b);
         for (auto &kl : b->nx_knots)
             if (kl.second.first) (void)hipFree(kl.second.first);
+        for (hipStream_t st : b->gstreams) (void)hipStreamDestroy(st);
+        for (hipEvent_t ev : b->gevents) (void)hipEventDestroy(ev);
+        if (b->dgorder) (void)hipFree(b->dgorder);
         for (void *p : {(void *)b->dN, (void *)b->dnx, (void *)b->dnu, (void *)b->dorder, (void *)b->dknot,
                         (void *)b->ditems, (void *)b->dgeneric, (void *)b->doff_nn, (void *)b->doff_nu, (void *)b->doff_uu, (void *)b->doff_v,
                         (void *)b->dkoff, (void *)b->doff_blk32, (void *)b->doff_blk64, (void *)b->Qinv, (void *)b->Rinv,
@@ -289,6 +427,7 @@ ssp_status ssp_set_mapping(ssp_batch *b, int32_t threads, int32_t lds_bytes, int
     b->threads = threads;
     b->lds_bytes = lds_bytes;
     b->kernel = kernel;
+    for (auto &g : b->groups) g.threads = g.lds = 0;
     return SSP_OK;
 }
 
@@ -329,36 +468,9 @@ ssp_status ssp_solve(ssp_batch *b, double rel_tol, int32_t max_iter, const doubl
     if (!b->built) return SSP_ERR_STATE;
     DevGuard g(b->device);
     hipStream_t s = (hipStream_t)stream;
-    ssp::SolveArgs a{};
-    a.order = b->dorder;
-    a.N = b->dN;
-    a.nx = b->dnx;
-    a.off_blk = b->fp32 ? b->doff_blk32 : b->doff_blk64;
-    a.off_v = b->doff_v;
-    a.status = prob_status;
-    a.B3 = b->B3;
-    a.SDlo = b->fp32 ? b->SDlo : nullptr;
-    a.SLlo = b->fp32 ? b->SLlo : nullptr;
-    a.pc = (int)b->pc;
-    a.gamma = gamma;
-    a.lambda = lambda;
-    a.use_lambda0 = use_lambda0;
-    a.tol = rel_tol;
-    a.max_iter = max_iter;
-    a.refine = b->prec == SSP_FP32_REFINE64 ? 1 : 0;
-    a.max_outer = a.refine ? 5 : 1;
-    a.theta = 0.5;
-    a.tau_min = 1e-6;
-    a.iters = iters;
-    a.outer = b->douter;
-    a.relres = relres;
-    a.work = b->work;
-    a.r64 = b->r64;
-    a.tot_v = b->off_v[b->P];
-    const int lds2 = b->kernel == 0 ? fused_lds(b) : 0;
-    if (lds2 > 0) {
-        a.lds_bytes = lds2;
-        SSP_HIP(ssp::launch_pcg2(a, b->P, b->fp32, b->threads, s));
+    ssp::SolveArgs a = solve_args(b, rel_tol, max_iter, gamma, lambda, use_lambda0, iters, relres, prob_status);
+    if (b->kernel == 0 && fused_ok(b)) {
+        return launch_groups(b, a, -1, s);
     } else {
         // explicit stored stair blocks (also the fallback when a knot does not
         // fit the fused kernel's registers or LDS)
@@ -397,6 +509,88 @@ ssp_status ssp_export(ssp_batch *b, int which, double *diag, double *off, void *
         const bool lo = which == 0 && b->fp32;
         SSP_HIP(ssp::launch_export(a, b->B3, 3, 0, lo ? b->SDlo : nullptr, b->fp32, diag, b->knots, s));
         SSP_HIP(ssp::launch_export(a, b->B3, 3, 1, lo ? b->SLlo : nullptr, b->fp32, off, b->knots, s));
+    }
+    return SSP_OK;
+}
+
+ssp_status ssp_autotune(ssp_batch *b, double rel_tol, const double *gamma, double *lambda, int32_t *iters,
+                        double *relres, int32_t *prob_status, void *stream) {
+    if (!b || !gamma || !lambda || !iters || !relres || !prob_status || !(rel_tol >= 0.0)) return SSP_ERR_ARG;
+    if (!b->built) return SSP_ERR_STATE;
+    if (b->kernel != 0 || !fused_ok(b)) return SSP_OK;  // only the fused kernel has a mapping to tune
+    DevGuard dg(b->device);
+    hipStream_t s = (hipStream_t)stream;
+    int32_t *st0 = nullptr;
+    if (dalloc(&st0, (size_t)b->P) != hipSuccess) {
+        g_last_error = "hipMalloc of status copy failed";
+        return SSP_ERR_ALLOC;
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ssp_status rc = SSP_OK;
+    auto fail = [&](hipError_t e, const char *what) {
+        if (rc == SSP_OK) rc = hip_fail(e, what);
+    };
+    hipError_t e = hipMemcpyAsync(st0, prob_status, sizeof(int32_t) * b->P, hipMemcpyDeviceToDevice, s);
+    if (e) fail(e, "status copy");
+    if (rc == SSP_OK && ((e = hipEventCreate(&e0)) || (e = hipEventCreate(&e1)))) fail(e, "hipEventCreate");
+    const ssp::SolveArgs a = solve_args(b, rel_tol, 0, gamma, lambda, 0, iters, relres, prob_status);
+    for (size_t gi = 0; rc == SSP_OK && gi < b->groups.size(); ++gi) {
+        auto &g = b->groups[gi];
+        int best_t = 0, best_l = 0;
+        float best = 0.0f;
+        for (int t : {128, 256}) {
+            for (int l : lds_candidates(b, g.nx, t)) {
+                g.threads = t;
+                g.lds = l;
+                float ms = 0.0f;
+                for (int rep = 0; rep < 2 && rc == SSP_OK; ++rep) {  // warm-up, then timed
+                    if ((e = hipMemcpyAsync(prob_status, st0, sizeof(int32_t) * b->P, hipMemcpyDeviceToDevice, s))) {
+                        fail(e, "status restore");
+                        break;
+                    }
+                    if ((e = hipEventRecord(e0, s))) fail(e, "hipEventRecord");
+                    if (rc == SSP_OK && (rc = launch_groups(b, a, (int)gi, s)) != SSP_OK) break;
+                    if ((e = hipEventRecord(e1, s)) || (e = hipEventSynchronize(e1)) ||
+                        (e = hipEventElapsedTime(&ms, e0, e1)))
+                        fail(e, "autotune timing");
+                }
+                if (rc != SSP_OK) break;
+                if (best_t == 0 || ms < best) {
+                    best = ms;
+                    best_t = t;
+                    best_l = l;
+                }
+            }
+            if (rc != SSP_OK) break;
+        }
+        g.threads = best_t;
+        g.lds = best_l;
+        g.tuned_ms = best;
+    }
+    // leave valid results of the chosen mapping in the outputs
+    if (rc == SSP_OK &&
+        (e = hipMemcpyAsync(prob_status, st0, sizeof(int32_t) * b->P, hipMemcpyDeviceToDevice, s)))
+        fail(e, "status restore");
+    if (rc == SSP_OK) rc = launch_groups(b, a, -1, s);
+    if (rc == SSP_OK && (e = hipStreamSynchronize(s))) fail(e, "hipStreamSynchronize");
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(st0);
+    return rc;
+}
+
+ssp_status ssp_get_mapping(const ssp_batch *b, int32_t max_groups, int32_t *nx, int32_t *threads,
+                           int32_t *lds_bytes, float *tuned_ms, int32_t *ngroups) {
+    if (!b || !ngroups || max_groups < 0) return SSP_ERR_ARG;
+    const int ng = (int)b->groups.size();
+    *ngroups = ng;
+    for (int i = 0; i < ng && i < max_groups; ++i) {
+        int t, l;
+        group_mapping(b, b->groups[i], &t, &l);
+        if (nx) nx[i] = b->groups[i].nx;
+        if (threads) threads[i] = t;
+        if (lds_bytes) lds_bytes[i] = l;
+        if (tuned_ms) tuned_ms[i] = b->groups[i].tuned_ms;
     }
     return SSP_OK;
 }

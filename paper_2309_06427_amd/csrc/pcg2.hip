@@ -796,10 +796,10 @@ int pcg2_lds(int nx_max, bool fp32, int threads) {
     int bytes = (C + 2) * per + nxp * eb + 16;
     const int res = bt_sweep_min_lds(nx_max, true, 8);
     if (bytes < res) bytes = res;
-    if (bytes > 160 * 1024) {
+    if (bytes > kFusedLdsCap) {
         // shrink the step to the LDS limit
-        C = (160 * 1024 - nxp * eb - 16) / per - 2;
-        if (C < 1 || res > 160 * 1024) return 0;
+        C = (kFusedLdsCap - nxp * eb - 16) / per - 2;
+        if (C < 1 || res > kFusedLdsCap) return 0;
         bytes = (C + 2) * per + nxp * eb + 16;
         if (bytes < res) bytes = res;
     }
@@ -808,9 +808,19 @@ int pcg2_lds(int nx_max, bool fp32, int threads) {
 
 template <typename TI, int BLOCK>
 static hipError_t launch2_t(const SolveArgs &a, int nprob, hipStream_t s) {
-    hipError_t e = hipFuncSetAttribute((const void *)k_pcg2<TI, BLOCK>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       a.lds_bytes);
-    if (e != hipSuccess) return e;
+    // all the LDS a workgroup may have is allowed once; each launch asks for
+    // its own size (launches of other sizes may be in flight on other streams)
+    static int allowed = 0;
+    if (allowed == 0) {
+        hipFuncAttributes fa;
+        hipError_t e = hipFuncGetAttributes(&fa, (const void *)k_pcg2<TI, BLOCK>);
+        if (e != hipSuccess) return e;
+        const int cap = 160 * 1024 - (int)fa.sharedSizeBytes;
+        e = hipFuncSetAttribute((const void *)k_pcg2<TI, BLOCK>, hipFuncAttributeMaxDynamicSharedMemorySize, cap);
+        if (e != hipSuccess) return e;
+        allowed = cap;
+    }
+    if (a.lds_bytes > allowed) return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_pcg2<TI, BLOCK>), dim3(nprob), dim3(BLOCK), a.lds_bytes, s, a);
     return hipGetLastError();
 }

@@ -86,4 +86,17 @@ struct ssp_batch {
     int threads = 128;
     int lds_bytes = 0;  // 0: default
     int kernel = 0;     // 0 fused single-sweep, 1 explicit two-sweep
+    // Fused solve groups: the problems of one state size, largest first,
+    // launched on their own stream with their own workgroup size and LDS
+    // budget (0: derived from threads / lds_bytes above).
+    struct Group {
+        int nx = 0, count = 0, offset = 0;  // problems dgorder[offset .. offset + count)
+        double work = 0;                    // sum of N nx^2 (launch order: largest first)
+        int threads = 0, lds = 0;
+        float tuned_ms = 0.0f;  // best solve time the autotuner measured (0: not tuned)
+    };
+    std::vector<Group> groups;
+    int32_t *dgorder = nullptr;
+    std::vector<hipStream_t> gstreams;
+    std::vector<hipEvent_t> gevents;  // one per group, plus the fork event at the end
 };

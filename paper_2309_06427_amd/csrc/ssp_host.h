@@ -72,6 +72,10 @@ hipError_t launch_pcg(const SolveArgs &a, int nprob, bool fp32, int threads, hip
 int pcg_min_lds(int nx_max, bool has_sub);
 int pcg_default_lds(int nx_max, bool fp32, int threads);
 
+// Dynamic LDS the fused kernel may ask for (a CU's 160 KB less room for
+// the kernel's own static arrays).
+constexpr int kFusedLdsCap = 160 * 1024 - 256;
+
 // Fused single-sweep PCG with the preconditioner applied from D^-1 and S.
 hipError_t launch_pcg2(const SolveArgs &a, int nprob, bool fp32, int threads, hipStream_t s);
 int pcg2_lds(int nx_max, bool fp32, int threads);  // 0 if the mapping cannot hold one knot

@@ -66,6 +66,23 @@ class BatchSolver:
                                     int(use_lambda0), _ptr(iters), _ptr(relres), _ptr(status),
                                     _stream(stream)), "ssp_solve")
 
+    def autotune(self, tol: float, gamma, lam, iters, relres, status, stream=None):
+        check(_lib.load().ssp_autotune(self._h, float(tol), _ptr(gamma), _ptr(lam), _ptr(iters), _ptr(relres),
+                                       _ptr(status), _stream(stream)), "ssp_autotune")
+
+    def mapping(self) -> list:
+        """[(nx, threads, lds_bytes, tuned_ms)] per solve group."""
+        L = _lib.load()
+        n = C.c_int32()
+        check(L.ssp_get_mapping(self._h, 0, None, None, None, None, C.byref(n)), "ssp_get_mapping")
+        k = n.value
+        nx, th, lds = (np.zeros(max(k, 1), dtype=np.int32) for _ in range(3))
+        ms = np.zeros(max(k, 1), dtype=np.float32)
+        p32 = lambda a: a.ctypes.data_as(C.POINTER(C.c_int32))
+        check(L.ssp_get_mapping(self._h, k, p32(nx), p32(th), p32(lds), ms.ctypes.data_as(C.POINTER(C.c_float)),
+                                C.byref(n)), "ssp_get_mapping")
+        return [(int(nx[i]), int(th[i]), int(lds[i]), float(ms[i])) for i in range(k)]
+
     def solve_outer(self, outer, stream=None):
         check(_lib.load().ssp_solve_outer(self._h, _ptr(outer), _stream(stream)), "ssp_solve_outer")
 
@@ -111,6 +128,12 @@ class DeviceBatch:
         self.solver.solve(tol, max_iter, self.gamma, self.lam, use, self.iters, self.relres,
                           self.status, stream)
         self.solver.solve_outer(self.outer, stream)
+
+    def autotune(self, tol: float = 1e-6, stream=None) -> list:
+        """Pick the fused kernel's mapping per state size on this batch (after a build)."""
+        self.solver.autotune(tol, self.gamma, self.lam, self.iters, self.relres, self.status, stream)
+        self.solver.solve_outer(self.outer, stream)
+        return self.solver.mapping()
 
     def results(self) -> dict:
         import torch

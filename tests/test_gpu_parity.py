@@ -191,3 +191,26 @@ def test_warm_start_with_solution_takes_no_iterations():
     ref = oracle.solve_batch(b, "sym", "fp64", tol=1e-12)
     out = solve_gpu(b, "sym", "fp64", 1e-8, lam0=ref["lam"])
     assert (out["iters"] == 0).all() and (out["status"] == 0).all()
+
+
+def test_autotune_keeps_results_valid_and_reports_a_mapping():
+    from paper_2309_06427_amd import solver
+    b = inputs.batch(30, 41, N_range=(8, 80), nx_choices=(6, 14, 26, 5))
+    db = solver.DeviceBatch(b)
+    db.build("sym", "fp32_refine64")
+    mapping = db.autotune(1e-6)
+    assert sorted(m[0] for m in mapping) == sorted(set(int(x) for x in b.nx))
+    for nx, threads, lds, ms in mapping:
+        assert threads in (128, 256) and 0 < lds <= 160 * 1024 and ms > 0
+    out = db.results()
+    assert (out["status"] == 0).all() and out["relres"].max() <= 1e-6
+    # a plain solve with the tuned mapping agrees with the oracle's direct solution
+    db.solve(1e-6)
+    out = db.results()
+    assert (out["status"] == 0).all() and out["relres"].max() <= 1e-6
+    for p in range(b.P):
+        pr = b.problem(p)
+        st, D, L, Di, M = oracle.build(pr["A"], pr["B"], pr["Q"], pr["R"], "sym")
+        st, lam = oracle.direct(D, L, pr["gamma"])
+        err = np.linalg.norm(seg(b, out["lam"], p) - lam) / np.linalg.norm(lam)
+        assert err < 1e-3, (p, err)
