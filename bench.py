@@ -29,9 +29,9 @@ HBM_PEAK_GBS = 8000.0
 # a hash of the kernel's sources: a changed kernel reports null.
 SOLVE_SOURCES = ("pcg2.hip", "ssp_device.h", "ssp_sweep.h", "ssp_host.h")
 MEASURED_TRAFFIC = {
-    # (workload, pc, precision, threads, kernel): (sources sha256[:16], bytes)
-    ("batch4096_ragged", "sym", "fp32_refine64", 128, 0):
-        ("9899cbe1fde8cf9a", (30930481.1 * 2.0 + 5600953.2 * 1.0) * 1024),
+    # (workload, pc, precision, kernel): (sources sha256[:16], bytes of one solve, all its dispatches)
+    ("batch4096_ragged", "sym", "fp32_refine64", 0):
+        ("438a306aa20265eb", ((22907169.625 + 7193071.0625) * 2.0 + (4052229.21875 + 1735518.28125) * 1.0) * 1024),
 }
 
 
@@ -116,6 +116,8 @@ def main() -> int:
     ap.add_argument("--warm", default="auto", choices=["auto", "zero", "learned"],
                     help="learned: also run the step with the trained warm-start networks "
                          "(auto: when their weights are present)")
+    ap.add_argument("--mapping", default="",
+                    help="fixed per-state-size mapping nx:threads:lds,... instead of autotuning")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="keep the default mapping instead of timing candidates per state size first")
     ap.add_argument("--no-graph", dest="graph", action="store_false",
@@ -169,7 +171,14 @@ def main() -> int:
         db.solver.set_mapping(args.threads or 128, args.lds, args.kernel)
     stream = torch.cuda.current_stream()
     mapping = None
-    if args.autotune and not (args.threads or args.lds or args.kernel):
+    if args.mapping:
+        # a fixed per-state-size mapping, "nx:threads:lds,..." (e.g. from an earlier autotune)
+        db.build(args.pc, precision)
+        for item in args.mapping.split(","):
+            nx_, t_, l_ = (int(v) for v in item.split(":"))
+            db.solver.set_group_mapping(nx_, t_, l_)
+        mapping = db.solver.mapping()
+    elif args.autotune and not (args.threads or args.lds or args.kernel):
         db.build(args.pc, precision)
         mapping = db.autotune(tol)
         print(f"[bench] autotuned mapping (nx, threads, lds, ms): {mapping}", file=sys.stderr, flush=True)
@@ -248,12 +257,12 @@ def main() -> int:
     head_mode = min(runs, key=lambda m: step_wall(runs[m]))
     head = runs[head_mode]
     head_wall = step_wall(head)
-    ok = bool(all(((r["res"]["status"] & ~8) == 0).all() and r["res"]["relres"].max() <= tol
+    ok = bool(all(((r["res"]["status"] & ~24) == 0).all() and r["res"]["relres"].max() <= tol
                   for r in runs.values()))
     if args.graph:
         ok = ok and all(r["graph_matches_eager"] for r in runs.values())
     bytes_solve = float(algorithmic_bytes(b, res["iters"], res["outer"], args.pc, precision, args.kernel).sum())
-    rec = MEASURED_TRAFFIC.get((args.workload, args.pc, precision, args.threads or 128, args.kernel))
+    rec = MEASURED_TRAFFIC.get((args.workload, args.pc, precision, args.kernel))
     traffic = rec[1] if rec and rec[0] == solve_sources_hash() else None
     solve_avg_s = float(plain["solve_ms"].mean()) / 1e3
     achieved = bytes_solve / solve_avg_s / 1e9

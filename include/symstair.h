@@ -56,8 +56,12 @@ enum {
     SSP_P_MAXITER = 2,   /* max_iter inner iterations or max refinement steps reached */
     SSP_P_NONFINITE = 3, /* NaN/Inf in gamma, lambda0 or a recurrence scalar */
     SSP_P_BREAKDOWN = 4, /* p^T S p <= 0 or r^T z <= 0 inside PCG */
-    SSP_P_WARM_FALLBACK = 8 /* bit OR-ed onto the status: the warm start did not
-                               reduce the residual and the solve started from 0 */
+    SSP_P_WARM_FALLBACK = 8, /* bit OR-ed onto the status: the warm start did not
+                                reduce the residual and the solve started from 0 */
+    SSP_P_PC_FALLBACK = 16   /* bit OR-ed onto the status (FP32 with refinement):
+                                a float breakdown under a stair preconditioner
+                                did not reduce the FP64 residual, so the
+                                refinement went on with block-Jacobi */
 };
 
 typedef enum {
@@ -117,7 +121,11 @@ ssp_status ssp_build(ssp_batch *b, ssp_precon pc, ssp_precision prec, const doub
  *             failed to build are skipped), out = solve status.
  *   max_iter: cap on the inner iterations per problem (<= 0: 10 * N * nx).
  * FP32_REFINE64 runs at most 5 refinement steps; the inner relative
- * tolerance of step j is clamp(0.5 * rel_tol * ||gamma|| / ||r_j||, 1e-6, 1). */
+ * tolerance of step j is clamp(0.5 * rel_tol * ||gamma|| / ||r_j||, 1e-6, 1).
+ * There a float breakdown only ends the inner solve; if the next FP64
+ * residual is not smaller, a stair preconditioner is replaced by
+ * block-Jacobi for the rest of the solve (SSP_P_PC_FALLBACK, with 5 more
+ * refinement steps), and under block-Jacobi SSP_P_BREAKDOWN is reported. */
 ssp_status ssp_solve(ssp_batch *b, double rel_tol, int32_t max_iter, const double *gamma,
                      double *lambda, int use_lambda0, int32_t *iters, double *relres,
                      int32_t *prob_status, void *stream);
@@ -213,6 +221,13 @@ ssp_status ssp_gemm_f32(int32_t M, int32_t N, int32_t K, const float *A, int32_t
  * kernel. */
 ssp_status ssp_autotune(ssp_batch *b, double rel_tol, const double *gamma, double *lambda, int32_t *iters,
                         double *relres, int32_t *prob_status, void *stream);
+/* Set the fused kernel's mapping of the solve group with state size nx
+ * (e.g. a mapping the autotuner found earlier): threads 128 or 256 and an
+ * LDS budget that holds at least one pipeline step; 0, 0 restores the
+ * default.  The storage precision of the next ssp_build must be the one the
+ * budget was checked for (checked against the current storage).
+ * SSP_ERR_ARG for an unknown nx or an unusable mapping. */
+ssp_status ssp_set_group_mapping(ssp_batch *b, int32_t nx, int32_t threads, int32_t lds_bytes);
 /* The mapping in use per solve group (largest total work first): up to
  * max_groups entries of state size, threads, LDS bytes and the autotuner's
  * best time in ms (0 if not tuned), host arrays (any may be NULL); the group

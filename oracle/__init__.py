@@ -20,6 +20,7 @@ _LIB = os.path.join(_HERE, "libssp_oracle.so")
 
 OK, NOT_SPD, MAXITER, NONFINITE, BREAKDOWN = 0, 1, 2, 3, 4
 WARM_FALLBACK = 8  # OR-ed onto a status: the warm start was replaced by zero
+PC_FALLBACK = 16   # OR-ed: the refinement went on with block-Jacobi after a float breakdown
 PC = {"bj": 0, "add": 1, "sym": 2}
 PREC = {"fp64": 0, "fp32": 1, "fp32_refine64": 2}
 # refinement constants: inner tolerance tau_j = clamp(THETA*tol*|g|/|r_j|, TAU_MIN, 1)

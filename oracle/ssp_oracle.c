@@ -43,6 +43,7 @@
 #define OR_NONFINITE 3
 #define OR_BREAKDOWN 4
 #define OR_WARM_FALLBACK 8 /* OR-ed: the warm start was replaced by zero */
+#define OR_PC_FALLBACK 16  /* OR-ed: the solve went on with block-Jacobi after a float breakdown */
 
 #define OR_PC_BJ 0
 #define OR_PC_ADD 1
@@ -327,8 +328,12 @@ static int pcg_f32(int N, int nx, const float *D, const float *L, const float *D
  * refine = 0 runs one inner solve only (plain FP32 mode).
  * Under refinement an inner breakdown (p^T S p <= 0 or r^T z <= 0 in float,
  * a loss of float accuracy for an SPD S) ends that inner solve; the step
- * still updates lam and the loop goes on, and BREAKDOWN is reported only if
- * the next FP64 residual is not smaller than the one before that step.
+ * still updates lam and the loop goes on.  If the next FP64 residual is not
+ * smaller than the one before that step, a stair preconditioner (M != 0) is
+ * replaced by block-Jacobi (M = 0), whose float operator stays positive
+ * definite far longer, and the refinement restarts its step budget; the
+ * status then carries OR_PC_FALLBACK.  BREAKDOWN is reported when this
+ * happens under block-Jacobi.
  * *iters is the total number of inner S-products, *outer the refinement
  * steps taken. */
 int ssp_oracle_pcg_mixed(int N, int nx, const double *D, const double *L, const double *Dinv,
@@ -339,10 +344,11 @@ int ssp_oracle_pcg_mixed(int N, int nx, const double *D, const double *L, const 
     float *Df = malloc(sizeof(float) * nb), *Lf = malloc(sizeof(float) * nb);
     float *DIf = malloc(sizeof(float) * nb), *Mf = malloc(sizeof(float) * nb);
     double *r = malloc(sizeof(double) * n), *d = malloc(sizeof(double) * n);
-    int st = OR_OK, total = 0, steps = 0, broke = 0;
+    int st = OR_OK, total = 0, steps = 0, broke = 0, base = 0, fell = 0, stair = 0;
     double prev = INFINITY;
     for (size_t e = 0; e < nb; ++e) {
         Df[e] = (float)D[e]; Lf[e] = (float)L[e]; DIf[e] = (float)Dinv[e]; Mf[e] = (float)M[e];
+        if (M[e] != 0.0) stair = 1;
     }
     *iters = 0;
     *outer = 0;
@@ -356,8 +362,14 @@ int ssp_oracle_pcg_mixed(int N, int nx, const double *D, const double *L, const 
         if (!isfinite(rnorm)) { st = OR_NONFINITE; break; }
         if (rnorm <= tol * gnorm) break;
         if (steps > 0 && !refine) break;
-        if (broke && !(rnorm < prev)) { st = OR_BREAKDOWN; break; }
-        if (steps >= max_outer) { st = OR_MAXITER; break; }
+        if (broke && !(rnorm < prev)) {
+            if (!stair || fell) { st = OR_BREAKDOWN; break; }
+            memset(Mf, 0, sizeof(float) * nb);  /* go on with block-Jacobi */
+            fell = OR_PC_FALLBACK;
+            broke = 0;
+            base = steps;
+        }
+        if (steps - base >= max_outer) { st = OR_MAXITER; break; }
         prev = rnorm;
         double tau = refine ? theta * tol * gnorm / rnorm : tol * gnorm / rnorm;
         if (refine && tau < tau_min) tau = tau_min;
@@ -375,7 +387,7 @@ done:
     *iters = total;
     *outer = steps;
     free(Df); free(Lf); free(DIf); free(Mf); free(r); free(d);
-    return st;
+    return st | fell;
 }
 
 /* ||gamma - S lam||_2 / ||gamma||_2 in FP64 (0 when gamma = 0). */

@@ -13,6 +13,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsymstair
 SSP_OK, SSP_ERR_ARG, SSP_ERR_ALLOC, SSP_ERR_HIP, SSP_ERR_STATE = range(5)
 SSP_P_OK, SSP_P_NOT_SPD, SSP_P_MAXITER, SSP_P_NONFINITE, SSP_P_BREAKDOWN = range(5)
 SSP_P_WARM_FALLBACK = 8
+SSP_P_PC_FALLBACK = 16
 SSP_PC_BLOCK_JACOBI, SSP_PC_STAIR_ADD, SSP_PC_SYM_STAIR = range(3)
 SSP_FP64, SSP_FP32, SSP_FP32_REFINE64 = range(3)
 
@@ -44,6 +45,7 @@ SIGNATURES = {
     "ssp_mlp_adam": (C.c_int, [_vp, _f, _f, _f, _f, _vp]),
     "ssp_gemm_f32": (C.c_int, [_i32, _i32, _i32, _vp, _i32, _i32, _vp, _i32, _i32, _vp, _i32, _vp]),
     "ssp_autotune": (C.c_int, [_vp, _d, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "ssp_set_group_mapping": (C.c_int, [_vp, _i32, _i32, _i32]),
     "ssp_get_mapping": (C.c_int, [_vp, _i32, _pi32, _pi32, _pi32, C.POINTER(_f), _pi32]),
     "ssp_status_str": (C.c_char_p, [C.c_int]),
     "ssp_last_error": (C.c_char_p, []),

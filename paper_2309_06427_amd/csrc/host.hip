@@ -579,6 +579,25 @@ ssp_status ssp_autotune(ssp_batch *b, double rel_tol, const double *gamma, doubl
     return rc;
 }
 
+ssp_status ssp_set_group_mapping(ssp_batch *b, int32_t nx, int32_t threads, int32_t lds_bytes) {
+    if (!b) return SSP_ERR_ARG;
+    for (auto &g : b->groups) {
+        if (g.nx != nx) continue;
+        if (threads == 0 && lds_bytes == 0) {
+            g.threads = g.lds = 0;
+            return SSP_OK;
+        }
+        if (!ssp::pcg2_threads_ok(threads) || lds_bytes < ssp::bt_sweep_min_lds(nx, true, 8) ||
+            lds_bytes > ssp::kFusedLdsCap || ssp::pcg2_steps_for(nx, b->fp32, threads, lds_bytes) < 1)
+            return SSP_ERR_ARG;
+        g.threads = threads;
+        g.lds = lds_bytes;
+        g.tuned_ms = 0.0f;
+        return SSP_OK;
+    }
+    return SSP_ERR_ARG;
+}
+
 ssp_status ssp_get_mapping(const ssp_batch *b, int32_t max_groups, int32_t *nx, int32_t *threads,
                            int32_t *lds_bytes, float *tuned_ms, int32_t *ngroups) {
     if (!b || !ngroups || max_groups < 0) return SSP_ERR_ARG;

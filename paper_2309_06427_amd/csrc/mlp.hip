@@ -209,6 +209,96 @@ hipError_t gemm(int M, int N, int K, int splits, const AL &al, const BL &bl, con
     return hipGetLastError();
 }
 
+// First layer, z = standardised inputs x W1 + b1, h = gelu(z), for 64 knots
+// by up to 128 hidden units per workgroup (4 waves, each 16 knots x 128
+// units as 8 MFMA tiles).  A thread loads four consecutive inputs of one knot
+// with one vector load: the D and L blocks of a knot are adjacent in the
+// stored array (block stride nx^2 when nx^2 is a multiple of the vector
+// width, which the caller checks), and L_0 is stored as zeros.
+template <typename TM>
+__global__ __launch_bounds__(GT) void k_layer1(FeatSrc s, const float *__restrict__ W1, const float *__restrict__ b1,
+                                               const float *__restrict__ mu, const float *__restrict__ isd, int nin,
+                                               int H, float *__restrict__ Z, float *__restrict__ Hout) {
+    constexpr int L1N = 128;
+    __shared__ float As[BK][BM + PADL];
+    __shared__ float Bs[BK][L1N + PADL];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int m0 = blockIdx.x * BM, n0 = blockIdx.y * L1N;
+    const int nn = s.nx * s.nx, nd = 2 * nn;
+    // this thread's row of the A tile and its input quad
+    const int am = t >> 2, aq = (t & 3) * 4;
+    const bool arow = m0 + am < s.M;
+    KnotInfo q{};
+    if (arow) q = s.ki[m0 + am];
+    const TM *src = (const TM *)s.B3 + q.blk;
+    // B tile: row t / 16, eight columns from 8 (t % 16)
+    const int bk = t >> 4, bn = (t & 15) * 8;
+    f32x4 acc[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < nin; k0 += BK) {
+        __syncthreads();
+        {
+            const int f = k0 + aq;
+            float x[4] = {0.f, 0.f, 0.f, 0.f};
+            if (arow) {
+                if (f + 3 < nd) {
+                    if constexpr (sizeof(TM) == 4) {
+                        const f32x4 v = *(const f32x4 *)(src + f);
+                        x[0] = v.x;
+                        x[1] = v.y;
+                        x[2] = v.z;
+                        x[3] = v.w;
+                    } else {
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) x[j] = (float)src[f + j];
+                    }
+                } else {
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int fj = f + j;
+                        if (fj < nd) x[j] = (float)src[fj];
+                        else if (fj < nin) x[j] = (float)s.gamma[q.vec + (fj - nd)];
+                    }
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int fj = f + j;
+                As[aq + j][am] = (arow && fj < nin) ? (x[j] - mu[fj]) * isd[fj] : 0.f;
+            }
+        }
+        {
+            const int kr = k0 + bk;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int n = n0 + bn + j;
+                Bs[bk][bn + j] = (kr < nin && n < H) ? W1[(int64_t)kr * H + n] : 0.f;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int sub = 0; sub < BK / 4; ++sub) {
+            const int kr = 4 * sub + (lane >> 4), c = lane & 15;
+            const float a = As[kr][16 * w + c];
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, Bs[kr][16 * j + c], acc[j], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int m = m0 + 16 * w + 4 * (lane >> 4) + r, n = n0 + 16 * j + (lane & 15);
+            if (m < s.M && n < H) {
+                const float z = acc[j][r] + b1[n];
+                if (Z) Z[(int64_t)m * H + n] = z;
+                Hout[(int64_t)m * H + n] = gelu(z);
+            }
+        }
+}
+
 // number of K splits gemm() will use (the partial buffer holds that many)
 int split_count(int K, int splits) {
     if (splits < 1) splits = 1;
@@ -398,8 +488,15 @@ template <typename TM>
 hipError_t forward_t(const FeatSrc &f, const NetView &w, const float *mu, const float *isd, float ys, float *Z1,
                      float *H1, float *Z2, float *H2, float *O, double *lam, hipStream_t s) {
     hipError_t e;
-    FeatA<TM> fa{f, mu, isd, w.nin};
-    if ((e = gemm(f.M, w.H, w.nin, 1, fa, RowB{w.W1, w.H, w.nin, w.H}, EpBiasGelu{w.b1, Z1, H1, w.H}, s))) return e;
+    if (f.bs == f.nx * f.nx) {
+        hipLaunchKernelGGL(k_layer1<TM>, dim3((f.M + BM - 1) / BM, (w.H + 127) / 128), dim3(GT), 0, s, f, w.W1, w.b1,
+                           mu, isd, w.nin, w.H, Z1, H1);
+        if ((e = hipGetLastError())) return e;
+    } else {
+        FeatA<TM> fa{f, mu, isd, w.nin};
+        if ((e = gemm(f.M, w.H, w.nin, 1, fa, RowB{w.W1, w.H, w.nin, w.H}, EpBiasGelu{w.b1, Z1, H1, w.H}, s)))
+            return e;
+    }
     if ((e = gemm(f.M, w.H, w.H, 1, RowA{H1, w.H, f.M, w.H}, RowB{w.W2, w.H, w.H, w.H}, EpBiasGelu{w.b2, Z2, H2, w.H},
                   s)))
         return e;

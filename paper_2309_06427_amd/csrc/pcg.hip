@@ -54,7 +54,7 @@ __global__ __launch_bounds__(BLOCK) void k_pcg(SolveArgs a) {
         }
         return;
     }
-    const bool has_M = a.PM != nullptr;
+    bool has_M = a.PM != nullptr;
     const TM *SD = (const TM *)a.B3 + 3 * onn, *SL = SD + bs, *PD = SD + 2 * bs;  // knot stride 3 bs
     const int ks3 = 3 * bs;
     const float *SDlo = a.SDlo ? a.SDlo + onn : nullptr, *SLlo = a.SLlo ? a.SLlo + onn : nullptr;
@@ -78,7 +78,8 @@ __global__ __launch_bounds__(BLOCK) void k_pcg(SolveArgs a) {
     }
     block_sum2<BLOCK>(gg, bad, red64);
     int total = 0, steps = 0;
-    bool fallback = false;  // the warm start was dropped for lambda = 0
+    bool fallback = false;     // the warm start was dropped for lambda = 0
+    bool pc_fallback = false;  // block-Jacobi took over after a float breakdown
     double rnorm = 0.0;
     const double gnorm = sqrt(gg);
     if (!isfinite(gnorm) || bad != 0.0) {
@@ -90,7 +91,7 @@ __global__ __launch_bounds__(BLOCK) void k_pcg(SolveArgs a) {
         const Geo g64 = make_geo<double>(nx, bs, true, a.lds_bytes, BLOCK);
         const Geo gS = make_geo<TI>(nx, bs, true, a.lds_bytes, BLOCK);
         const Geo gP = make_geo<TI>(nx, bs, has_M, a.lds_bytes, BLOCK);
-        int pending = kOk;
+        int pending = kOk, base = 0;
         bool broke = false;  // last inner solve ended in a float breakdown (refinement only)
         double prev = INFINITY;
         for (;;) {
@@ -126,10 +127,17 @@ __global__ __launch_bounds__(BLOCK) void k_pcg(SolveArgs a) {
             if (rnorm <= a.tol * gnorm) break;
             if (steps > 0 && !a.refine) break;
             if (broke && !(rnorm < prev)) {
-                st = kBreakdown;
-                break;
+                // the float stair operator lost definiteness: go on with block-Jacobi
+                if (!has_M) {
+                    st = kBreakdown;
+                    break;
+                }
+                has_M = false;
+                pc_fallback = true;
+                broke = false;
+                base = steps;
             }
-            if (steps >= a.max_outer) {
+            if (steps - base >= a.max_outer) {
                 st = kMaxIter;
                 break;
             }
@@ -218,7 +226,7 @@ __global__ __launch_bounds__(BLOCK) void k_pcg(SolveArgs a) {
         a.iters[p] = total;
         a.outer[p] = steps;
         a.relres[p] = gg == 0.0 ? 0.0 : rnorm / gnorm;
-        a.status[p] = st | (fallback ? kWarmFallback : 0);
+        a.status[p] = st | (fallback ? kWarmFallback : 0) | (pc_fallback ? kPcFallback : 0);
     }
 }
 

@@ -562,7 +562,8 @@ struct Prob {
 // Outcome of one problem's solve.
 struct Outcome {
     int st = kOk, total = 0, steps = 0;
-    bool fallback = false;  // the warm start was dropped for lambda = 0
+    bool fallback = false;     // the warm start was dropped for lambda = 0
+    bool pc_fallback = false;  // block-Jacobi took over after a float breakdown
     double rnorm = 0.0;
 };
 
@@ -588,6 +589,8 @@ __device__ __forceinline__ Outcome solve_problem(const SolveArgs &a, const Prob<
     const Geo g64 = make_geo<double>(nx, q.bs, true, a.lds_bytes, BLOCK);
     const int Cres = NX > 0 ? residual_knots_per_step<TM>(nx, BLOCK, a.lds_bytes) : 0;
     int pending = kOk;
+    int pcur = a.pc;     // block-Jacobi after a stair breakdown (refinement only)
+    int base = 0;        // refinement steps before that switch
     bool broke = false;  // last inner solve ended in a float breakdown (refinement only)
     double prev = INFINITY;
     const double *rsrc = q.r64;  // where the next inner solve reads its right-hand side
@@ -638,10 +641,17 @@ __device__ __forceinline__ Outcome solve_problem(const SolveArgs &a, const Prob<
         if (o.rnorm <= a.tol * q.gnorm) break;
         if (o.steps > 0 && !a.refine) break;
         if (broke && !(o.rnorm < prev)) {
-            o.st = kBreakdown;
-            break;
+            // the float stair operator lost definiteness: go on with block-Jacobi
+            if (pcur == 0) {
+                o.st = kBreakdown;
+                break;
+            }
+            pcur = 0;
+            o.pc_fallback = true;
+            broke = false;
+            base = o.steps;
         }
-        if (o.steps >= a.max_outer) {
+        if (o.steps - base >= a.max_outer) {
             o.st = kMaxIter;
             break;
         }
@@ -653,7 +663,7 @@ __device__ __forceinline__ Outcome solve_problem(const SolveArgs &a, const Prob<
 
         // inner PCG on S d = r / ||r|| from d = 0
         int it = 0, ist = kOk;
-        Dots<TI> dt = fused_pass<TI, BLOCK, NX>(g, a.pc, true, false, TI(0), TI(0), inv_s, rsrc, q.B3, q.Rv, q.Uv,
+        Dots<TI> dt = fused_pass<TI, BLOCK, NX>(g, pcur, true, false, TI(0), TI(0), inv_s, rsrc, q.B3, q.Rv, q.Uv,
                                                 q.Wv, q.Pv, q.Sv, q.Xv, (TI *)smem_raw);
         block_sum2<BLOCK>(dt.gam, dt.del, redT);
         dt.rho = block_sum<BLOCK>(dt.rho, redT + 2 * (BLOCK / kWave));
@@ -686,7 +696,7 @@ __device__ __forceinline__ Outcome solve_problem(const SolveArgs &a, const Prob<
             }
             alpha = dt.gam / den;
             gam_prev = dt.gam;
-            dt = fused_pass<TI, BLOCK, NX>(g, a.pc, false, it == 0, alpha, beta, 0.0, q.r64, q.B3, q.Rv, q.Uv, q.Wv,
+            dt = fused_pass<TI, BLOCK, NX>(g, pcur, false, it == 0, alpha, beta, 0.0, q.r64, q.B3, q.Rv, q.Uv, q.Wv,
                                            q.Pv, q.Sv, q.Xv, (TI *)smem_raw);
             block_sum2<BLOCK>(dt.gam, dt.del, redT);
             dt.rho = block_sum<BLOCK>(dt.rho, redT + 2 * (BLOCK / kWave));
@@ -775,7 +785,7 @@ __global__ __launch_bounds__(BLOCK, 2) void k_pcg2(SolveArgs a) {
         a.iters[p] = o.total;
         a.outer[p] = o.steps;
         a.relres[p] = gg == 0.0 ? 0.0 : o.rnorm / q.gnorm;
-        a.status[p] = o.st | (o.fallback ? kWarmFallback : 0);
+        a.status[p] = o.st | (o.fallback ? kWarmFallback : 0) | (o.pc_fallback ? kPcFallback : 0);
     }
 }
 

@@ -13,6 +13,7 @@ constexpr int kWave = 64;
 // Per-problem status codes (numerically equal to the public SSP_P_* values).
 constexpr int kOk = 0, kNotSpd = 1, kMaxIter = 2, kNonFinite = 3, kBreakdown = 4;
 constexpr int kWarmFallback = 8;  // OR-ed flag: the warm start was replaced by zero
+constexpr int kPcFallback = 16;   // OR-ed flag: block-Jacobi took over after a float breakdown
 
 // Butterfly sum over the 64 lanes of a wavefront.  Every lane ends with the
 // same bits: each stage adds the same two operands on both partner lanes.

@@ -70,6 +70,10 @@ class BatchSolver:
         check(_lib.load().ssp_autotune(self._h, float(tol), _ptr(gamma), _ptr(lam), _ptr(iters), _ptr(relres),
                                        _ptr(status), _stream(stream)), "ssp_autotune")
 
+    def set_group_mapping(self, nx: int, threads: int, lds_bytes: int):
+        check(_lib.load().ssp_set_group_mapping(self._h, int(nx), int(threads), int(lds_bytes)),
+              "ssp_set_group_mapping")
+
     def mapping(self) -> list:
         """[(nx, threads, lds_bytes, tuned_ms)] per solve group."""
         L = _lib.load()

@@ -136,14 +136,14 @@ def _dense(D, L):
     return T
 
 
-@pytest.mark.parametrize("kernel", [pytest.param(0, marks=pytest.mark.xfail(
-    reason="one of these problems (kappa(S) ~ 4e6) stalls the single-reduction float recurrence "
-           "of the fused kernel; a float-to-FP64 fallback is not built yet", strict=False)), 1])
+@pytest.mark.parametrize("kernel", [0, 1])
 def test_fp32_alone_stalls_refinement_recovers(kernel):
+    # problem 4 (kappa(S) ~ 4e6) loses the definiteness of the float stair
+    # operator in the fused kernel; refinement finishes it with block-Jacobi
     b = inputs.make("batch1024_n128_nx26_cond1e6", P=8)
     r32 = solve_gpu(b, "sym", "fp32", 1e-6, kernel=kernel)
     rr = solve_gpu(b, "sym", "fp32_refine64", 1e-6, kernel=kernel)
-    assert (rr["status"] == 0).all()
+    assert ((rr["status"] & ~16) == 0).all(), rr["status"]
     assert rr["relres"].max() <= 1e-6
     assert r32["relres"].max() > 1e-6
     assert (rr["outer"] >= 2).any()
