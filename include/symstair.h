@@ -59,8 +59,7 @@ enum {
     SSP_P_WARM_FALLBACK = 8, /* bit OR-ed onto the status: the warm start did not
                                 reduce the residual and the solve started from 0 */
     SSP_P_PC_FALLBACK = 16   /* bit OR-ed onto the status (FP32 with refinement):
-                                a float breakdown under a stair preconditioner
-                                did not reduce the FP64 residual, so the
+                                the float stair operator broke down, so the
                                 refinement went on with block-Jacobi */
 };
 
@@ -122,10 +121,11 @@ ssp_status ssp_build(ssp_batch *b, ssp_precon pc, ssp_precision prec, const doub
  *   max_iter: cap on the inner iterations per problem (<= 0: 10 * N * nx).
  * FP32_REFINE64 runs at most 5 refinement steps; the inner relative
  * tolerance of step j is clamp(0.5 * rel_tol * ||gamma|| / ||r_j||, 1e-6, 1).
- * There a float breakdown only ends the inner solve; if the next FP64
- * residual is not smaller, a stair preconditioner is replaced by
- * block-Jacobi for the rest of the solve (SSP_P_PC_FALLBACK, with 5 more
- * refinement steps), and under block-Jacobi SSP_P_BREAKDOWN is reported. */
+ * There a float breakdown only ends the inner solve; under a stair
+ * preconditioner it also replaces it by block-Jacobi for the rest of the
+ * solve (SSP_P_PC_FALLBACK, with a fresh budget of 5 refinement steps), and
+ * under block-Jacobi SSP_P_BREAKDOWN is reported if the next FP64 residual
+ * is not smaller. */
 ssp_status ssp_solve(ssp_batch *b, double rel_tol, int32_t max_iter, const double *gamma,
                      double *lambda, int use_lambda0, int32_t *iters, double *relres,
                      int32_t *prob_status, void *stream);

@@ -328,12 +328,12 @@ static int pcg_f32(int N, int nx, const float *D, const float *L, const float *D
  * refine = 0 runs one inner solve only (plain FP32 mode).
  * Under refinement an inner breakdown (p^T S p <= 0 or r^T z <= 0 in float,
  * a loss of float accuracy for an SPD S) ends that inner solve; the step
- * still updates lam and the loop goes on.  If the next FP64 residual is not
- * smaller than the one before that step, a stair preconditioner (M != 0) is
- * replaced by block-Jacobi (M = 0), whose float operator stays positive
- * definite far longer, and the refinement restarts its step budget; the
- * status then carries OR_PC_FALLBACK.  BREAKDOWN is reported when this
- * happens under block-Jacobi.
+ * still updates lam and the loop goes on.  Under a stair preconditioner
+ * (M != 0) the breakdown also replaces it by block-Jacobi (M = 0), whose
+ * float operator stays positive definite far longer, for the rest of the
+ * solve, with a fresh budget of refinement steps; the status then carries
+ * OR_PC_FALLBACK.  Under block-Jacobi, BREAKDOWN is reported if the next FP64
+ * residual is not smaller than the one before that step.
  * *iters is the total number of inner S-products, *outer the refinement
  * steps taken. */
 int ssp_oracle_pcg_mixed(int N, int nx, const double *D, const double *L, const double *Dinv,
@@ -362,13 +362,7 @@ int ssp_oracle_pcg_mixed(int N, int nx, const double *D, const double *L, const 
         if (!isfinite(rnorm)) { st = OR_NONFINITE; break; }
         if (rnorm <= tol * gnorm) break;
         if (steps > 0 && !refine) break;
-        if (broke && !(rnorm < prev)) {
-            if (!stair || fell) { st = OR_BREAKDOWN; break; }
-            memset(Mf, 0, sizeof(float) * nb);  /* go on with block-Jacobi */
-            fell = OR_PC_FALLBACK;
-            broke = 0;
-            base = steps;
-        }
+        if (broke && !(rnorm < prev)) { st = OR_BREAKDOWN; break; }
         if (steps - base >= max_outer) { st = OR_MAXITER; break; }
         prev = rnorm;
         double tau = refine ? theta * tol * gnorm / rnorm : tol * gnorm / rnorm;
@@ -380,6 +374,12 @@ int ssp_oracle_pcg_mixed(int N, int nx, const double *D, const double *L, const 
         ++steps;
         for (size_t i = 0; i < n; ++i) lam[i] += d[i];
         broke = refine && ist == OR_BREAKDOWN;
+        if (broke && stair && !fell) {
+            memset(Mf, 0, sizeof(float) * nb);  /* go on with block-Jacobi */
+            fell = OR_PC_FALLBACK;
+            broke = 0;
+            base = steps;
+        }
         if (ist == OR_NONFINITE || (ist == OR_BREAKDOWN && !refine)) { st = ist; break; }
         if (ist == OR_MAXITER) { st = OR_MAXITER; break; }
     }

@@ -127,15 +127,8 @@ __global__ __launch_bounds__(BLOCK) void k_pcg(SolveArgs a) {
             if (rnorm <= a.tol * gnorm) break;
             if (steps > 0 && !a.refine) break;
             if (broke && !(rnorm < prev)) {
-                // the float stair operator lost definiteness: go on with block-Jacobi
-                if (!has_M) {
-                    st = kBreakdown;
-                    break;
-                }
-                has_M = false;
-                pc_fallback = true;
-                broke = false;
-                base = steps;
+                st = kBreakdown;
+                break;
             }
             if (steps - base >= a.max_outer) {
                 st = kMaxIter;
@@ -217,9 +210,17 @@ __global__ __launch_bounds__(BLOCK) void k_pcg(SolveArgs a) {
             ++steps;
             __syncthreads();
             for (int row = tid; row < n; row += BLOCK) lam[row] += rnorm * (double)Dv[row];
-            // under refinement a float breakdown only ends the inner solve
+            // under refinement a float breakdown only ends the inner solve; under a
+            // stair preconditioner it also hands the rest of the solve to
+            // block-Jacobi (the float stair operator lost definiteness)
             broke = a.refine && ist == kBreakdown;
-            if (ist != kOk && !broke) pending = ist;
+            if (broke && has_M) {
+                has_M = false;
+                pc_fallback = true;
+                broke = false;
+                base = steps;
+            }
+            if (ist != kOk && !broke && !(a.refine && ist == kBreakdown)) pending = ist;
         }
     }
     if (tid == 0) {

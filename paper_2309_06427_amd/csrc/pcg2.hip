@@ -641,15 +641,8 @@ __device__ __forceinline__ Outcome solve_problem(const SolveArgs &a, const Prob<
         if (o.rnorm <= a.tol * q.gnorm) break;
         if (o.steps > 0 && !a.refine) break;
         if (broke && !(o.rnorm < prev)) {
-            // the float stair operator lost definiteness: go on with block-Jacobi
-            if (pcur == 0) {
-                o.st = kBreakdown;
-                break;
-            }
-            pcur = 0;
-            o.pc_fallback = true;
-            broke = false;
-            base = o.steps;
+            o.st = kBreakdown;
+            break;
         }
         if (o.steps - base >= a.max_outer) {
             o.st = kMaxIter;
@@ -706,9 +699,17 @@ __device__ __forceinline__ Outcome solve_problem(const SolveArgs &a, const Prob<
         ++o.steps;
         __syncthreads();
         for (int row = tid; row < n; row += BLOCK) q.lam[row] += o.rnorm * (double)q.Xv[row];
-        // under refinement a float breakdown only ends the inner solve
+        // under refinement a float breakdown only ends the inner solve; under a
+        // stair preconditioner it also hands the rest of the solve to
+        // block-Jacobi (the float stair operator lost definiteness)
         broke = a.refine && ist == kBreakdown;
-        if (ist != kOk && !broke) pending = ist;
+        if (broke && pcur != 0) {
+            pcur = 0;
+            o.pc_fallback = true;
+            broke = false;
+            base = o.steps;
+        }
+        if (ist != kOk && !broke && !(a.refine && ist == kBreakdown)) pending = ist;
     }
     return o;
 }
