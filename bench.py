@@ -45,27 +45,35 @@ def solve_sources_hash() -> str:
 
 
 def algorithmic_bytes(b, iters, outer, pc: str, precision: str, kernel: int = 0) -> np.ndarray:
-    """Bytes the solve kernel must stream per problem: every stored block it
-    reads in each pass (each element once per pass), plus gamma in and lambda
-    out once.  L_0 and Phi^-1[0][-1] do not exist and are not counted.
+    """Bytes the solve must stream per problem in the library's storage format:
+    every stored block element each pass reads, once per pass, plus gamma in
+    and lambda out once.  D_k and D_k^-1 are symmetric and stored packed
+    (nx(nx+1)/2 elements), L_k full (nx^2); L_0 and Phi^-1[0][-1] do not
+    exist and are not counted.
 
     fused kernel (0): each inner solve makes iters + 1 passes over D, L and
-    D^-1 ((3N - 1) nx^2 elements); explicit kernel (1): iters passes over S
-    and Phi^-1 plus one initial Phi^-1 pass.  Every refinement step and the
-    final check read S in FP64 (or FP32 hi + FP32 lo): 8 (2N - 1) nx^2 bytes.
+    D^-1; explicit kernel (1): iters passes over S (D, L) and Phi^-1 (D^-1,
+    explicit sub-diagonal blocks M_k, full) plus one initial Phi^-1 pass.
+    Every FP64 residual reads D and L in FP64 (or FP32 hi + FP32 lo); a zero
+    start needs no residual before its first inner solve (the fused kernel),
+    so there are `outer` residual sweeps, `outer + 1` for the explicit one.
     """
     N = b.N.astype(np.float64)
-    nn = b.nx.astype(np.float64) ** 2
+    nx = b.nx.astype(np.float64)
+    nn = nx * nx
+    npk = nx * (nx + 1) / 2
     e = 8.0 if precision == "fp64" else 4.0
-    nbS = nn * (2 * N - 1)
     it = iters.astype(np.float64)
     st = outer.astype(np.float64)
     if kernel == 0:
-        inner = e * nn * (3 * N - 1) * (it + st)
+        inner = e * (N * 2 * npk + (N - 1) * nn) * (it + st)
+        sweeps = st
     else:
-        nbP = nn * N if pc == "bj" else nbS
+        nbS = N * npk + (N - 1) * nn
+        nbP = N * npk if pc == "bj" else N * npk + (N - 1) * nn
         inner = e * (it * (nbS + nbP) + st * nbP)
-    return inner + 8.0 * (st + 1) * nbS + 16.0 * N * b.nx
+        sweeps = st + 1
+    return inner + 8.0 * sweeps * (N * npk + (N - 1) * nn) + 16.0 * N * nx
 
 
 def load_nets(b, warm: str) -> list:

@@ -89,6 +89,21 @@ __device__ void store_split(TM *hi, float *lo, const double *src, int cnt, doubl
     }
 }
 
+// Upper triangle of the symmetric n x n matrix src (row-major, LDS) into
+// packed form, with the FP32 remainder.
+template <typename TM>
+__device__ void store_split_packed(TM *hi, float *lo, const double *src, int n) {
+    for (int e = threadIdx.x; e < n * n; e += T) {
+        const int r = e / n, c = e - r * n;
+        if (c >= r) {
+            const double v = src[e];
+            const TM h = (TM)v;
+            hi[packed_row(r, n) + c] = h;
+            if (lo) lo[packed_row(r, n) + c] = (float)(v - (double)h);
+        }
+    }
+}
+
 __device__ __forceinline__ void knot_of(const BuildArgs &a, int &p, int &k) {
     const int g = blockIdx.x;
     p = a.knot_prob[g];
@@ -100,6 +115,15 @@ __device__ __forceinline__ void listed_knot_of(const BuildArgs &a, int &p, int &
     const int g = a.knot_list[blockIdx.x];
     p = a.knot_prob[g];
     k = g - (int)a.koff[p];
+}
+
+// full n x n matrix in LDS from its packed upper triangle
+template <typename TM>
+__device__ void team_load_packed(double *dst, const TM *src, int n) {
+    for (int e = threadIdx.x; e < n * n; e += T) {
+        const int r = e / n, c = e - r * n;
+        dst[e] = (double)src[packed_index(r, c, n)];
+    }
 }
 
 template <typename TM>
@@ -138,9 +162,10 @@ __global__ __launch_bounds__(T) void k_build_S(BuildArgs a) {
     const int nx = a.nx[p], nu = a.nu[p];
     const int nn = nx * nx;
     const int64_t o = a.off_nn[p] + (int64_t)k * nn;
-    const int bs = block_stride(nx, sizeof(TM));
-    const int64_t os = a.off_blk[p] + (int64_t)k * bs;          // remainder arrays
-    TM *blk = (TM *)a.B3 + 3 * a.off_blk[p] + (int64_t)k * 3 * bs;  // D_k, L_k, D_k^-1
+    const int bs = block_stride(nx, sizeof(TM)), bp = packed_stride(nx, sizeof(TM));
+    const int64_t os = a.off_blk[p] + (int64_t)k * bs;  // remainder of L_k
+    const int64_t od = a.off_pk[p] + (int64_t)k * bp;   // remainder of D_k (packed)
+    TM *blk = (TM *)a.B3 + a.off_b3[p] + (int64_t)k * (2 * bp + bs);  // D_k (packed), L_k, D_k^-1 (packed)
     double *Dm = sm, *Am = Dm + nn, *Qp = Am + nn, *T1 = Qp + nn, *Bm = T1 + nn;
     double *Rm = Bm + nx * nu, *BR = Rm + nu * nu, *col = BR + nx * nu;
     team_load(Dm, a.Qinv + o, nn);
@@ -171,10 +196,10 @@ __global__ __launch_bounds__(T) void k_build_S(BuildArgs a) {
             }
         }
         __syncthreads();
-        store_split(blk + bs, a.SLlo ? a.SLlo + os : nullptr, T1, nn, -1.0);
+        store_split(blk + bp, a.SLlo ? a.SLlo + os : nullptr, T1, nn, -1.0);
     } else {
         for (int e = threadIdx.x; e < nn; e += T) {
-            blk[bs + e] = (TM)0;
+            blk[bp + e] = (TM)0;
             if (a.SLlo) a.SLlo[os + e] = 0.f;
         }
     }
@@ -189,10 +214,10 @@ __global__ __launch_bounds__(T) void k_build_S(BuildArgs a) {
         }
     }
     __syncthreads();
-    store_split(blk, a.SDlo ? a.SDlo + os : nullptr, Dm, nn, 1.0);
+    store_split_packed(blk, a.SDlo ? a.SDlo + od : nullptr, Dm, nx);
     __syncthreads();
     const bool ok = team_spd_inverse(Dm, col, nx);
-    store_split(blk + 2 * bs, (float *)nullptr, Dm, nn, 1.0);
+    store_split_packed(blk + bp + bs, (float *)nullptr, Dm, nx);
     if (!ok && threadIdx.x == 0) atomicOr(a.status + p, kNotSpd);
 }
 
@@ -205,17 +230,18 @@ __global__ __launch_bounds__(T) void k_build_phi(BuildArgs a) {
     int p, k;
     knot_of(a, p, k);
     const int nx = a.nx[p];
-    const int nn = nx * nx, bs = block_stride(nx, sizeof(TM));
+    const int nn = nx * nx, bs = block_stride(nx, sizeof(TM)), bp = packed_stride(nx, sizeof(TM));
+    const int ks = 2 * bp + bs;
     const int64_t os = a.off_blk[p] + (int64_t)k * bs;
-    const TM *blk = (const TM *)a.B3 + 3 * a.off_blk[p] + (int64_t)k * 3 * bs;  // D_k, L_k, D_k^-1
+    const TM *blk = (const TM *)a.B3 + a.off_b3[p] + (int64_t)k * ks;  // D_k (packed), L_k, D_k^-1 (packed)
     double *Di = sm, *Lm = Di + nn, *Dp = Lm + nn, *T1 = Dp + nn, *T2 = T1 + nn;
     if (k == 0 || a.pc == 0) {
         for (int e = threadIdx.x; e < nn; e += T) ((TM *)a.PM)[os + e] = (TM)0;
         return;
     }
-    team_load_lo(Di, blk + 2 * bs, (const float *)nullptr, nn, 1.0);
-    team_load_lo(Lm, blk + bs, a.SLlo ? a.SLlo + os : nullptr, nn, -1.0);  // +phi = -L_k
-    team_load_lo(Dp, blk - bs, (const float *)nullptr, nn, 1.0);            // D_{k-1}^-1
+    team_load_packed(Di, blk + bp + bs, nx);                                // D_k^-1
+    team_load_lo(Lm, blk + bp, a.SLlo ? a.SLlo + os : nullptr, nn, -1.0);  // +phi = -L_k
+    team_load_packed(Dp, blk - ks + bp + bs, nx);                           // D_{k-1}^-1
     __syncthreads();
     team_gemm(nx, nx, nx, Di, Lm, false, T1);
     team_gemm(nx, nx, nx, T1, Dp, false, T2);
@@ -223,17 +249,31 @@ __global__ __launch_bounds__(T) void k_build_phi(BuildArgs a) {
     store_split((TM *)a.PM + os, (float *)nullptr, T2, nn, a.pc == 1 ? 0.5 : 1.0);
 }
 
-// Export kernel: one workgroup per knot copies hi (+ lo) from the stored
-// (padded) layout to the caller's packed FP64 layout.
+// Export kernel: one workgroup per knot copies one block kind from the
+// stored layout to the caller's full FP64 blocks (which: 0 D, 1 L, 2 D^-1,
+// 3 explicit stair blocks), adding the FP32 remainder lo when given.
 template <typename TM>
-__global__ void k_export(BuildArgs a, const TM *hi, int mult, int sub, const float *lo, double *dst) {
+__global__ void k_export(BuildArgs a, int which, const TM *hi, const float *lo, double *dst) {
     int p, k;
     knot_of(a, p, k);
-    const int nx = a.nx[p], nn = nx * nx, bs = block_stride(nx, sizeof(TM));
+    const int nx = a.nx[p], nn = nx * nx, bs = block_stride(nx, sizeof(TM)), bp = packed_stride(nx, sizeof(TM));
     const int64_t o = a.off_nn[p] + (int64_t)k * nn;
-    const int64_t oh = mult * a.off_blk[p] + (int64_t)k * mult * bs + sub * bs;
-    const int64_t ol = a.off_blk[p] + (int64_t)k * bs;
-    for (int e = threadIdx.x; e < nn; e += T) dst[o + e] = (double)hi[oh + e] + (lo ? (double)lo[ol + e] : 0.0);
+    const int64_t kb = a.off_b3[p] + (int64_t)k * (2 * bp + bs);
+    for (int e = threadIdx.x; e < nn; e += T) {
+        const int r = e / nx, c = e - r * nx;
+        double v;
+        if (which == 0) {
+            const int pi = packed_index(r, c, nx);
+            v = (double)hi[kb + pi] + (lo ? (double)lo[a.off_pk[p] + (int64_t)k * bp + pi] : 0.0);
+        } else if (which == 1) {
+            v = (double)hi[kb + bp + e] + (lo ? (double)lo[a.off_blk[p] + (int64_t)k * bs + e] : 0.0);
+        } else if (which == 2) {
+            v = (double)hi[kb + bp + bs + packed_index(r, c, nx)];
+        } else {
+            v = (double)hi[a.off_blk[p] + (int64_t)k * bs + e];
+        }
+        dst[o + e] = v;
+    }
 }
 
 __global__ void k_fill_i32(int32_t *dst, int32_t v, int64_t n) {
@@ -283,15 +323,14 @@ hipError_t launch_build_phi(const BuildArgs &a, int64_t knots, int nx_max, bool 
     return hipGetLastError();
 }
 
-hipError_t launch_export(const BuildArgs &a, const void *hi, int mult, int sub, const float *lo, bool fp32,
-                         double *dst, int64_t knots, hipStream_t s) {
+hipError_t launch_export(const BuildArgs &a, int which, const void *hi, const float *lo, bool fp32, double *dst,
+                         int64_t knots, hipStream_t s) {
     if (knots == 0) return hipSuccess;
     if (fp32)
-        hipLaunchKernelGGL(k_export<float>, dim3((unsigned)knots), dim3(T), 0, s, a, (const float *)hi, mult, sub, lo,
-                           dst);
+        hipLaunchKernelGGL(k_export<float>, dim3((unsigned)knots), dim3(T), 0, s, a, which, (const float *)hi, lo, dst);
     else
-        hipLaunchKernelGGL(k_export<double>, dim3((unsigned)knots), dim3(T), 0, s, a, (const double *)hi, mult, sub,
-                           lo, dst);
+        hipLaunchKernelGGL(k_export<double>, dim3((unsigned)knots), dim3(T), 0, s, a, which, (const double *)hi, lo,
+                           dst);
     return hipGetLastError();
 }
 

@@ -195,6 +195,23 @@ __device__ __forceinline__ void store_split_row(TM *__restrict__ hi, float *__re
     });
 }
 
+// Store the upper-triangle part (j >= i) of row i of a symmetric matrix into
+// its packed form (entry (i, j) at packed_row(i) + j), with the FP32 remainder.
+template <typename TM, int NX>
+__device__ __forceinline__ void store_split_packed_row(TM *__restrict__ hi, float *__restrict__ lo, int i,
+                                                       const double (&r)[NX]) {
+    const int base = packed_row(i, NX);
+    static_for<0, NX>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        if (j >= i) {
+            const double v = r[j];
+            const TM h = (TM)v;
+            hi[base + j] = h;
+            if (lo) lo[base + j] = (float)(v - (double)h);
+        }
+    });
+}
+
 }  // namespace
 
 // Phase 1 for one state size: Q_k^-1 for every knot and R_k^-1 for k < N-1
@@ -226,7 +243,7 @@ __global__ __launch_bounds__(kThreads) void k_build_inv_nx(BuildArgs a, const in
 }
 
 // Phase 2 for one state size: D_k, L_k (storage type, FP32 remainder under
-// FP32 storage) and D_k^-1, interleaved per knot.
+// FP32 storage) and D_k^-1, interleaved per knot (D_k and D_k^-1 packed).
 template <typename TM, int NX>
 __global__ __launch_bounds__(kThreads) void k_build_asm_nx(BuildArgs a, const int2 *items) {
     constexpr int KN = (kThreads / 64) * Lane<NX>::KW;
@@ -237,9 +254,10 @@ __global__ __launch_bounds__(kThreads) void k_build_asm_nx(BuildArgs a, const in
     const Lane<NX> ln = lane_of<NX>(it.y, N);
     double *M = sm + ln.g * knot_lds_doubles<NX>();
     const int nn = NX * NX, k = ln.knot, i = ln.i;
-    const int bs = block_stride(NX, sizeof(TM));
-    TM *blk = (TM *)a.B3 + 3 * a.off_blk[p] + (int64_t)k * 3 * bs;  // D_k, L_k, D_k^-1
-    const int64_t ol = a.off_blk[p] + (int64_t)k * bs;            // remainder arrays
+    const int bs = block_stride(NX, sizeof(TM)), bp = packed_stride(NX, sizeof(TM));
+    TM *blk = (TM *)a.B3 + a.off_b3[p] + (int64_t)k * (2 * bp + bs);  // D_k (packed), L_k, D_k^-1 (packed)
+    const int64_t ol = a.off_blk[p] + (int64_t)k * bs;               // remainder of L_k
+    const int64_t od = a.off_pk[p] + (int64_t)k * bp;                // remainder of D_k (packed)
     const bool prev = ln.row && k > 0;
 
     double d[NX], t[NX];
@@ -257,7 +275,7 @@ __global__ __launch_bounds__(kThreads) void k_build_asm_nx(BuildArgs a, const in
     if (prev) lds_put_row<NX>(M + i * NP, x);  // rows of A_{k-1}
     wave_sync();
     if (prev) row_times_t<NX>(t, M, NX, d);
-    if (ln.row) store_split_row<TM, NX>(blk + bs + i * NX, a.SLlo ? a.SLlo + ol + i * NX : nullptr, t, -1.0);
+    if (ln.row) store_split_row<TM, NX>(blk + bp + i * NX, a.SLlo ? a.SLlo + ol + i * NX : nullptr, t, -1.0);
     // D_k += B_{k-1} R_{k-1}^-1 B_{k-1}^T
     if (nu > 0) {
         wave_sync();
@@ -272,11 +290,11 @@ __global__ __launch_bounds__(kThreads) void k_build_asm_nx(BuildArgs a, const in
         wave_sync();
         if (prev) row_times_t<NX>(t, M, nu, d);
     }
-    symmetrise<NX>(d, i, ln.row, M);  // the PCG kernels read D by columns
-    if (ln.row) store_split_row<TM, NX>(blk + i * NX, a.SDlo ? a.SDlo + ol + i * NX : nullptr, d, 1.0);
+    symmetrise<NX>(d, i, ln.row, M);  // exactly symmetric before the upper triangle is kept
+    if (ln.row) store_split_packed_row<TM, NX>(blk, a.SDlo ? a.SDlo + od : nullptr, i, d);
     const bool ok = gj_inverse<NX>(d, i, ln.row, NX, M);
     symmetrise<NX>(d, i, ln.row, M);
-    if (ln.row) store_split_row<TM, NX>(blk + 2 * bs + i * NX, (float *)nullptr, d, 1.0);
+    if (ln.row) store_split_packed_row<TM, NX>(blk + bp + bs, (float *)nullptr, i, d);
     if (ln.row && !ok) atomicOr(a.status + p, kNotSpd);
 }
 

@@ -34,14 +34,15 @@ ssp_status alloc_storage(ssp_batch *b, bool fp32) {
     free_storage(b);
     const size_t elem = fp32 ? sizeof(float) : sizeof(double);
     const size_t nn = (size_t)(fp32 ? b->off_blk32 : b->off_blk64)[b->P];
+    const size_t n3 = (size_t)(fp32 ? b->off_b3_32 : b->off_b3_64)[b->P];
     const size_t nv = (size_t)b->off_v[b->P];
-    if (hipMalloc(&b->B3, std::max<size_t>(3 * nn, 1) * elem) != hipSuccess) {
+    if (hipMalloc(&b->B3, std::max<size_t>(n3, 1) * elem) != hipSuccess) {
         free_storage(b);
         g_last_error = "hipMalloc of matrix storage failed";
         return SSP_ERR_ALLOC;
     }
     if (fp32) {
-        if (dalloc(&b->SDlo, nn) != hipSuccess || dalloc(&b->SLlo, nn) != hipSuccess) {
+        if (dalloc(&b->SDlo, (size_t)b->off_pk32[b->P]) != hipSuccess || dalloc(&b->SLlo, nn) != hipSuccess) {
             free_storage(b);
             g_last_error = "hipMalloc of FP32 remainder storage failed";
             return SSP_ERR_ALLOC;
@@ -98,6 +99,8 @@ ssp::BuildArgs build_args(const ssp_batch *b) {
     a.off_nu = b->doff_nu;
     a.off_uu = b->doff_uu;
     a.off_blk = b->fp32 ? b->doff_blk32 : b->doff_blk64;
+    a.off_b3 = b->fp32 ? b->doff_b3_32 : b->doff_b3_64;
+    a.off_pk = b->doff_pk32;
     a.knot_prob = b->dknot;
     a.koff = b->dkoff;
     a.knot_list = b->dgeneric;
@@ -137,6 +140,8 @@ ssp::SolveArgs solve_args(const ssp_batch *b, double rel_tol, int32_t max_iter, 
     a.N = b->dN;
     a.nx = b->dnx;
     a.off_blk = b->fp32 ? b->doff_blk32 : b->doff_blk64;
+    a.off_b3 = b->fp32 ? b->doff_b3_32 : b->doff_b3_64;
+    a.off_pk = b->doff_pk32;
     a.off_v = b->doff_v;
     a.status = prob_status;
     a.B3 = b->B3;
@@ -169,8 +174,8 @@ std::vector<int> lds_candidates(const ssp_batch *b, int nx, int threads) {
     if (need == 0) return out;
     const int cmax = ssp::pcg2_steps_for(nx, b->fp32, threads, need);
     const int eb = b->fp32 ? 4 : 8, V = 16 / eb;
-    const int bs = ssp::block_stride(nx, eb), nxp = (nx + V - 1) / V * V;
-    const int per = (3 * bs + 4 * nxp) * eb;
+    const int ks = ssp::knot_stride(nx, eb), nxp = (nx + V - 1) / V * V;
+    const int per = (ks + 4 * nxp) * eb;
     const int lo = ssp::bt_sweep_min_lds(nx, true, 8);
     for (int c : {cmax, cmax - 1, (cmax + 1) / 2}) {
         if (c < 1) continue;
@@ -262,9 +267,15 @@ ssp_status ssp_batch_create(int32_t nprob, const int32_t *N, const int32_t *nx, 
     }
     b->off_blk32.assign(nprob + 1, 0);
     b->off_blk64.assign(nprob + 1, 0);
+    b->off_b3_32.assign(nprob + 1, 0);
+    b->off_b3_64.assign(nprob + 1, 0);
+    b->off_pk32.assign(nprob + 1, 0);
     for (int p = 0; p < nprob; ++p) {
         b->off_blk32[p + 1] = b->off_blk32[p] + (int64_t)N[p] * ssp::block_stride(nx[p], 4);
         b->off_blk64[p + 1] = b->off_blk64[p] + (int64_t)N[p] * ssp::block_stride(nx[p], 8);
+        b->off_b3_32[p + 1] = b->off_b3_32[p] + (int64_t)N[p] * ssp::knot_stride(nx[p], 4);
+        b->off_b3_64[p + 1] = b->off_b3_64[p] + (int64_t)N[p] * ssp::knot_stride(nx[p], 8);
+        b->off_pk32[p + 1] = b->off_pk32[p] + (int64_t)N[p] * ssp::packed_stride(nx[p], 4);
     }
     b->knots = b->koff[nprob];
     // the per-knot FP64 assembly keeps 4 nx^2 + 2 nx nu + nu^2 + nx doubles in LDS
@@ -372,6 +383,9 @@ ssp_status ssp_batch_create(int32_t nprob, const int32_t *N, const int32_t *nx, 
     up(&b->dkoff, b->koff.data(), nprob + 1);
     up(&b->doff_blk32, b->off_blk32.data(), nprob + 1);
     up(&b->doff_blk64, b->off_blk64.data(), nprob + 1);
+    up(&b->doff_b3_32, b->off_b3_32.data(), nprob + 1);
+    up(&b->doff_b3_64, b->off_b3_64.data(), nprob + 1);
+    up(&b->doff_pk32, b->off_pk32.data(), nprob + 1);
     if (rc == SSP_OK) {
         const size_t nn = b->off_nn[nprob], uu = b->off_uu[nprob], nv = b->off_v[nprob];
         if (dalloc(&b->Qinv, nn) != hipSuccess || dalloc(&b->Rinv, uu) != hipSuccess ||
@@ -400,7 +414,8 @@ ssp_status ssp_batch_destroy(ssp_batch *b) {
         if (b->dgorder) (void)hipFree(b->dgorder);
         for (void *p : {(void *)b->dN, (void *)b->dnx, (void *)b->dnu, (void *)b->dorder, (void *)b->dknot,
                         (void *)b->ditems, (void *)b->dgeneric, (void *)b->doff_nn, (void *)b->doff_nu, (void *)b->doff_uu, (void *)b->doff_v,
-                        (void *)b->dkoff, (void *)b->doff_blk32, (void *)b->doff_blk64, (void *)b->Qinv, (void *)b->Rinv,
+                        (void *)b->dkoff, (void *)b->doff_blk32, (void *)b->doff_blk64, (void *)b->doff_b3_32, (void *)b->doff_b3_64,
+                        (void *)b->doff_pk32, (void *)b->Qinv, (void *)b->Rinv,
                         (void *)b->r64, (void *)b->douter})
             if (p) (void)hipFree(p);
     }
@@ -500,15 +515,15 @@ ssp_status ssp_export(ssp_batch *b, int which, double *diag, double *off, void *
     hipStream_t s = (hipStream_t)stream;
     ssp::BuildArgs a = build_args(b);
     if (which == 1) {
-        SSP_HIP(ssp::launch_export(a, b->B3, 3, 2, nullptr, b->fp32, diag, b->knots, s));
+        SSP_HIP(ssp::launch_export(a, 2, b->B3, nullptr, b->fp32, diag, b->knots, s));
         ssp_status rc = ensure_m(b, s);
         if (rc != SSP_OK) return rc;
         a = build_args(b);
-        SSP_HIP(ssp::launch_export(a, b->PM, 1, 0, nullptr, b->fp32, off, b->knots, s));
+        SSP_HIP(ssp::launch_export(a, 3, b->PM, nullptr, b->fp32, off, b->knots, s));
     } else {
         const bool lo = which == 0 && b->fp32;
-        SSP_HIP(ssp::launch_export(a, b->B3, 3, 0, lo ? b->SDlo : nullptr, b->fp32, diag, b->knots, s));
-        SSP_HIP(ssp::launch_export(a, b->B3, 3, 1, lo ? b->SLlo : nullptr, b->fp32, off, b->knots, s));
+        SSP_HIP(ssp::launch_export(a, 0, b->B3, lo ? b->SDlo : nullptr, b->fp32, diag, b->knots, s));
+        SSP_HIP(ssp::launch_export(a, 1, b->B3, lo ? b->SLlo : nullptr, b->fp32, off, b->knots, s));
     }
     return SSP_OK;
 }

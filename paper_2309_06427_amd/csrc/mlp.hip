@@ -14,6 +14,7 @@
 
 #include "ssp_device.h"
 #include "ssp_mlp.h"
+#include "ssp_sweep.h"
 
 namespace ssp {
 
@@ -61,13 +62,17 @@ struct ColB {  // B(k, n) = p[n * ld + k]
     __device__ float operator()(int k, int n) const { return (k < K && n < N) ? p[(int64_t)n * ld + k] : 0.f; }
 };
 
-// Raw input f of knot m: vec D_k, then vec L_k (zero at the first knot), then gamma_k.
+// Raw input f of knot m: vec D_k (row-major, read from the packed upper
+// triangle), then vec L_k (zero at the first knot), then gamma_k.
 template <typename TM>
 __device__ __forceinline__ float raw_feature(const FeatSrc &s, const KnotInfo &q, int f) {
     const int nn = s.nx * s.nx;
     const TM *B3 = (const TM *)s.B3;
-    if (f < nn) return (float)B3[q.blk + f];
-    if (f < 2 * nn) return q.first ? 0.f : (float)B3[q.blk + s.bs + (f - nn)];
+    if (f < nn) {
+        const int r = f / s.nx, c = f - r * s.nx;
+        return (float)B3[q.blk + packed_index(r, c, s.nx)];
+    }
+    if (f < 2 * nn) return q.first ? 0.f : (float)B3[q.blk + s.lofs + (f - nn)];
     return (float)s.gamma[q.vec + (f - 2 * nn)];
 }
 
@@ -211,10 +216,10 @@ hipError_t gemm(int M, int N, int K, int splits, const AL &al, const BL &bl, con
 
 // First layer, z = standardised inputs x W1 + b1, h = gelu(z), for 64 knots
 // by up to 128 hidden units per workgroup (4 waves, each 16 knots x 128
-// units as 8 MFMA tiles).  A thread loads four consecutive inputs of one knot
-// with one vector load: the D and L blocks of a knot are adjacent in the
-// stored array (block stride nx^2 when nx^2 is a multiple of the vector
-// width, which the caller checks), and L_0 is stored as zeros.
+// units as 8 MFMA tiles).  A thread loads four consecutive inputs of one
+// knot: entries of D_k from its packed upper triangle, L_k (stored as zeros
+// at the first knot) with one vector load; nx^2 must be a multiple of 4 so
+// that no quad straddles two input sections (the caller checks).
 template <typename TM>
 __global__ __launch_bounds__(GT) void k_layer1(FeatSrc s, const float *__restrict__ W1, const float *__restrict__ b1,
                                                const float *__restrict__ mu, const float *__restrict__ isd, int nin,
@@ -225,6 +230,7 @@ __global__ __launch_bounds__(GT) void k_layer1(FeatSrc s, const float *__restric
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int m0 = blockIdx.x * BM, n0 = blockIdx.y * L1N;
     const int nn = s.nx * s.nx, nd = 2 * nn;
+    const int lofs = s.lofs;
     // this thread's row of the A tile and its input quad
     const int am = t >> 2, aq = (t & 3) * 4;
     const bool arow = m0 + am < s.M;
@@ -242,22 +248,29 @@ __global__ __launch_bounds__(GT) void k_layer1(FeatSrc s, const float *__restric
             const int f = k0 + aq;
             float x[4] = {0.f, 0.f, 0.f, 0.f};
             if (arow) {
-                if (f + 3 < nd) {
+                if (f < nn) {
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int r = (f + j) / s.nx, c = f + j - r * s.nx;
+                        x[j] = (float)src[packed_index(r, c, s.nx)];
+                    }
+                } else if (f + 3 < nd) {
+                    const TM *lsrc = src + lofs + (f - nn);
                     if constexpr (sizeof(TM) == 4) {
-                        const f32x4 v = *(const f32x4 *)(src + f);
+                        const f32x4 v = *(const f32x4 *)lsrc;
                         x[0] = v.x;
                         x[1] = v.y;
                         x[2] = v.z;
                         x[3] = v.w;
                     } else {
 #pragma unroll
-                        for (int j = 0; j < 4; ++j) x[j] = (float)src[f + j];
+                        for (int j = 0; j < 4; ++j) x[j] = (float)lsrc[j];
                     }
                 } else {
 #pragma unroll
                     for (int j = 0; j < 4; ++j) {
                         const int fj = f + j;
-                        if (fj < nd) x[j] = (float)src[fj];
+                        if (fj < nd) x[j] = (float)src[lofs + (fj - nn)];
                         else if (fj < nin) x[j] = (float)s.gamma[q.vec + (fj - nd)];
                     }
                 }
@@ -310,8 +323,8 @@ int split_count(int K, int splits) {
 
 // ------------------------------------------------------------ small kernels ---
 
-__global__ void k_knot_info(const int32_t *knot_prob, const int64_t *koff, const int32_t *N, const int64_t *off_blk,
-                            const int64_t *off_v, const int32_t *list, int64_t g0, int M, int nx, int bs,
+__global__ void k_knot_info(const int32_t *knot_prob, const int64_t *koff, const int32_t *N, const int64_t *off_b3,
+                            const int64_t *off_v, const int32_t *list, int64_t g0, int M, int nx, int ks,
                             KnotInfo *out) {
     const int m = blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= M) return;
@@ -319,7 +332,7 @@ __global__ void k_knot_info(const int32_t *knot_prob, const int64_t *koff, const
     const int p = knot_prob[g];
     const int k = (int)(g - koff[p]);
     KnotInfo q;
-    q.blk = 3 * off_blk[p] + (int64_t)k * 3 * bs;
+    q.blk = off_b3[p] + (int64_t)k * ks;
     q.vec = off_v[p] + (int64_t)k * nx;
     q.first = k == 0;
     q.last = k == N[p] - 1;
@@ -430,16 +443,16 @@ __global__ __launch_bounds__(256) void k_smul(FeatSrc s, const float *X, float s
         const int m = (int)(e / nx), i = (int)(e - (int64_t)m * nx);
         const KnotInfo q = s.ki[m];
         const TM *B3 = (const TM *)s.B3;
-        const TM *Dr = B3 + q.blk + i * nx;
+        const TM *Dp = B3 + q.blk;  // D_k packed
         const float *x = X + (int64_t)m * nx;
         float y = 0.f;
-        for (int j = 0; j < nx; ++j) y += (float)Dr[j] * x[j];
+        for (int j = 0; j < nx; ++j) y += (float)Dp[packed_index(i, j, nx)] * x[j];
         if (!q.first) {
-            const TM *Lr = B3 + q.blk + s.bs + i * nx;  // row i of L_k
+            const TM *Lr = B3 + q.blk + s.lofs + i * nx;  // row i of L_k
             for (int j = 0; j < nx; ++j) y += (float)Lr[j] * x[j - nx];
         }
         if (!q.last) {
-            const TM *Ln = B3 + s.ki[m + 1].blk + s.bs;  // column i of L_{k+1}
+            const TM *Ln = B3 + s.ki[m + 1].blk + s.lofs;  // column i of L_{k+1}
             for (int j = 0; j < nx; ++j) y += (float)Ln[j * nx + i] * x[nx + j];
         }
         y *= scale;
@@ -488,7 +501,7 @@ template <typename TM>
 hipError_t forward_t(const FeatSrc &f, const NetView &w, const float *mu, const float *isd, float ys, float *Z1,
                      float *H1, float *Z2, float *H2, float *O, double *lam, hipStream_t s) {
     hipError_t e;
-    if (f.bs == f.nx * f.nx) {
+    if ((f.nx * f.nx) % 4 == 0) {
         hipLaunchKernelGGL(k_layer1<TM>, dim3((f.M + BM - 1) / BM, (w.H + 127) / 128), dim3(GT), 0, s, f, w.W1, w.b1,
                            mu, isd, w.nin, w.H, Z1, H1);
         if ((e = hipGetLastError())) return e;
@@ -542,12 +555,12 @@ hipError_t backward_t(const FeatSrc &f, const NetView &w, const float *mu, const
 
 }  // namespace
 
-hipError_t launch_knot_info(const int32_t *knot_prob, const int64_t *koff, const int32_t *N, const int64_t *off_blk,
-                            const int64_t *off_v, const int32_t *list, int64_t g0, int M, int nx, int bs,
+hipError_t launch_knot_info(const int32_t *knot_prob, const int64_t *koff, const int32_t *N, const int64_t *off_b3,
+                            const int64_t *off_v, const int32_t *list, int64_t g0, int M, int nx, int ks,
                             KnotInfo *out, hipStream_t s) {
     if (M <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_knot_info, dim3((M + 255) / 256), dim3(256), 0, s, knot_prob, koff, N, off_blk, off_v, list,
-                       g0, M, nx, bs, out);
+    hipLaunchKernelGGL(k_knot_info, dim3((M + 255) / 256), dim3(256), 0, s, knot_prob, koff, N, off_b3, off_v, list,
+                       g0, M, nx, ks, out);
     return hipGetLastError();
 }
 

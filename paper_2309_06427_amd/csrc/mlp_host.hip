@@ -114,13 +114,13 @@ ssp::FeatSrc feat_src(const ssp_batch *b, const ssp_mlp *m, const double *gamma,
     f.ki = m->ki;
     f.M = M;
     f.nx = m->nx;
-    f.bs = ssp::block_stride(m->nx, b->fp32 ? 4 : 8);
+    f.lofs = ssp::packed_stride(m->nx, b->fp32 ? 4 : 8);  // L_k after the packed D_k
     return f;
 }
 
 ssp_status knot_info(const ssp_batch *b, ssp_mlp *m, const int32_t *list, int64_t g0, int M, hipStream_t s) {
-    SSP_HIP(ssp::launch_knot_info(b->dknot, b->dkoff, b->dN, b->fp32 ? b->doff_blk32 : b->doff_blk64, b->doff_v,
-                                  list, g0, M, m->nx, ssp::block_stride(m->nx, b->fp32 ? 4 : 8), m->ki, s));
+    SSP_HIP(ssp::launch_knot_info(b->dknot, b->dkoff, b->dN, b->fp32 ? b->doff_b3_32 : b->doff_b3_64, b->doff_v,
+                                  list, g0, M, m->nx, ssp::knot_stride(m->nx, b->fp32 ? 4 : 8), m->ki, s));
     return SSP_OK;
 }
 
@@ -240,8 +240,8 @@ ssp_status ssp_mlp_fit_scaling(ssp_mlp *m, ssp_batch *b, const double *gamma, co
         g_last_error = "hipMalloc of knot info failed";
         return SSP_ERR_ALLOC;
     }
-    SSP_HIP(ssp::launch_knot_info(b->dknot, b->dkoff, b->dN, b->fp32 ? b->doff_blk32 : b->doff_blk64, b->doff_v, list,
-                                  0, (int)cnt, m->nx, ssp::block_stride(m->nx, b->fp32 ? 4 : 8), all, s));
+    SSP_HIP(ssp::launch_knot_info(b->dknot, b->dkoff, b->dN, b->fp32 ? b->doff_b3_32 : b->doff_b3_64, b->doff_v,
+                                  list, 0, (int)cnt, m->nx, ssp::knot_stride(m->nx, b->fp32 ? 4 : 8), all, s));
     ssp::FeatSrc f = feat_src(b, m, gamma, (int)cnt);
     f.ki = all;
     hipError_t e = ssp::launch_feature_stats(f, lambda_star, m->mu, m->isd, m->ys_dev, m->part, s);

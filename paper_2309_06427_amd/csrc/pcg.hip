@@ -55,9 +55,9 @@ __global__ __launch_bounds__(BLOCK) void k_pcg(SolveArgs a) {
         return;
     }
     bool has_M = a.PM != nullptr;
-    const TM *SD = (const TM *)a.B3 + 3 * onn, *SL = SD + bs, *PD = SD + 2 * bs;  // knot stride 3 bs
-    const int ks3 = 3 * bs;
-    const float *SDlo = a.SDlo ? a.SDlo + onn : nullptr, *SLlo = a.SLlo ? a.SLlo + onn : nullptr;
+    const int bp = packed_stride(nx, sizeof(TM)), ks3 = 2 * bp + bs;  // knot stride
+    const TM *SD = (const TM *)a.B3 + a.off_b3[p], *SL = SD + bp, *PD = SD + bp + bs;  // D, D^-1 packed
+    const float *SDlo = a.SDlo ? a.SDlo + a.off_pk[p] : nullptr, *SLlo = a.SLlo ? a.SLlo + onn : nullptr;
     const TM *PM = has_M ? (const TM *)a.PM + onn : nullptr;
     TI *W = (TI *)a.work;
     TI *R[2] = {W + 0 * a.tot_v + ov, W + 1 * a.tot_v + ov};
@@ -98,7 +98,7 @@ __global__ __launch_bounds__(BLOCK) void k_pcg(SolveArgs a) {
             // true residual r = gamma - S lambda in FP64
             double rr64 = 0.0;
             bt_sweep<double, TM, BLOCK, 0>(
-                N, g64, SD, ks3, SDlo, SL, ks3, SLlo, true, (double *)smem_raw, [&](int row) { return lam[row]; },
+                N, g64, SD, ks3, SDlo, bp, SL, ks3, SLlo, true, (double *)smem_raw, [&](int row) { return lam[row]; },
                 [&](int row, double y, double) {
                     const double r = gam[row] - y;
                     r64[row] = r;
@@ -144,7 +144,7 @@ __global__ __launch_bounds__(BLOCK) void k_pcg(SolveArgs a) {
             int rc = 0, pc = 0, it = 0, ist = kOk;
             TI rz = TI(0), rr = TI(0), beta = TI(0), alpha = TI(0);
             bt_sweep<TI, TM, BLOCK, 0>(
-                N, gP, PD, ks3, nullptr, PM, bs, nullptr, has_M, (TI *)smem_raw,
+                N, gP, PD, ks3, nullptr, bp, PM, bs, nullptr, has_M, (TI *)smem_raw,
                 [&](int row) { return (TI)(r64[row] * inv_s); },
                 [&](int row, TI y, TI x) {
                     Zv[row] = y;
@@ -172,7 +172,7 @@ __global__ __launch_bounds__(BLOCK) void k_pcg(SolveArgs a) {
                 const bool first = (it == 0);
                 TI *Pold = Pv[pc], *Pnew = Pv[pc ^ 1];
                 bt_sweep<TI, TM, BLOCK, 0>(
-                    N, gS, SD, ks3, nullptr, SL, ks3, nullptr, true, (TI *)smem_raw,
+                    N, gS, SD, ks3, nullptr, bp, SL, ks3, nullptr, true, (TI *)smem_raw,
                     [&](int row) { return first ? Zv[row] : Zv[row] + beta * Pold[row]; },
                     [&](int row, TI y, TI x) {
                         Qv[row] = y;
@@ -192,7 +192,7 @@ __global__ __launch_bounds__(BLOCK) void k_pcg(SolveArgs a) {
                 rr = TI(0);
                 TI *Rold = R[rc], *Rnew = R[rc ^ 1], *Pcur = Pv[pc];
                 bt_sweep<TI, TM, BLOCK, 0>(
-                    N, gP, PD, ks3, nullptr, PM, bs, nullptr, has_M, (TI *)smem_raw,
+                    N, gP, PD, ks3, nullptr, bp, PM, bs, nullptr, has_M, (TI *)smem_raw,
                     [&](int row) { return Rold[row] - alpha * Qv[row]; },
                     [&](int row, TI y, TI x) {
                         Zv[row] = y;

@@ -41,7 +41,7 @@ namespace {
 // 16-byte prefetch registers per thread (fewer for FP64, whose arithmetic
 // needs twice the registers)
 template <typename TM>
-constexpr int prefetch_slots() { return sizeof(TM) == 4 ? 16 : 8; }
+constexpr int prefetch_slots() { return sizeof(TM) == 4 ? 12 : 8; }
 
 // The six recurrence vectors of a problem.
 template <typename TI>
@@ -73,23 +73,24 @@ struct Vec16<double> {
 // on row l % nx of knot w * kw + l / nx, so all rows of a knot sit in one
 // wave.  A step covers C <= waves * kw knots.
 struct Geo2 {
-    int N, nx, nn, bs, nxp;  // knots, state size, block elements, block stride, vector slot stride
+    int N, nx, nn, bs, bp, ks, nxp;  // knots, state size, block elements, full / packed block stride,
+                                     // knot stride, vector slot stride
     int C, R, RU;            // knots per step, block/vector ring slots, u ring slots
     int kw;                  // knots per wave
 };
 
 // Knots per step that fit the wave mapping, the prefetch registers and the
-// LDS budget.  Ring slot: D, L, D^-1 blocks (3 bs) and the r, y, t, u vector
+// LDS budget.  Ring slot: one knot's D, L, D^-1 (knot stride) and the r, y, t, u vector
 // windows (4 nxp), plus one extra u slot.
 template <typename TM>
 __host__ __device__ inline int pcg2_knots_per_step(int nx, int block, int lds_bytes) {
     const int V = 16 / (int)sizeof(TM);
-    const int bs = block_stride(nx, sizeof(TM));
+    const int ks = knot_stride(nx, sizeof(TM));
     const int nxp = (nx + V - 1) / V * V;
     int C = (block / 64) * (64 / nx);
-    const int Cp = (prefetch_slots<TM>() * block * V) / (3 * bs);
+    const int Cp = (prefetch_slots<TM>() * block * V) / ks;
     if (Cp < C) C = Cp;
-    const int per = (3 * bs + 4 * nxp) * (int)sizeof(TM);
+    const int per = (ks + 4 * nxp) * (int)sizeof(TM);
     const int Cl = (lds_bytes - nxp * (int)sizeof(TM) - 16) / per - 2;  // + one u slot + 16-byte spot
     if (Cl < C) C = Cl;
     return C;  // may be < 1: the mapping cannot run this nx
@@ -109,11 +110,11 @@ struct Prefetch {
     TM vec[6];       // u, w, p, s, x, r of this thread's lead row
     double res = 0;  // init pass: the FP64 residual of that row instead
 
-    __device__ __forceinline__ void issue(const TM *B3, int k0, int kc, int bs, bool init, int lead_row,
+    __device__ __forceinline__ void issue(const TM *B3, int k0, int kc, int ks, bool init, int lead_row,
                                           const double *r64, const Vecs<TM> vs) {
-        // the step's D, L, D^-1 blocks: one contiguous chunk of 3 kc bs elements
-        const int nvec = 3 * kc * bs / V;
-        const VT *src = (const VT *)(B3 + (int64_t)k0 * 3 * bs);
+        // the step's D, L, D^-1 blocks: one contiguous chunk of kc knot strides
+        const int nvec = kc * ks / V;
+        const VT *src = (const VT *)(B3 + (int64_t)k0 * ks);
         static_for<0, kPF>([&](auto mc) {
             constexpr int m = decltype(mc)::value;
             int q = threadIdx.x + m * BLOCK;
@@ -133,16 +134,16 @@ struct Prefetch {
         }
     }
 
-    // Copy the prefetched chunk into the block ring (3 bs elements per slot,
+    // Copy the prefetched chunk into the block ring (one knot stride per slot,
     // in the same D, L, D^-1 order): register m lands at
-    // (ring slot of k0) * 3 bs + its offset in the chunk, modulo the ring.
+    // (ring slot of k0) * ks + its offset in the chunk, modulo the ring.
     // Slots wholly past the chunk are skipped by a uniform branch; in the
     // partial slot the surplus lanes write a 16-byte scratch spot (dummy)
     // instead of branching.
-    __device__ __forceinline__ void store(TM *ring, int kc, int sb, int bs, int R, TM *dummy) const {
-        const int nvec = 3 * kc * bs / V;
-        const int wrap = R * 3 * bs;
-        const int base = sb * 3 * bs;
+    __device__ __forceinline__ void store(TM *ring, int kc, int sb, int ks, int R, TM *dummy) const {
+        const int nvec = kc * ks / V;
+        const int wrap = R * ks;
+        const int base = sb * ks;
         static_for<0, kPF>([&](auto mc) {
             constexpr int m = decltype(mc)::value;
             if (m * BLOCK < nvec) {
@@ -234,6 +235,49 @@ __device__ __forceinline__ T row_dot(const T *__restrict__ blk, int i, const T *
     return block_dot<NX, false>(blk, i, x, nrt);
 }
 
+// Row i (= column i) of a symmetric block stored packed in LDS (upper
+// triangle by rows) times x: entry (j, i) sits at packed_row(j) + i for
+// j <= i and at packed_row(i) + j above.  Chunks of 8 terms, four partial
+// sums, as in block_dot.
+template <int NX, typename T>
+__device__ __forceinline__ T sym_dot(const T *__restrict__ P, int i, const T *__restrict__ x, int nrt) {
+    if constexpr (NX > 0) {
+        using P2 = typename std::conditional<sizeof(T) == 4, f32x2, f64x2>::type;
+        constexpr int CH = sizeof(T) == 4 ? kChunk : kChunk / 2;
+        const int ri = packed_row(i, NX);
+        T s[4] = {T(0), T(0), T(0), T(0)};
+        static_for<0, (NX + CH - 1) / CH>([&](auto cc) {
+            constexpr int j0 = decltype(cc)::value * CH;
+            constexpr int jn = NX - j0 < CH ? NX - j0 : CH;
+            T xr[jn], ar[jn];
+            static_for<0, jn / 2>([&](auto hc) {
+                constexpr int j = 2 * decltype(hc)::value;
+                const P2 v = *(const P2 *)(x + j0 + j);
+                xr[j] = v.x;
+                xr[j + 1] = v.y;
+            });
+            static_for<0, jn>([&](auto jc) {
+                constexpr int j = j0 + decltype(jc)::value;
+                ar[decltype(jc)::value] = P[j <= i ? packed_row(j, NX) + i : ri + j];
+            });
+            static_for<0, jn>([&](auto jc) {
+                constexpr int j = decltype(jc)::value;
+                s[(j0 + j) % 4] += ar[j] * xr[j];
+            });
+        });
+        return (s[0] + s[1]) + (s[2] + s[3]);
+    } else {
+        T s0 = T(0), s1 = T(0);
+        int j = 0;
+        for (; j + 2 <= nrt; j += 2) {
+            s0 += P[packed_index(i, j, nrt)] * x[j];
+            s1 += P[packed_index(i, j + 1, nrt)] * x[j + 1];
+        }
+        if (j < nrt) s0 += P[packed_index(i, j, nrt)] * x[j];
+        return s0 + s1;
+    }
+}
+
 }  // namespace
 
 // Per-thread partial sums of one pass.
@@ -252,11 +296,11 @@ __device__ __forceinline__ Dots<TI> fused_pass(const Geo2 &g, int pc, bool init,
                                                TI *Xv, TI *smem) {
     using TM = TI;
     constexpr int W = BLOCK / 64;
-    const int nx = NX > 0 ? NX : g.nx, bs = g.bs, nxp = g.nxp;
+    const int nx = NX > 0 ? NX : g.nx, bs = g.bs, bp = g.bp, ks = g.ks, nxp = g.nxp;
     const int N = g.N, C = g.C, R = g.R, RU = g.RU, kw = g.kw;
-    TM *ring = smem;  // slot s: D at s * 3 bs, L at + bs, D^-1 at + 2 bs
-    TM *rD = ring, *rL = ring + bs, *rDi = ring + 2 * bs;
-    const int ss = 3 * bs;  // slot stride of the block ring
+    TM *ring = smem;  // slot s: D (packed) at s * ks, L at + bp, D^-1 (packed) at + bp + bs
+    TM *rD = ring, *rL = ring + bp, *rDi = ring + bp + bs;
+    const int ss = ks;  // slot stride of the block ring
     TI *vr = ring + R * ss, *vy = vr + R * nxp, *vt = vy + R * nxp, *vu = vt + R * nxp;
     const bool bj = pc == 0;
     const TI c2 = pc == 2 ? TI(1) : TI(0.5);
@@ -276,7 +320,7 @@ __device__ __forceinline__ Dots<TI> fused_pass(const Geo2 &g, int pc, bool init,
     // s / sp: block-ring slots of k / k + 1
     auto s_row = [&](const TI *xb, int sx, int sxm, int sxp, int s, int sp, bool diag) -> TI {
         TI y = TI(0);
-        if (diag) y += col_dot<NX>(rD + s * ss, i, xb + sx * nxp, nx);        // D_k symmetric
+        if (diag) y += sym_dot<NX>(rD + s * ss, i, xb + sx * nxp, nx);        // D_k (packed)
         if (sxm >= 0) y += row_dot<NX>(rL + s * ss, i, xb + sxm * nxp, nx);   // row i of L_k
         if (sxp >= 0) y += col_dot<NX>(rL + sp * ss, i, xb + sxp * nxp, nx);  // column i of L_{k+1}
         return y;
@@ -289,13 +333,13 @@ __device__ __forceinline__ Dots<TI> fused_pass(const Geo2 &g, int pc, bool init,
     Prefetch<TM, BLOCK> pf;
     const int nsteps = (N + C - 1) / C;
     auto lead_row = [&](int k0, int kc) { return (lane_ok && kme < kc) ? (k0 + kme) * nx + i : -1; };
-    pf.issue(B3, 0, min(C, N), bs, init, lead_row(0, min(C, N)), r64, vsrc);
+    pf.issue(B3, 0, min(C, N), ks, init, lead_row(0, min(C, N)), r64, vsrc);
     int sb = 0, sbu = 0;  // ring slots of knot k0
     for (int c = 0; c < nsteps; ++c) {
         const int k0 = c * C, kc = min(C, N - k0), k1 = k0 + kc;
         const bool last = k1 == N;
         __syncthreads();  // every reader of the slots about to be refilled is done
-        pf.store(ring, kc, sb, bs, R, vu + RU * nxp);
+        pf.store(ring, kc, sb, ks, R, vu + RU * nxp);
         TM cur[6];
 #pragma unroll
         for (int v = 0; v < 6; ++v) cur[v] = pf.vec[v];
@@ -312,7 +356,7 @@ __device__ __forceinline__ Dots<TI> fused_pass(const Geo2 &g, int pc, bool init,
         if (rowU >= 0) Uv[rowU] = oU;
         if (rowW >= 0) Wv[rowW] = oW;
         rowA = rowU = rowW = -1;
-        if (!last) pf.issue(B3, k1, min(C, N - k1), bs, init, lead_row(k1, min(C, N - k1)), r64, vsrc);
+        if (!last) pf.issue(B3, k1, min(C, N - k1), ks, init, lead_row(k1, min(C, N - k1)), r64, vsrc);
 
         const bool lead = lane_ok && kme < kc;
         const int sl = slot_of(sb, kme, R);
@@ -339,7 +383,7 @@ __device__ __forceinline__ Dots<TI> fused_pass(const Geo2 &g, int pc, bool init,
         // B: y = D^-1 r on the lead knots (u itself for block-Jacobi)
         if (lead) {
             const TI *rk = vr + sl * nxp;
-            const TI y = col_dot<NX>(rDi + sl * ss, i, rk, nx);
+            const TI y = sym_dot<NX>(rDi + sl * ss, i, rk, nx);
             if (bj) {
                 vu[slot_of(sbu, kme, RU) * nxp + i] = y;
                 oU = y;
@@ -367,7 +411,7 @@ __device__ __forceinline__ Dots<TI> fused_pass(const Geo2 &g, int pc, bool init,
                 if (!lane_ok) break;
                 const int k = tlo + kk, dk = k - k0;
                 const int s = slot_of(sb, dk, R);
-                const TI z = col_dot<NX>(rDi + s * ss, i, vt + s * nxp, nx);
+                const TI z = sym_dot<NX>(rDi + s * ss, i, vt + s * nxp, nx);
                 const TI u = vy[s * nxp + i] - c2 * z;
                 vu[slot_of(sbu, dk, RU) * nxp + i] = u;
                 d.gam += vr[s * nxp + i] * u;
@@ -427,17 +471,16 @@ constexpr int residual_slots() { return sizeof(TM) == 4 ? 8 : 16; }
 
 // Knots per step of the pipelined FP64 residual pass for a compiled state
 // size (< 1: it cannot run and the staged sweep is used).  LDS: a ring of
-// C + 1 knots of D and L in FP64 (2 bs doubles each) and a lambda window of
-// C + 2 knots.
+// C + 1 knots of D (packed) and L in FP64 and a lambda window of C + 2 knots.
 template <typename TM>
 __host__ __device__ inline int residual_knots_per_step(int nx, int block, int lds_bytes) {
     const int V = 16 / (int)sizeof(TM);
-    const int bs = block_stride(nx, sizeof(TM));
+    const int per = packed_stride(nx, sizeof(TM)) + block_stride(nx, sizeof(TM));  // D and L of a knot
     const int nxp = (nx + 1) & ~1;
     int C = (block / 64) * (64 / nx);
-    const int Cp = (residual_slots<TM>() * block * V) / (2 * bs);
+    const int Cp = (residual_slots<TM>() * block * V) / per;
     if (Cp < C) C = Cp;
-    const int Cl = (lds_bytes / 8 - nxp) / (2 * bs + nxp) - 1;
+    const int Cl = (lds_bytes / 8 - nxp) / (per + nxp) - 1;
     if (Cl < C) C = Cl;
     return C;
 }
@@ -458,10 +501,12 @@ __device__ __forceinline__ double residual_pass(int N, int C, const TM *__restri
     constexpr int KP = residual_slots<TM>();
     constexpr bool LO = sizeof(TM) == 4;
     constexpr int W = BLOCK / 64, KW = 64 / NX, NXP = (NX + 1) & ~1;
-    constexpr int BS = (NX * NX + V - 1) / V * V;  // block stride of the storage
-    constexpr int VPK = 2 * BS / V;                // 16-byte vectors of D and L per knot
-    const int R = C + 1, RL = C + 2, ss = 2 * BS;
-    double *ring = smem, *win = smem + R * ss;  // slot: D (BS doubles), then L
+    constexpr int BS = (NX * NX + V - 1) / V * V;                // full block stride of the storage
+    constexpr int BP = (NX * (NX + 1) / 2 + V - 1) / V * V;      // packed block stride
+    constexpr int KS = 2 * BP + BS;                              // knot stride: D, L, D^-1
+    constexpr int VPK = (BP + BS) / V;                           // 16-byte vectors of D and L per knot
+    const int R = C + 1, RL = C + 2, ss = BP + BS;
+    double *ring = smem, *win = smem + R * ss;  // slot: D (packed, BP doubles), then L
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int kloc = lane / NX, i = lane - kloc * NX;
     const bool lane_ok = kloc < KW;
@@ -478,9 +523,9 @@ __device__ __forceinline__ double residual_pass(int N, int C, const TM *__restri
             if (q >= nvec) q = 0;  // surplus slots re-read the first vector
             const int kk = q / VPK, e = (q - kk * VPK) * V;
             const int64_t k = k0 + kk;
-            hi[m] = *(const VT *)(B3 + k * 3 * BS + e);
+            hi[m] = *(const VT *)(B3 + k * KS + e);
             if constexpr (LO) {
-                const float *src = e < BS ? Dlo + k * BS + e : Llo + k * BS + (e - BS);
+                const float *src = e < BP ? Dlo + k * BP + e : Llo + k * BS + (e - BP);
                 lo[m] = *(const f32x4 *)src;
             }
         });
@@ -531,10 +576,10 @@ __device__ __forceinline__ double residual_pass(int N, int C, const TM *__restri
             if (!lane_ok) break;
             const int k = klo + kk, dk = k - k0;
             const double *Dk = ring + slot_of(sb, dk, R) * ss;
-            double y = col_dot<NX>(Dk, i, win + slot_of(sw, dk, RL) * NXP, NX);  // D_k symmetric
-            if (k > 0) y += row_dot<NX>(Dk + BS, i, win + slot_of(sw, dk - 1, RL) * NXP, NX);
+            double y = sym_dot<NX>(Dk, i, win + slot_of(sw, dk, RL) * NXP, NX);  // D_k (packed)
+            if (k > 0) y += row_dot<NX>(Dk + BP, i, win + slot_of(sw, dk - 1, RL) * NXP, NX);
             if (k + 1 < N)
-                y += col_dot<NX>(ring + slot_of(sb, dk + 1, R) * ss + BS, i, win + slot_of(sw, dk + 1, RL) * NXP, NX);
+                y += col_dot<NX>(ring + slot_of(sb, dk + 1, R) * ss + BP, i, win + slot_of(sw, dk + 1, RL) * NXP, NX);
             const double r = gam[(int64_t)k * NX + i] - y;
             r64[(int64_t)k * NX + i] = r;
             rr += r * r;
@@ -550,9 +595,9 @@ __device__ __forceinline__ double residual_pass(int N, int C, const TM *__restri
 // Pointers of one problem inside the batch buffers.
 template <typename TI>
 struct Prob {
-    int N, bs, max_iter;
+    int N, bs, bp, ks, max_iter;
     double gnorm;
-    const TI *B3;  // interleaved D, L, D^-1 blocks of the problem (knot stride 3 bs)
+    const TI *B3;  // per knot: D (packed), L, D^-1 (packed), knot stride ks
     const float *SDlo, *SLlo;
     double *lam, *r64;
     const double *gam;
@@ -581,6 +626,8 @@ __device__ __forceinline__ Outcome solve_problem(const SolveArgs &a, const Prob<
     g.nx = nx;
     g.nn = nx * nx;
     g.bs = q.bs;
+    g.bp = q.bp;
+    g.ks = q.ks;
     g.nxp = (nx + Vec16<TM>::V - 1) / Vec16<TM>::V * Vec16<TM>::V;
     g.kw = 64 / nx;
     g.C = pcg2_knots_per_step<TM>(nx, BLOCK, a.lds_bytes);
@@ -607,7 +654,7 @@ __device__ __forceinline__ Outcome solve_problem(const SolveArgs &a, const Prob<
                                                                    q.r64, (double *)smem_raw);
             } else {
                 bt_sweep<double, TM, BLOCK, NX>(
-                    N, g64, q.B3, 3 * q.bs, q.SDlo, q.B3 + q.bs, 3 * q.bs, q.SLlo, true, (double *)smem_raw,
+                    N, g64, q.B3, q.ks, q.SDlo, q.bp, q.B3 + q.bp, q.ks, q.SLlo, true, (double *)smem_raw,
                     [&](int row) { return q.lam[row]; },
                     [&](int row, double y, double) {
                         const double r = q.gam[row] - y;
@@ -728,6 +775,8 @@ __global__ __launch_bounds__(BLOCK, 2) void k_pcg2(SolveArgs a) {
     Prob<TI> q;
     q.N = N;
     q.bs = block_stride(nx, sizeof(TM));
+    q.bp = packed_stride(nx, sizeof(TM));
+    q.ks = 2 * q.bp + q.bs;
     q.max_iter = a.max_iter > 0 ? a.max_iter : 10 * n;
     q.lam = a.lambda + ov;
     q.gam = a.gamma + ov;
@@ -744,8 +793,8 @@ __global__ __launch_bounds__(BLOCK, 2) void k_pcg2(SolveArgs a) {
         }
         return;
     }
-    q.B3 = (const TM *)a.B3 + 3 * ob;
-    q.SDlo = a.SDlo ? a.SDlo + ob : nullptr;
+    q.B3 = (const TM *)a.B3 + a.off_b3[p];
+    q.SDlo = a.SDlo ? a.SDlo + a.off_pk[p] : nullptr;
     q.SLlo = a.SLlo ? a.SLlo + ob : nullptr;
     TI *W = (TI *)a.work;
     q.Rv = W + 0 * a.tot_v + ov;
@@ -802,8 +851,8 @@ int pcg2_lds(int nx_max, bool fp32, int threads) {
                  : pcg2_knots_per_step<double>(nx_max, threads, 1 << 30);
     if (C < 1) return 0;
     const int V = 16 / eb;
-    const int bs = block_stride(nx_max, eb), nxp = (nx_max + V - 1) / V * V;
-    const int per = (3 * bs + 4 * nxp) * eb;
+    const int ks = knot_stride(nx_max, eb), nxp = (nx_max + V - 1) / V * V;
+    const int per = (ks + 4 * nxp) * eb;
     int bytes = (C + 2) * per + nxp * eb + 16;
     const int res = bt_sweep_min_lds(nx_max, true, 8);
     if (bytes < res) bytes = res;

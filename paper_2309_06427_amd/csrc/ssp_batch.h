@@ -50,7 +50,9 @@ struct ssp_batch {
     int P = 0;
     std::vector<int32_t> N, nx, nu;
     std::vector<int64_t> off_nn, off_nu, off_uu, off_v, koff;
-    std::vector<int64_t> off_blk32, off_blk64;  // stored-block offsets (padded stride)
+    std::vector<int64_t> off_blk32, off_blk64;  // full-block offsets (padded stride bs)
+    std::vector<int64_t> off_b3_32, off_b3_64;  // solve-array offsets (knot stride)
+    std::vector<int64_t> off_pk32;              // packed-block offsets (D remainders, FP32 storage)
     int nx_max = 1, nu_max = 0;
     int64_t knots = 0;
     // device metadata
@@ -66,12 +68,13 @@ struct ssp_batch {
     std::vector<std::pair<int, std::pair<int32_t *, int64_t>>> nx_knots;
     int64_t *doff_nn = nullptr, *doff_nu = nullptr, *doff_uu = nullptr, *doff_v = nullptr, *dkoff = nullptr;
     int64_t *doff_blk32 = nullptr, *doff_blk64 = nullptr;
+    int64_t *doff_b3_32 = nullptr, *doff_b3_64 = nullptr, *doff_pk32 = nullptr;
     // FP64 build workspaces
     double *Qinv = nullptr, *Rinv = nullptr;
     // stored matrices
     bool fp32 = false;
     bool have_storage = false;
-    void *B3 = nullptr;  // per knot: D_k, L_k, D_k^-1 (storage type, padded stride bs each)
+    void *B3 = nullptr;  // per knot: D_k (packed), L_k, D_k^-1 (packed), storage type
     void *PM = nullptr;  // explicit stair blocks, built on demand
     float *SDlo = nullptr, *SLlo = nullptr;
     // solve workspace

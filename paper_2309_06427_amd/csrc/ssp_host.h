@@ -9,14 +9,16 @@ namespace ssp {
 struct BuildArgs {
     const int32_t *N, *nx, *nu;
     const int64_t *off_nn, *off_nu, *off_uu;  // input (caller) layout
-    const int64_t *off_blk;                   // stored-block layout (padded block stride)
+    const int64_t *off_blk;                   // full-block layout: sum of N bs (L remainders, explicit blocks)
+    const int64_t *off_b3;                    // solve array: sum of N knot_stride
+    const int64_t *off_pk;                    // packed-block layout: sum of N packed_stride (D remainders)
     const int32_t *knot_prob;                 // global knot index -> problem
     const int64_t *koff;                      // problem -> first global knot
     const int32_t *knot_list;                 // generic assembly: workgroup -> global knot
     const double *A, *B, *Q, *R;
     double *Qinv, *Rinv;  // FP64 workspaces (layout of Q, R)
-    void *B3;           // per knot k: D_k, L_k, D_k^-1 blocks, each bs elements (storage type)
-    float *SDlo, *SLlo;  // FP64 remainders of D_k, L_k under FP32 storage (stride bs; else null)
+    void *B3;            // per knot k: D_k (packed), L_k (full), D_k^-1 (packed), storage type
+    float *SDlo, *SLlo;  // FP64 remainders of D_k (packed stride), L_k (stride bs) under FP32 storage
     void *PM;           // explicit Phi^-1[k][k-1] blocks (stride bs; null: not built)
     int32_t *status;
     int pc;  // 0 block-Jacobi, 1 additive stair, 2 symmetric stair
@@ -26,10 +28,11 @@ struct BuildArgs {
 struct SolveArgs {
     const int32_t *order;  // workgroup -> problem (largest first)
     const int32_t *N, *nx;
-    const int64_t *off_blk, *off_v;
+    const int64_t *off_blk, *off_v;  // full-block layout (L remainders, explicit blocks), vectors
+    const int64_t *off_b3, *off_pk;  // solve array, packed-block layout (D remainders)
     int32_t *status;
-    const void *B3;            // interleaved D, L, D^-1 blocks (3 bs per knot)
-    const float *SDlo, *SLlo;  // FP64 remainders of D, L (bs per knot)
+    const void *B3;            // per knot: D (packed), L, D^-1 (packed)
+    const float *SDlo, *SLlo;  // FP64 remainders of D (packed stride), L (stride bs)
     const void *PM;            // explicit sub-diagonal blocks (explicit kernel only)
     int pc;               // 0 block-Jacobi, 1 additive stair, 2 symmetric stair
     const double *gamma;
@@ -59,11 +62,11 @@ int build_knots_per_item(int nx);
 hipError_t launch_build_class(int cls, const BuildArgs &a, const int2 *items, int nitems, bool fp32, hipStream_t s);
 // Explicit stair blocks from the stored D^-1 and L (every knot of the batch).
 hipError_t launch_build_phi(const BuildArgs &a, int64_t knots, int nx_max, bool fp32, hipStream_t s);
-// Copy one stored block array to the caller's packed FP64 layout: block k of
-// problem p sits at mult * off_blk[p] + k * mult * bs + sub * bs of `hi`
-// (mult = 3 for the interleaved array, 1 otherwise), plus `lo` (stride bs).
-hipError_t launch_export(const BuildArgs &a, const void *hi, int mult, int sub, const float *lo, bool fp32,
-                         double *dst, int64_t knots, hipStream_t s);
+// Copy one stored block kind to the caller's FP64 layout (full nx x nx
+// blocks at off_nn): which = 0 D_k (+ packed remainder lo), 1 L_k (+ lo),
+// 2 D_k^-1, 3 the explicit stair blocks (array `hi`, stride bs).
+hipError_t launch_export(const BuildArgs &a, int which, const void *hi, const float *lo, bool fp32, double *dst,
+                         int64_t knots, hipStream_t s);
 hipError_t launch_fill_i32(int32_t *dst, int32_t v, int64_t n, hipStream_t s);
 hipError_t launch_fill_f64(double *dst, double v, int64_t n, hipStream_t s);
 

@@ -6,9 +6,9 @@
 
 namespace ssp {
 
-// One knot of a feature set: element offset of its D block in the stored
-// array (L follows at +bs), offset of its rows in the vector layout, and
-// whether it is the first / last knot of its problem.
+// One knot of a feature set: element offset of its run in the stored array
+// (D_k packed, then L_k at +lofs), offset of its rows in the vector layout,
+// and whether it is the first / last knot of its problem.
 struct KnotInfo {
     int64_t blk;
     int64_t vec;
@@ -16,13 +16,14 @@ struct KnotInfo {
 };
 
 // Knots whose inputs are read: M knots of state size nx from the stored
-// blocks (storage type float when fp32, else double, block stride bs).
+// blocks (storage type float when fp32, else double; L_k at lofs after the
+// start of a knot's run).
 struct FeatSrc {
     const void *B3;
     bool fp32;
     const double *gamma;
     const KnotInfo *ki;
-    int M, nx, bs;
+    int M, nx, lofs;
 };
 
 // Parameter layout (floats): W1 (nin x H), b1, W2 (H x H), b2, W3 (H x nx), b3.
@@ -31,10 +32,10 @@ struct NetView {
     const float *W1, *b1, *W2, *b2, *W3, *b3;
 };
 
-// knot_prob / koff / N / off_blk / off_v: batch metadata (device).  Knot m is
-// list[m] when list != null, else g0 + m.
-hipError_t launch_knot_info(const int32_t *knot_prob, const int64_t *koff, const int32_t *N, const int64_t *off_blk,
-                            const int64_t *off_v, const int32_t *list, int64_t g0, int M, int nx, int bs,
+// knot_prob / koff / N / off_b3 / off_v: batch metadata (device); ks: knot
+// stride of the stored array.  Knot m is list[m] when list != null, else g0 + m.
+hipError_t launch_knot_info(const int32_t *knot_prob, const int64_t *koff, const int32_t *N, const int64_t *off_b3,
+                            const int64_t *off_v, const int32_t *list, int64_t g0, int M, int nx, int ks,
                             KnotInfo *out, hipStream_t s);
 
 // Per-feature mean and 1 / max(std, 1e-6) of the inputs of f's knots, and the

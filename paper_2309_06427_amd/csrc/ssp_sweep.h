@@ -12,12 +12,29 @@ __host__ __device__ inline int block_stride(int nx, int elem_bytes) {
     return (nx * nx + v - 1) / v * v;
 }
 
+// The symmetric blocks D_k and D_k^-1 are stored packed: the upper triangle
+// row by row, entry (r, c) with r <= c at packed_row(r, nx) + c, padded to
+// 16 bytes.
+__host__ __device__ constexpr int packed_row(int r, int nx) { return r * nx - r * (r + 1) / 2; }
+__host__ __device__ inline int packed_stride(int nx, int elem_bytes) {
+    const int v = 16 / elem_bytes;
+    return (nx * (nx + 1) / 2 + v - 1) / v * v;
+}
+// packed index of entry (i, j) of a symmetric block
+__host__ __device__ inline int packed_index(int i, int j, int nx) {
+    return i <= j ? packed_row(i, nx) + j : packed_row(j, nx) + i;
+}
+// One knot of the solve array: D_k (packed), L_k (full), D_k^-1 (packed).
+__host__ __device__ inline int knot_stride(int nx, int elem_bytes) {
+    return 2 * packed_stride(nx, elem_bytes) + block_stride(nx, elem_bytes);
+}
+
 // Staging geometry of one sweep.  Rows of a staged block are padded to
 // nx + 1 elements (odd for even nx) so that row-wise LDS reads by
 // consecutive lanes fall in distinct banks.
 struct Geo {
     int nx, ldx, blk, nn, bs, C;
-    uint64_t mg, mgb;  // division magics for nx and bs
+    uint64_t mg, mgb, mgn;  // division magics for nx, bs and nx * nx
 };
 
 template <typename TS>
@@ -30,6 +47,7 @@ __device__ __forceinline__ Geo make_geo(int nx, int bs, bool has_sub, int lds_by
     g.bs = bs;
     g.mg = div_magic(nx);
     g.mgb = div_magic(bs);
+    g.mgn = div_magic(nx * nx);
     const int per_knot = (has_sub ? 2 : 1) * g.blk + nx;
     const int fixed = (has_sub ? g.blk : 0) + 2 * nx;
     int C = block / nx;
@@ -46,17 +64,32 @@ inline int bt_sweep_min_lds(int nx, bool has_sub, int elem_bytes) {
 }
 
 // Copy the blocks [k0, k0 + kc) of a stored array (block k at src + k * ks,
-// its FP32 remainder at lo + k * bs) into LDS rows padded to ldx.
+// its FP32 remainder at lo + k * los) into LDS rows padded to ldx.  packed:
+// the stored blocks are symmetric and packed (upper triangle) and are
+// unpacked to full rows here.
 template <typename TS, typename TM, int BLOCK>
 __device__ __forceinline__ void stage_blocks(TS *dst, const TM *__restrict__ src, int ks,
-                                             const float *__restrict__ lo, int k0, int kc, const Geo &g) {
-    const int cnt = kc * g.bs;
-    for (int e = threadIdx.x; e < cnt; e += BLOCK) {
-        const int kk = fast_div(e, g.mgb), f = e - kk * g.bs;
-        if (f < g.nn) {
-            TS v = (TS)src[(int64_t)(k0 + kk) * ks + f];
-            if (lo) v += (TS)lo[(int64_t)(k0 + kk) * g.bs + f];
-            dst[kk * g.blk + f + fast_div(f, g.mg)] = v;
+                                             const float *__restrict__ lo, int los, bool packed, int k0, int kc,
+                                             const Geo &g) {
+    if (!packed) {
+        const int cnt = kc * g.bs;
+        for (int e = threadIdx.x; e < cnt; e += BLOCK) {
+            const int kk = fast_div(e, g.mgb), f = e - kk * g.bs;
+            if (f < g.nn) {
+                TS v = (TS)src[(int64_t)(k0 + kk) * ks + f];
+                if (lo) v += (TS)lo[(int64_t)(k0 + kk) * los + f];
+                dst[kk * g.blk + f + fast_div(f, g.mg)] = v;
+            }
+        }
+    } else {
+        const int cnt = kc * g.nn;
+        for (int e = threadIdx.x; e < cnt; e += BLOCK) {
+            const int kk = fast_div(e, g.mgn), f = e - kk * g.nn;
+            const int r = fast_div(f, g.mg), c = f - r * g.nx;
+            const int pi = packed_index(r, c, g.nx);
+            TS v = (TS)src[(int64_t)(k0 + kk) * ks + pi];
+            if (lo) v += (TS)lo[(int64_t)(k0 + kk) * los + pi];
+            dst[kk * g.blk + r * g.ldx + c] = v;
         }
     }
 }
@@ -82,17 +115,17 @@ __device__ __forceinline__ T strided_dot(const T *__restrict__ a, int stride, co
 
 // One block-tridiagonal product over a problem of N knots,
 //   y_k = Dg_k x_k + Sb_k x_{k-1} + Sb_{k+1}^T x_{k+1},
-// with Dg symmetric.  Dg, Sb: stored blocks at knot strides dks, sks
-// (Sb[0] ignored); Dlo / Slo: optional FP32 remainders (stride bs) added
-// while staging.  xval(row) gives the input
+// with Dg symmetric and stored packed.  Dg, Sb: stored blocks at knot
+// strides dks, sks (Sb[0] ignored); Dlo / Slo: optional FP32 remainders
+// (strides dlos, bs) added while staging.  xval(row) gives the input
 // vector (it may be called for halo rows of other threads); epi(row, y, x) is
 // called once per row by the row's owner.
 // NX: compile-time state size (0 = runtime g.nx).
 template <typename TS, typename TM, int BLOCK, int NX, typename XF, typename EF>
 __device__ __forceinline__ void bt_sweep(int N, const Geo &g, const TM *__restrict__ Dg, int dks,
-                                         const float *__restrict__ Dlo, const TM *__restrict__ Sb, int sks,
-                                         const float *__restrict__ Slo, bool has_sub, TS *smem, XF &&xval,
-                                         EF &&epi) {
+                                         const float *__restrict__ Dlo, int dlos, const TM *__restrict__ Sb,
+                                         int sks, const float *__restrict__ Slo, bool has_sub, TS *smem,
+                                         XF &&xval, EF &&epi) {
     const int tid = threadIdx.x;
     const int nx = NX > 0 ? NX : g.nx, ldx = nx + 1, blk = nx * ldx, C = g.C;
     TS *Ds = smem;
@@ -101,8 +134,8 @@ __device__ __forceinline__ void bt_sweep(int N, const Geo &g, const TM *__restri
     for (int k0 = 0; k0 < N; k0 += C) {
         const int kc = min(C, N - k0);
         __syncthreads();
-        stage_blocks<TS, TM, BLOCK>(Ds, Dg, dks, Dlo, k0, kc, g);
-        if (has_sub) stage_blocks<TS, TM, BLOCK>(Ss, Sb, sks, Slo, k0, min(kc + 1, N - k0), g);
+        stage_blocks<TS, TM, BLOCK>(Ds, Dg, dks, Dlo, dlos, true, k0, kc, g);
+        if (has_sub) stage_blocks<TS, TM, BLOCK>(Ss, Sb, sks, Slo, g.bs, false, k0, min(kc + 1, N - k0), g);
         {
             const int cnt = (kc + 2) * nx;
             const int base = (k0 - 1) * nx;
