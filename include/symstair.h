@@ -144,13 +144,21 @@ ssp_status ssp_export(ssp_batch *b, int which, double *diag, double *off, void *
 
 /* Kernel-mapping knobs of the batched PCG kernel (the autotuner sets them):
  * threads per workgroup (64, 128, 256 or 512), the LDS staging budget in
- * bytes per workgroup (0 = library default) and the kernel: 0 = fused single
- * sweep per iteration applying Phi^-1 = c1 D^-1 - c2 D^-1 S D^-1 from the
- * stored D^-1 and S (default), 1 = two sweeps per iteration over the
- * explicitly stored stair blocks.  The fused kernel is built for 128 and 256
- * threads and for knots that fit its LDS rings; otherwise the explicit kernel
- * runs.  Returns SSP_ERR_ARG for an unknown value or a budget that cannot
- * hold one knot of the largest nx. */
+ * bytes per workgroup (0 = library default) and the kernel:
+ *   0 = automatic (default): a batch of one problem with N >= 64 knots runs
+ *       the cooperative solve when its grid fits on the device at once, any
+ *       other batch the fused kernel;
+ *   1 = two sweeps per iteration over the explicitly stored stair blocks;
+ *   2 = the fused kernel: one sweep per iteration applying
+ *       Phi^-1 = D^-1 - c D^-1 O D^-1 (O = S - D; c = 1 symmetric stair,
+ *       1/2 additive stair, 0 block-Jacobi) from the stored D^-1 and S, one
+ *       workgroup per problem;
+ *   3 = the cooperative solve for a batch of one problem of any length whose
+ *       grid fits (else as 0): the same method with the problem's knots
+ *       spread over the grid, four per workgroup, and grid-wide barriers.
+ * The fused kernel is built for 128 and 256 threads and for knots that fit
+ * its LDS rings; otherwise the explicit kernel runs.  Returns SSP_ERR_ARG for
+ * an unknown value or a budget that cannot hold one knot of the largest nx. */
 ssp_status ssp_set_mapping(ssp_batch *b, int32_t threads, int32_t lds_bytes, int32_t kernel);
 
 /* ---------------------------------------------------------------------------

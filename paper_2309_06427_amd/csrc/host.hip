@@ -75,6 +75,21 @@ void group_mapping(const ssp_batch *b, const ssp_batch::Group &g, int *threads, 
     *lds = l;
 }
 
+// knots from which a single problem runs the cooperative solve by default
+constexpr int kCoopMinKnots = 64;
+
+// a single problem long enough to spread over the grid, whose grid fits on
+// the device at once (the plan is cached per storage precision)
+bool use_coop(ssp_batch *b) {
+    if (b->P != 1 || !b->dbar || !(b->kernel == 3 || (b->kernel == 0 && b->N[0] >= kCoopMinKnots))) return false;
+    const int key = b->fp32 ? 1 : 0;
+    if (b->coop_key != key) {
+        b->coop_key = key;
+        if (!ssp::coop_plan(b->N[0], b->nx[0], b->fp32, b->device, &b->coop_W, &b->coop_G)) b->coop_W = 0;
+    }
+    return b->coop_W > 0;
+}
+
 // every group can run the fused kernel
 bool fused_ok(const ssp_batch *b) {
     for (const auto &g : b->groups) {
@@ -386,6 +401,10 @@ ssp_status ssp_batch_create(int32_t nprob, const int32_t *N, const int32_t *nx, 
     up(&b->doff_b3_32, b->off_b3_32.data(), nprob + 1);
     up(&b->doff_b3_64, b->off_b3_64.data(), nprob + 1);
     up(&b->doff_pk32, b->off_pk32.data(), nprob + 1);
+    if (rc == SSP_OK && nprob == 1) {
+        if (dalloc(&b->dbar, ssp::coop_flag_words(N[0])) != hipSuccess || dalloc(&b->dpart, (size_t)8 * N[0]) != hipSuccess)
+            rc = SSP_ERR_ALLOC;
+    }
     if (rc == SSP_OK) {
         const size_t nn = b->off_nn[nprob], uu = b->off_uu[nprob], nv = b->off_v[nprob];
         if (dalloc(&b->Qinv, nn) != hipSuccess || dalloc(&b->Rinv, uu) != hipSuccess ||
@@ -415,7 +434,7 @@ ssp_status ssp_batch_destroy(ssp_batch *b) {
         for (void *p : {(void *)b->dN, (void *)b->dnx, (void *)b->dnu, (void *)b->dorder, (void *)b->dknot,
                         (void *)b->ditems, (void *)b->dgeneric, (void *)b->doff_nn, (void *)b->doff_nu, (void *)b->doff_uu, (void *)b->doff_v,
                         (void *)b->dkoff, (void *)b->doff_blk32, (void *)b->doff_blk64, (void *)b->doff_b3_32, (void *)b->doff_b3_64,
-                        (void *)b->doff_pk32, (void *)b->Qinv, (void *)b->Rinv,
+                        (void *)b->doff_pk32, (void *)b->dbar, (void *)b->dpart, (void *)b->Qinv, (void *)b->Rinv,
                         (void *)b->r64, (void *)b->douter})
             if (p) (void)hipFree(p);
     }
@@ -437,7 +456,7 @@ ssp_status ssp_set_mapping(ssp_batch *b, int32_t threads, int32_t lds_bytes, int
     if (!b) return SSP_ERR_ARG;
     if (threads != 64 && threads != 128 && threads != 256 && threads != 512) return SSP_ERR_ARG;
     if (lds_bytes < 0 || lds_bytes > 160 * 1024) return SSP_ERR_ARG;
-    if (kernel != 0 && kernel != 1) return SSP_ERR_ARG;
+    if (kernel < 0 || kernel > 3) return SSP_ERR_ARG;
     if (lds_bytes > 0 && lds_bytes < ssp::pcg_min_lds(b->nx_max, true)) return SSP_ERR_ARG;
     b->threads = threads;
     b->lds_bytes = lds_bytes;
@@ -484,7 +503,13 @@ ssp_status ssp_solve(ssp_batch *b, double rel_tol, int32_t max_iter, const doubl
     DevGuard g(b->device);
     hipStream_t s = (hipStream_t)stream;
     ssp::SolveArgs a = solve_args(b, rel_tol, max_iter, gamma, lambda, use_lambda0, iters, relres, prob_status);
-    if (b->kernel == 0 && fused_ok(b)) {
+    if (use_coop(b)) {
+        // one long problem: spread its knots over the whole grid
+        SSP_HIP(ssp::launch_fill_i32((int32_t *)b->dbar, 0, ssp::coop_flag_words(b->N[0]), s));
+        SSP_HIP(ssp::launch_coop(a, b->dbar, b->dpart, b->nx[0], b->coop_W, b->coop_G, b->fp32, s));
+        return SSP_OK;
+    }
+    if (b->kernel != 1 && fused_ok(b)) {
         return launch_groups(b, a, -1, s);
     } else {
         // explicit stored stair blocks (also the fallback when a knot does not
@@ -532,7 +557,8 @@ ssp_status ssp_autotune(ssp_batch *b, double rel_tol, const double *gamma, doubl
                         double *relres, int32_t *prob_status, void *stream) {
     if (!b || !gamma || !lambda || !iters || !relres || !prob_status || !(rel_tol >= 0.0)) return SSP_ERR_ARG;
     if (!b->built) return SSP_ERR_STATE;
-    if (b->kernel != 0 || !fused_ok(b)) return SSP_OK;  // only the fused kernel has a mapping to tune
+    if (b->kernel == 1 || !fused_ok(b) || use_coop(b))
+        return SSP_OK;  // only the batched fused kernel has a mapping to tune
     DevGuard dg(b->device);
     hipStream_t s = (hipStream_t)stream;
     int32_t *st0 = nullptr;

@@ -88,7 +88,11 @@ struct ssp_batch {
     ssp_precision prec = SSP_FP64;
     int threads = 128;
     int lds_bytes = 0;  // 0: default
-    int kernel = 0;     // 0 fused single-sweep, 1 explicit two-sweep
+    int kernel = 0;     // 0 auto, 1 explicit, 2 batched fused, 3 cooperative (one problem)
+    // cooperative solve of a single problem: barrier words and partial sums
+    unsigned *dbar = nullptr;
+    double *dpart = nullptr;
+    int coop_key = -1, coop_W = 0, coop_G = 0;  // cached plan (key: storage precision)
     // Fused solve groups: the problems of one state size, largest first,
     // launched on their own stream with their own workgroup size and LDS
     // budget (0: derived from threads / lds_bytes above).

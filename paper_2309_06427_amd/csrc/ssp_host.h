@@ -75,6 +75,17 @@ hipError_t launch_pcg(const SolveArgs &a, int nprob, bool fp32, int threads, hip
 int pcg_min_lds(int nx_max, bool has_sub);
 int pcg_default_lds(int nx_max, bool fp32, int threads);
 
+// Cooperative solve of a batch of one problem (N knots of state size nx):
+// W own knots per workgroup, G workgroups (coop_plan picks them, or returns
+// false when no such grid can be resident on `device` at once).  flags:
+// coop_flag_words(N) zeroed unsigned words; part: 8 * G doubles; the
+// problem's r64 row and two vectors of the work array are used as exchange
+// buffers.
+bool coop_plan(int N, int nx, bool fp32, int device, int *W, int *G);
+int coop_flag_words(int N);
+hipError_t launch_coop(const SolveArgs &a, unsigned *flags, double *part, int nx, int W, int G, bool fp32,
+                       hipStream_t s);
+
 // Dynamic LDS the fused kernel may ask for (a CU's 160 KB less room for
 // the kernel's own static arrays).
 constexpr int kFusedLdsCap = 160 * 1024 - 256;
