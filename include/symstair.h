@@ -145,7 +145,7 @@ ssp_status ssp_export(ssp_batch *b, int which, double *diag, double *off, void *
 /* Kernel-mapping knobs of the batched PCG kernel (the autotuner sets them):
  * threads per workgroup (64, 128, 256 or 512), the LDS staging budget in
  * bytes per workgroup (0 = library default) and the kernel:
- *   0 = automatic (default): a batch of one problem with N >= 64 knots runs
+ *   0 = automatic (default): a batch of one problem with N >= 24 knots runs
  *       the cooperative solve when its grid fits on the device at once, any
  *       other batch the fused kernel;
  *   1 = two sweeps per iteration over the explicitly stored stair blocks;

@@ -16,19 +16,22 @@
 // partial sums before the one synchronisation.  The refinement's FP64
 // residual (a few times per solve) exchanges lambda and r64 the same way.
 //
-// A published value is read by the neighbours after the synchronisation
-// that follows its store and is not stored again before the next one has
-// passed: w and the partial sums alternate between two buffers by iteration,
-// lambda and r64 are written once per refinement step.
-//
-// Synchronisation: every value that crosses workgroups is written and read
-// with agent-scope atomics (they are coherent across the chiplets' L2s
-// without cache maintenance); a workgroup arrives by storing its count of
-// synchronisations in its own word once all its threads' stores have
-// completed, and waits until every word has reached that count.  The wait
-// is bounded: a workgroup that waits too long raises an error flag that ends
-// every other wait, so the grid always drains.  The launch is cooperative
-// (the whole grid resident or the launch fails).
+// Synchronisation.  Every value that crosses workgroups is written and read
+// with agent-scope atomics, which are coherent across the chiplets' L2s
+// without cache maintenance.  The per-iteration exchange needs no separate
+// barrier: each 64-bit word carries 32 bits of payload and a 32-bit tag, the
+// running count of grid sums (continued across launches from a counter kept
+// in device memory, so a tag never repeats and nothing has to be cleared), so
+// a reader knows a word is current when its tag matches.  A workgroup
+// publishes its w rows and then its partial sums; wave 0 of every workgroup
+// polls all partial-sum records, the ghost waves poll their w rows.  Records
+// and w rows alternate between two buffers by sum parity, so a fast
+// workgroup cannot overwrite a value before every reader has it.  The FP64
+// residual of the refinement (a few times per solve) also needs lambda of
+// the neighbours first: a plain grid barrier (arrival words) does that.
+// Every wait is bounded: a workgroup that waits too long raises an error
+// flag that ends every other wait, so the grid always drains.  The launch is
+// cooperative (the whole grid resident or the launch fails).
 #include <math.h>
 
 #include "ssp_device.h"
@@ -44,12 +47,17 @@ constexpr int kMaxW = 4;              // own knots per workgroup at most
 constexpr int kMaxSlots = kMaxW + 2 * kGh;
 constexpr int kCoopThreads = 64 * kMaxSlots;
 constexpr unsigned kSpin = 1u << 22;  // polls before a wait gives up
-constexpr int kFlag0 = 64;            // flags[0]: error; flags[kFlag0 + g]: arrivals of workgroup g
+// flags[kTagBase]: tag counter kept across launches; flags[kErr]: error flag;
+// flags[kFlag0 + g]: arrivals of workgroup g at the plain barrier
+constexpr int kTagBase = 0, kErr = 63, kFlag0 = 64;
+
+typedef unsigned long long u64;
 
 struct CoopArgs {
     SolveArgs s;
-    unsigned *flags;  // kFlag0 + G words, zero at launch
-    double *part;     // 2 * G * 4 partial sums (double-buffered)
+    unsigned *flags;  // kFlag0 + G words; [kErr, kFlag0 + G) zero at launch
+    u64 *rec;         // partial-sum records: 2 parities x G x 6 words
+    u64 *wtag;        // tagged w rows: 2 parities x n x (sizeof(TI) / 4) words
     int G, W;         // workgroups, own knots per workgroup
 };
 
@@ -62,8 +70,37 @@ __device__ __forceinline__ T get(T *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Grid-wide synchronisation (every thread of every workgroup calls it).
-// Returns false once any workgroup has given up waiting.
+// tagged values: one word per float, two per double (low, high halves)
+__device__ __forceinline__ void put_tagged(u64 *p, float v, unsigned tag) {
+    put(p, ((u64)tag << 32) | __float_as_uint(v));
+}
+__device__ __forceinline__ void put_tagged(u64 *p, double v, unsigned tag) {
+    const u64 b = (u64)__double_as_longlong(v);
+    put(p, ((u64)tag << 32) | (b & 0xffffffffull));
+    put(p + 1, ((u64)tag << 32) | (b >> 32));
+}
+__device__ __forceinline__ bool get_tagged(u64 *p, float &v, unsigned tag) {
+    const u64 a = get(p);
+    v = __uint_as_float((unsigned)a);
+    return (unsigned)(a >> 32) == tag;
+}
+__device__ __forceinline__ bool get_tagged(u64 *p, double &v, unsigned tag) {
+    const u64 a = get(p), b = get(p + 1);
+    v = __longlong_as_double((long long)((b << 32) | (a & 0xffffffffull)));
+    return (unsigned)(a >> 32) == tag && (unsigned)(b >> 32) == tag;
+}
+
+// spin accounting of a wave's bounded wait; false once it has to give up
+__device__ __forceinline__ bool keep_waiting(unsigned *flags, unsigned spins) {
+    if (spins > kSpin || ((spins & 63) == 63 && __any(get(flags + kErr) != 0u))) {
+        if ((threadIdx.x & 63) == 0) put(flags + kErr, 1u);
+        return false;
+    }
+    return true;
+}
+
+// Plain grid barrier (every thread of every workgroup calls it): arrival
+// words counted up to `gen`.  Returns false once any workgroup has given up.
 __device__ __forceinline__ bool grid_sync(unsigned *flags, int G, unsigned &gen, int *s_ok) {
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this thread's stores are visible
     __syncthreads();
@@ -76,8 +113,7 @@ __device__ __forceinline__ bool grid_sync(unsigned *flags, int G, unsigned &gen,
             bool here = true;
             for (int h = lane; h < G; h += 64) here = here && (int)(get(flags + kFlag0 + h) - gen) >= 0;
             if (__all(here)) break;
-            if (spins > kSpin || ((spins & 63) == 63 && __any(get(flags) != 0u))) {
-                if (lane == 0) put(flags, 1u);
+            if (!keep_waiting(flags, spins)) {
                 ok = 0;
                 break;
             }
@@ -158,7 +194,8 @@ __global__ __launch_bounds__(kCoopThreads) void k_coop(CoopArgs ca) {
     const SolveArgs &a = ca.s;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ double red[3 * kMaxSlots];
-    __shared__ int s_ok;
+    __shared__ double sums[2][3];
+    __shared__ int s_ok, s_sum_ok[2];
     const int p = a.order[0];
     const int N = a.N[p], nx = NX > 0 ? NX : a.nx[p], n = N * nx;
     const int G = ca.G, W = ca.W, S = W + 2 * kGh, g = blockIdx.x;
@@ -178,8 +215,10 @@ __global__ __launch_bounds__(kCoopThreads) void k_coop(CoopArgs ca) {
     double *lam = a.lambda + ov;
     const double *gam = a.gamma + ov;
     double *r64g = a.r64 + ov;   // FP64 residual rows (published by their owners)
-    TI *Wg = (TI *)a.work + ov;  // w rows (published by their owners), two buffers by iteration parity
-    unsigned gen = 0;
+    constexpr int TW = sizeof(TI) / 4;  // tagged words per value
+    unsigned gen = 0;                   // plain barriers passed
+    const unsigned tag0 = get(ca.flags + kTagBase);  // tags of this launch: tag0 + 1, tag0 + 2, ...
+    unsigned nsum = 0;                  // grid sums done
     const int e = k * nx + i;    // this lane's element of the problem's vectors (when row)
 
     TM *blk = (TM *)smem_raw;
@@ -234,11 +273,15 @@ __global__ __launch_bounds__(kCoopThreads) void k_coop(CoopArgs ca) {
         if constexpr (REG) return dot_reg<RN>(rl1, x);
         else return dot_col(Lk1, i, x, nx);
     };
-    int red_idx = 0;
 
-    // grid-wide sums of three values over the own knots (fixed order: wave
-    // butterflies, own slots in order, then workgroups as below)
-    auto grid_sum3 = [&](double v0, double v1, double v2, double out[3]) -> bool {
+    // Grid-wide sums of three values over the own knots (fixed order: wave
+    // butterflies, own slots in order, then workgroups as below).  Before it
+    // publishes its record a workgroup has published its w rows (tagged like
+    // the record) and, with FENCE, completed its other stores.  Ghost waves
+    // with `wslot` wait for their row of w and return it in `wv`.
+    auto grid_sum3 = [&](double v0, double v1, double v2, double out[3], bool fence, u64 *wslot, TI &wv) -> bool {
+        ++nsum;
+        const unsigned tag = tag0 + nsum, par = nsum & 1;
         v0 = wave_sum(v0);
         v1 = wave_sum(v1);
         v2 = wave_sum(v2);
@@ -247,28 +290,66 @@ __global__ __launch_bounds__(kCoopThreads) void k_coop(CoopArgs ca) {
             red[sl * 3 + 1] = v1;
             red[sl * 3 + 2] = v2;
         }
+        if (threadIdx.x == 0) s_sum_ok[par] = 1;
+        if (fence) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         __syncthreads();
-        double *pb = ca.part + (red_idx & 1) * G * 4;
+        u64 *rb = ca.rec + (size_t)par * G * 6;
         if (threadIdx.x < 3) {
             double t = 0.0;
             for (int q = kGh; q < kGh + W; ++q) t += red[q * 3 + threadIdx.x];
-            put(pb + g * 4 + threadIdx.x, t);
+            put_tagged(rb + g * 6 + 2 * threadIdx.x, t, tag);
         }
-        ++red_idx;
-        const bool ok = grid_sync(ca.flags, G, gen, &s_ok);
-        // every wave sums the G partials the same way: lane h takes
-        // workgroups h, h + 64, ... in order, then the wave butterfly
-        double t0 = 0.0, t1 = 0.0, t2 = 0.0;
-        for (int h = lane; h < G; h += 64) {
-            t0 += get(pb + h * 4 + 0);
-            t1 += get(pb + h * 4 + 1);
-            t2 += get(pb + h * 4 + 2);
+        if (sl == 0) {
+            // every workgroup sums the G records the same way: lane h takes
+            // workgroups h, h + 64, ... in order, then the wave butterfly
+            double t0, t1, t2;
+            for (unsigned spins = 0;; ++spins) {
+                bool here = true;
+                t0 = t1 = t2 = 0.0;
+                for (int h = lane; h < G; h += 64) {
+                    double x0, x1, x2;
+                    const bool h0 = get_tagged(rb + h * 6 + 0, x0, tag);
+                    const bool h1 = get_tagged(rb + h * 6 + 2, x1, tag);
+                    const bool h2 = get_tagged(rb + h * 6 + 4, x2, tag);
+                    here = here && h0 && h1 && h2;
+                    t0 += x0;
+                    t1 += x1;
+                    t2 += x2;
+                }
+                if (__all(here)) break;
+                if (!keep_waiting(ca.flags, spins)) {
+                    s_sum_ok[par] = 0;
+                    break;
+                }
+            }
+            t0 = wave_sum(t0);
+            t1 = wave_sum(t1);
+            t2 = wave_sum(t2);
+            if (lane == 0) {
+                sums[par][0] = t0;
+                sums[par][1] = t1;
+                sums[par][2] = t2;
+            }
         }
-        out[0] = wave_sum(t0);
-        out[1] = wave_sum(t1);
-        out[2] = wave_sum(t2);
-        return ok;
+        if (wslot) {
+            for (unsigned spins = 0;; ++spins) {
+                TI x;
+                const bool here = !row || get_tagged(wslot, x, tag);
+                if (row) wv = x;
+                if (__all(here)) break;
+                if (!keep_waiting(ca.flags, spins)) {
+                    s_sum_ok[par] = 0;
+                    break;
+                }
+            }
+        }
+        __syncthreads();
+        out[0] = sums[par][0];
+        out[1] = sums[par][1];
+        out[2] = sums[par][2];
+        return s_sum_ok[par] != 0;
     };
+    TI wdummy = TI(0);
 
     int st = a.status[p];
     const bool failed_build = st != kOk;
@@ -285,7 +366,7 @@ __global__ __launch_bounds__(kCoopThreads) void k_coop(CoopArgs ca) {
             if (a.use_lambda0 == 0) put(lam + e, 0.0);
         }
         double t[3];
-        alive = grid_sum3(gg, bad, 0.0, t);
+        alive = grid_sum3(gg, bad, 0.0, t, false, nullptr, wdummy);
         gnorm = sqrt(t[0]);
         if (st == kOk && (!isfinite(gnorm) || t[1] != 0.0)) {
             st = kNonFinite;
@@ -339,7 +420,7 @@ __global__ __launch_bounds__(kCoopThreads) void k_coop(CoopArgs ca) {
                     put(r64g + e, r64);
                 }
                 double t[3];
-                if (!grid_sum3(rr, 0.0, 0.0, t)) {
+                if (!grid_sum3(rr, 0.0, 0.0, t, true, nullptr, wdummy)) {  // r64 rows are visible
                     alive = false;
                     break;
                 }
@@ -410,15 +491,16 @@ __global__ __launch_bounds__(kCoopThreads) void k_coop(CoopArgs ca) {
                     w = mv_d(Uw + sl * nxp);
                     if (k > 0) w += mv_l0(Uw + (sl - 1) * nxp);
                     if (k + 1 < N) w += mv_l1(Uw + (sl + 1) * nxp);
-                    put(Wg + (it & 1) * a.tot_v + e, w);
                 }
+                // this sum's tag and buffer: the next grid sum's
+                u64 *wslot = ca.wtag + ((size_t)((nsum + 1) & 1) * n + (row ? e : 0)) * TW;
+                if (own) put_tagged(wslot, w, tag0 + nsum + 1);
                 double t3[3];
                 if (!grid_sum3(own ? (double)(r * u) : 0.0, own ? (double)(w * u) : 0.0,
-                               own ? (double)(r * r) : 0.0, t3)) {
+                               own ? (double)(r * r) : 0.0, t3, false, is_own ? nullptr : wslot, w)) {
                     alive = false;
                     break;
                 }
-                if (row && !is_own) w = get(Wg + (it & 1) * a.tot_v + e);  // ghosts: the owners' w
                 const TI dgam = (TI)t3[0], ddel = (TI)t3[1], drho = (TI)t3[2];
                 if (it == 0) bnorm = sqrt(drho);
                 const TI rn = sqrt(drho);
@@ -469,6 +551,11 @@ __global__ __launch_bounds__(kCoopThreads) void k_coop(CoopArgs ca) {
     }
     if (!alive) st = kNonFinite;  // a wait gave up: report the problem as failed
     if (failed_build && own) put(lam + e, 0.0);
+    // The next launch's tags start after every tag this one may have used:
+    // a workgroup publishes sum s + 1 only after it has seen workgroup 0's
+    // record of sum s, so no tag beyond tag0 + nsum + 1 was written (also
+    // after a failed wait).  Every workgroup read tag0 before its first record.
+    if (g == 0 && threadIdx.x == 0) put(ca.flags + kTagBase, tag0 + nsum + 2);
     if (g == 0 && threadIdx.x == 0) {
         a.iters[p] = total;
         a.outer[p] = steps;
@@ -484,6 +571,9 @@ int coop_lds(int nx, bool fp32, int W) {
 }
 
 int coop_flag_words(int N) { return kFlag0 + N; }
+int coop_clear_first() { return kErr; }
+size_t coop_rec_words(int N) { return (size_t)12 * N; }
+size_t coop_wtag_words(int N, int nx) { return (size_t)4 * N * nx; }
 
 namespace {
 
@@ -527,13 +617,14 @@ bool coop_plan(int N, int nx, bool fp32, int device, int *W_out, int *G_out) {
     return false;
 }
 
-hipError_t launch_coop(const SolveArgs &a, unsigned *flags, double *part, int nx, int W, int G, bool fp32,
+hipError_t launch_coop(const SolveArgs &a, unsigned *flags, u64 *rec, u64 *wtag, int nx, int W, int G, bool fp32,
                        hipStream_t s) {
     if (W < 2 || W > kMaxW || G < 1) return hipErrorInvalidValue;
     CoopArgs ca;
     ca.s = a;
     ca.flags = flags;
-    ca.part = part;
+    ca.rec = rec;
+    ca.wtag = wtag;
     ca.G = G;
     ca.W = W;
     const void *f = (const void *)coop_kernel(nx, fp32);

@@ -76,7 +76,7 @@ void group_mapping(const ssp_batch *b, const ssp_batch::Group &g, int *threads, 
 }
 
 // knots from which a single problem runs the cooperative solve by default
-constexpr int kCoopMinKnots = 64;
+constexpr int kCoopMinKnots = 24;
 
 // a single problem long enough to spread over the grid, whose grid fits on
 // the device at once (the plan is cached per storage precision)
@@ -402,8 +402,15 @@ ssp_status ssp_batch_create(int32_t nprob, const int32_t *N, const int32_t *nx, 
     up(&b->doff_b3_64, b->off_b3_64.data(), nprob + 1);
     up(&b->doff_pk32, b->off_pk32.data(), nprob + 1);
     if (rc == SSP_OK && nprob == 1) {
-        if (dalloc(&b->dbar, ssp::coop_flag_words(N[0])) != hipSuccess || dalloc(&b->dpart, (size_t)8 * N[0]) != hipSuccess)
+        if (dalloc(&b->dbar, ssp::coop_flag_words(N[0])) != hipSuccess ||
+            dalloc(&b->drec, ssp::coop_rec_words(N[0])) != hipSuccess ||
+            dalloc(&b->dwtag, ssp::coop_wtag_words(N[0], nx[0])) != hipSuccess)
             rc = SSP_ERR_ALLOC;
+        else if (hipMemset(b->dbar, 0, sizeof(unsigned) * ssp::coop_flag_words(N[0])) != hipSuccess ||
+                 hipMemset(b->drec, 0, 8 * ssp::coop_rec_words(N[0])) != hipSuccess ||
+                 hipMemset(b->dwtag, 0, 8 * ssp::coop_wtag_words(N[0], nx[0])) != hipSuccess ||
+                 hipDeviceSynchronize() != hipSuccess)
+            rc = SSP_ERR_HIP;
     }
     if (rc == SSP_OK) {
         const size_t nn = b->off_nn[nprob], uu = b->off_uu[nprob], nv = b->off_v[nprob];
@@ -434,7 +441,7 @@ ssp_status ssp_batch_destroy(ssp_batch *b) {
         for (void *p : {(void *)b->dN, (void *)b->dnx, (void *)b->dnu, (void *)b->dorder, (void *)b->dknot,
                         (void *)b->ditems, (void *)b->dgeneric, (void *)b->doff_nn, (void *)b->doff_nu, (void *)b->doff_uu, (void *)b->doff_v,
                         (void *)b->dkoff, (void *)b->doff_blk32, (void *)b->doff_blk64, (void *)b->doff_b3_32, (void *)b->doff_b3_64,
-                        (void *)b->doff_pk32, (void *)b->dbar, (void *)b->dpart, (void *)b->Qinv, (void *)b->Rinv,
+                        (void *)b->doff_pk32, (void *)b->dbar, (void *)b->drec, (void *)b->dwtag, (void *)b->Qinv, (void *)b->Rinv,
                         (void *)b->r64, (void *)b->douter})
             if (p) (void)hipFree(p);
     }
@@ -505,8 +512,9 @@ ssp_status ssp_solve(ssp_batch *b, double rel_tol, int32_t max_iter, const doubl
     ssp::SolveArgs a = solve_args(b, rel_tol, max_iter, gamma, lambda, use_lambda0, iters, relres, prob_status);
     if (use_coop(b)) {
         // one long problem: spread its knots over the whole grid
-        SSP_HIP(ssp::launch_fill_i32((int32_t *)b->dbar, 0, ssp::coop_flag_words(b->N[0]), s));
-        SSP_HIP(ssp::launch_coop(a, b->dbar, b->dpart, b->nx[0], b->coop_W, b->coop_G, b->fp32, s));
+        const int c0 = ssp::coop_clear_first();
+        SSP_HIP(ssp::launch_fill_i32((int32_t *)b->dbar + c0, 0, ssp::coop_flag_words(b->N[0]) - c0, s));
+        SSP_HIP(ssp::launch_coop(a, b->dbar, b->drec, b->dwtag, b->nx[0], b->coop_W, b->coop_G, b->fp32, s));
         return SSP_OK;
     }
     if (b->kernel != 1 && fused_ok(b)) {

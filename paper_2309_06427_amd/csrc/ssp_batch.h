@@ -91,7 +91,7 @@ struct ssp_batch {
     int kernel = 0;     // 0 auto, 1 explicit, 2 batched fused, 3 cooperative (one problem)
     // cooperative solve of a single problem: barrier words and partial sums
     unsigned *dbar = nullptr;
-    double *dpart = nullptr;
+    unsigned long long *drec = nullptr, *dwtag = nullptr;
     int coop_key = -1, coop_W = 0, coop_G = 0;  // cached plan (key: storage precision)
     // Fused solve groups: the problems of one state size, largest first,
     // launched on their own stream with their own workgroup size and LDS

@@ -78,13 +78,18 @@ int pcg_default_lds(int nx_max, bool fp32, int threads);
 // Cooperative solve of a batch of one problem (N knots of state size nx):
 // W own knots per workgroup, G workgroups (coop_plan picks them, or returns
 // false when no such grid can be resident on `device` at once).  flags:
-// coop_flag_words(N) zeroed unsigned words; part: 8 * G doubles; the
-// problem's r64 row and two vectors of the work array are used as exchange
-// buffers.
+// coop_flag_words(N) unsigned words, all zero when allocated, words from
+// coop_clear_first() on zeroed before every launch; rec, wtag:
+// coop_rec_words(N) and coop_wtag_words(N, nx) 64-bit words, zero when
+// allocated and never cleared again.  The problem's r64 row is used as an
+// exchange buffer.
 bool coop_plan(int N, int nx, bool fp32, int device, int *W, int *G);
 int coop_flag_words(int N);
-hipError_t launch_coop(const SolveArgs &a, unsigned *flags, double *part, int nx, int W, int G, bool fp32,
-                       hipStream_t s);
+int coop_clear_first();
+size_t coop_rec_words(int N);
+size_t coop_wtag_words(int N, int nx);
+hipError_t launch_coop(const SolveArgs &a, unsigned *flags, unsigned long long *rec, unsigned long long *wtag, int nx,
+                       int W, int G, bool fp32, hipStream_t s);
 
 // Dynamic LDS the fused kernel may ask for (a CU's 160 KB less room for
 // the kernel's own static arrays).

@@ -1,5 +1,5 @@
 """GPU parity of the cooperative single-problem solve (a batch of one problem
-with N >= 64 knots spreads its knots over the grid, a few per workgroup, each
+with N >= 24 knots spreads its knots over the grid, a few per workgroup, each
 workgroup also carrying two ghost knots on each side)
 against the CPU oracle and against the batched fused kernel on the same
 problem.
