@@ -31,7 +31,7 @@ SOLVE_SOURCES = ("pcg2.hip", "ssp_device.h", "ssp_sweep.h", "ssp_host.h")
 MEASURED_TRAFFIC = {
     # (workload, pc, precision, kernel): (sources sha256[:16], bytes of one solve, all its dispatches)
     ("batch4096_ragged", "sym", "fp32_refine64", 0):
-        ("d53f1c4fb0b0d80d", ((22906029.625 + 7193650.3125) * 2.0 + (4052465.75 + 1735644.90625) * 1.0) * 1024),
+        ("21a65b40d77d9a82", (21573947.6875 * 2.0 + 5568480.03125 * 1.0) * 1024),
 }
 
 
@@ -51,12 +51,14 @@ def algorithmic_bytes(b, iters, outer, pc: str, precision: str, kernel: int = 0)
     (nx(nx+1)/2 elements), L_k full (nx^2); L_0 and Phi^-1[0][-1] do not
     exist and are not counted.
 
-    fused kernel (0): each inner solve makes iters + 1 passes over D, L and
+    fused kernel (2): each inner solve makes iters + 1 passes over D, L and
     D^-1; explicit kernel (1): iters passes over S (D, L) and Phi^-1 (D^-1,
     explicit sub-diagonal blocks M_k, full) plus one initial Phi^-1 pass.
     Every FP64 residual reads D and L in FP64 (or FP32 hi + FP32 lo); a zero
     start needs no residual before its first inner solve (the fused kernel),
     so there are `outer` residual sweeps, `outer + 1` for the explicit one.
+    cooperative kernel (3): the blocks are read once into LDS and stay there;
+    each FP64 residual reads only the FP32 lo parts (none under FP64 storage).
     """
     N = b.N.astype(np.float64)
     nx = b.nx.astype(np.float64)
@@ -65,7 +67,10 @@ def algorithmic_bytes(b, iters, outer, pc: str, precision: str, kernel: int = 0)
     e = 8.0 if precision == "fp64" else 4.0
     it = iters.astype(np.float64)
     st = outer.astype(np.float64)
-    if kernel == 0:
+    if kernel == 3:
+        lo = 0.0 if precision == "fp64" else 4.0
+        return e * (N * 2 * npk + (N - 1) * nn) + lo * st * (N * npk + (N - 1) * nn) + 16.0 * N * nx
+    if kernel == 2:
         inner = e * (N * 2 * npk + (N - 1) * nn) * (it + st)
         sweeps = st
     else:
@@ -117,7 +122,8 @@ def main() -> int:
     ap.add_argument("--precision", default=None, choices=[None, "fp64", "fp32", "fp32_refine64"])
     ap.add_argument("--threads", type=int, default=0)
     ap.add_argument("--lds", type=int, default=0)
-    ap.add_argument("--kernel", type=int, default=0, help="0 fused single sweep, 1 explicit two sweeps")
+    ap.add_argument("--kernel", type=int, default=0, help="0 automatic (fused; cooperative for one long problem), 1 explicit two sweeps, 2 fused, "
+                         "3 cooperative")
     ap.add_argument("--cpu-sample", type=int, default=512)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true")
@@ -130,6 +136,8 @@ def main() -> int:
                     help="keep the default mapping instead of timing candidates per state size first")
     ap.add_argument("--no-graph", dest="graph", action="store_false",
                     help="time eager launches only (default: also replay the step as a HIP graph)")
+    ap.add_argument("--stream-calib", type=int, default=0, metavar="MIB",
+                    help="print the read / write / copy rates of plain device kernels on MIB-sized buffers")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (counter calibration "
                          "and measured copy bandwidth), print one JSON line and exit")
@@ -148,6 +156,27 @@ def main() -> int:
     if not torch.cuda.is_available():
         print("bench.py: no GPU visible", file=sys.stderr)
         return 1
+    if args.stream_calib:
+        # practical streaming rates of plain device kernels: read (sum), write (fill), copy
+        n = args.stream_calib * (1 << 20) // 4
+        x = torch.ones(n, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        out = {}
+        for name, fn, moved in (("read", lambda: x.sum(), n * 4), ("write", lambda: y.fill_(1.0), n * 4),
+                                ("copy", lambda: y.copy_(x), 2 * n * 4)):
+            for _ in range(3):
+                fn()
+            best = float("inf")
+            for _ in range(10):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                fn()
+                e1.record()
+                torch.cuda.synchronize()
+                best = min(best, e0.elapsed_time(e1))
+            out[name + "_GBps"] = round(moved / best / 1e6, 1)
+        print(json.dumps({"stream_bytes": n * 4, **out}), flush=True)
+        return 0
     if args.copy_calib:
         n = args.copy_calib * (1 << 20) // 4
         x = torch.ones(n, dtype=torch.float32, device="cuda")
@@ -269,7 +298,8 @@ def main() -> int:
                   for r in runs.values()))
     if args.graph:
         ok = ok and all(r["graph_matches_eager"] for r in runs.values())
-    bytes_solve = float(algorithmic_bytes(b, res["iters"], res["outer"], args.pc, precision, args.kernel).sum())
+    kern, coop_w, coop_g = db.solver.solve_kernel()  # the kernel the solves ran: 1 explicit, 2 fused, 3 cooperative
+    bytes_solve = float(algorithmic_bytes(b, res["iters"], res["outer"], args.pc, precision, kern).sum())
     rec = MEASURED_TRAFFIC.get((args.workload, args.pc, precision, args.kernel))
     traffic = rec[1] if rec and rec[0] == solve_sources_hash() else None
     solve_avg_s = float(plain["solve_ms"].mean()) / 1e3
@@ -328,8 +358,9 @@ def main() -> int:
             "precision": precision,
             "tol": tol,
             "warm_start": "learned (per-knot network, zero fallback)" if head_mode == "learned" else "zero",
-            "kernel": "fused" if args.kernel == 0 else "explicit",
-            "mapping": [{"nx": m[0], "threads": m[1], "lds_bytes": m[2]} for m in mapping] if mapping else None,
+            "kernel": {1: "explicit", 2: "fused", 3: "cooperative"}[kern],
+            "mapping": ({"own_knots_per_workgroup": coop_w, "workgroups": coop_g} if kern == 3 else
+                        [{"nx": m[0], "threads": m[1], "lds_bytes": m[2]} for m in mapping] if mapping else None),
             "timing": "hipGraph replay of the whole step" if args.graph else "eager launches",
             "step": ("build (FP64 assembly) + network inference + solve" if head_mode == "learned"
                      else "build (FP64 assembly) + solve"),
@@ -343,13 +374,15 @@ def main() -> int:
             "compare": compare,
         },
         "roofline": {
-            "kernel": "k_pcg2" if args.kernel == 0 else "k_pcg",
+            "kernel": {1: "k_pcg", 2: "k_pcg2", 3: "k_coop"}[kern],
             "bound": "hbm",
             "achieved": round(achieved, 2),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
+            **({"note": "latency-bound: blocks stay in LDS, one grid-wide sum per PCG iteration"}
+               if kern == 3 else {}),
         },
         "cpu_baseline": cpu,
     }

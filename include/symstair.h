@@ -225,8 +225,8 @@ ssp_status ssp_gemm_f32(int32_t M, int32_t N, int32_t K, const float *A, int32_t
  * then solves the whole batch once, so the outputs (same meaning as in
  * ssp_solve, zero start, max_iter = 10 N nx) hold valid results.  It
  * synchronises the stream and must not be captured into a graph.
- * ssp_set_mapping clears the tuned choice.  Does nothing for the explicit
- * kernel. */
+ * ssp_set_mapping clears the tuned choice.  With nothing to tune (the
+ * explicit kernel, the cooperative solve) it only solves once. */
 ssp_status ssp_autotune(ssp_batch *b, double rel_tol, const double *gamma, double *lambda, int32_t *iters,
                         double *relres, int32_t *prob_status, void *stream);
 /* Set the fused kernel's mapping of the solve group with state size nx
@@ -242,6 +242,13 @@ ssp_status ssp_set_group_mapping(ssp_batch *b, int32_t nx, int32_t threads, int3
  * count goes to *ngroups. */
 ssp_status ssp_get_mapping(const ssp_batch *b, int32_t max_groups, int32_t *nx, int32_t *threads,
                            int32_t *lds_bytes, float *tuned_ms, int32_t *ngroups);
+
+/* The kernel the last ssp_solve (or ssp_autotune) of this batch enqueued:
+ * 1 explicit two-sweep, 2 fused (one workgroup per problem), 3 cooperative
+ * (one problem over the whole grid); 0 before any solve.  *W and *G (may be
+ * NULL) receive the cooperative plan: own knots per workgroup and
+ * workgroups (0 for the other kernels). */
+ssp_status ssp_solve_kernel(const ssp_batch *b, int32_t *kernel, int32_t *W, int32_t *G);
 
 /* Human-readable text of a call-level status, and of the last HIP error seen
  * by this thread (static storage, never NULL). */

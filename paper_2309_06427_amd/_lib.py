@@ -47,6 +47,7 @@ SIGNATURES = {
     "ssp_autotune": (C.c_int, [_vp, _d, _vp, _vp, _vp, _vp, _vp, _vp]),
     "ssp_set_group_mapping": (C.c_int, [_vp, _i32, _i32, _i32]),
     "ssp_get_mapping": (C.c_int, [_vp, _i32, _pi32, _pi32, _pi32, C.POINTER(_f), _pi32]),
+    "ssp_solve_kernel": (C.c_int, [_vp, _pi32, _pi32, _pi32]),
     "ssp_status_str": (C.c_char_p, [C.c_int]),
     "ssp_last_error": (C.c_char_p, []),
 }

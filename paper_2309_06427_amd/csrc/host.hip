@@ -515,11 +515,14 @@ ssp_status ssp_solve(ssp_batch *b, double rel_tol, int32_t max_iter, const doubl
         const int c0 = ssp::coop_clear_first();
         SSP_HIP(ssp::launch_fill_i32((int32_t *)b->dbar + c0, 0, ssp::coop_flag_words(b->N[0]) - c0, s));
         SSP_HIP(ssp::launch_coop(a, b->dbar, b->drec, b->dwtag, b->nx[0], b->coop_W, b->coop_G, b->fp32, s));
+        b->last_kernel = 3;
         return SSP_OK;
     }
     if (b->kernel != 1 && fused_ok(b)) {
+        b->last_kernel = 2;
         return launch_groups(b, a, -1, s);
     } else {
+        b->last_kernel = 1;
         // explicit stored stair blocks (also the fallback when a knot does not
         // fit the fused kernel's registers or LDS)
         if (b->pc != SSP_PC_BLOCK_JACOBI) {
@@ -565,8 +568,8 @@ ssp_status ssp_autotune(ssp_batch *b, double rel_tol, const double *gamma, doubl
                         double *relres, int32_t *prob_status, void *stream) {
     if (!b || !gamma || !lambda || !iters || !relres || !prob_status || !(rel_tol >= 0.0)) return SSP_ERR_ARG;
     if (!b->built) return SSP_ERR_STATE;
-    if (b->kernel == 1 || !fused_ok(b) || use_coop(b))
-        return SSP_OK;  // only the batched fused kernel has a mapping to tune
+    if (b->kernel == 1 || !fused_ok(b) || use_coop(b))  // only the batched fused kernel has a mapping to tune
+        return ssp_solve(b, rel_tol, 0, gamma, lambda, 0, iters, relres, prob_status, stream);
     DevGuard dg(b->device);
     hipStream_t s = (hipStream_t)stream;
     int32_t *st0 = nullptr;
@@ -660,6 +663,14 @@ ssp_status ssp_get_mapping(const ssp_batch *b, int32_t max_groups, int32_t *nx, 
         if (lds_bytes) lds_bytes[i] = l;
         if (tuned_ms) tuned_ms[i] = b->groups[i].tuned_ms;
     }
+    return SSP_OK;
+}
+
+ssp_status ssp_solve_kernel(const ssp_batch *b, int32_t *kernel, int32_t *W, int32_t *G) {
+    if (!b || !kernel) return SSP_ERR_ARG;
+    *kernel = b->last_kernel;
+    if (W) *W = b->last_kernel == 3 ? b->coop_W : 0;
+    if (G) *G = b->last_kernel == 3 ? b->coop_G : 0;
     return SSP_OK;
 }
 

@@ -87,6 +87,13 @@ class BatchSolver:
                                 C.byref(n)), "ssp_get_mapping")
         return [(int(nx[i]), int(th[i]), int(lds[i]), float(ms[i])) for i in range(k)]
 
+    def solve_kernel(self) -> tuple:
+        """(kernel, W, G) of the last solve: 1 explicit, 2 fused, 3 cooperative
+        (W own knots per workgroup, G workgroups; 0 otherwise)."""
+        k, w, g = C.c_int32(), C.c_int32(), C.c_int32()
+        check(_lib.load().ssp_solve_kernel(self._h, C.byref(k), C.byref(w), C.byref(g)), "ssp_solve_kernel")
+        return int(k.value), int(w.value), int(g.value)
+
     def solve_outer(self, outer, stream=None):
         check(_lib.load().ssp_solve_outer(self._h, _ptr(outer), _stream(stream)), "ssp_solve_outer")
 

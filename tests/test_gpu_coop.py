@@ -162,6 +162,27 @@ def test_coop_warm_starts():
     np.testing.assert_array_equal(out["lam"], cold["lam"])
 
 
+def test_solve_kernel_reports_the_path():
+    from paper_2309_06427_amd import solver
+    b = _one(100, 14, 7, seed=9)
+    db = solver.DeviceBatch(b)
+    assert db.solver.solve_kernel() == (0, 0, 0)
+    db.build("sym", "fp32_refine64")
+    db.solve(1e-6)
+    k, W, G = db.solver.solve_kernel()
+    assert k == 3 and 2 <= W <= 4 and G == -(-100 // W)
+    db.solver.set_mapping(256, 0, 2)
+    db.solve(1e-6)
+    assert db.solver.solve_kernel() == (2, 0, 0)
+    db.solver.set_mapping(256, 0, 1)
+    db.solve(1e-6)
+    assert db.solver.solve_kernel() == (1, 0, 0)
+    short = solver.DeviceBatch(_one(10, 6, 3, seed=1))  # below the automatic threshold
+    short.build("sym", "fp64")
+    short.solve(1e-8)
+    assert short.solver.solve_kernel()[0] == 2
+
+
 def test_coop_is_deterministic():
     b = _one(300, 26, 13, seed=5)
     a = _solve(b, "sym", "fp32_refine64", 1e-6)
