@@ -219,7 +219,7 @@ ssp_status launch_groups(ssp_batch *b, ssp::SolveArgs a, int which, hipStream_t 
         ssp::SolveArgs ga = a;
         ga.order = b->dgorder + g.offset;
         ga.lds_bytes = l;
-        SSP_HIP(ssp::launch_pcg2(ga, g.count, b->fp32, t, fork ? b->gstreams[i] : s));
+        SSP_HIP(ssp::launch_pcg2(ga, g.count, b->fp32, t, g.nx, fork ? b->gstreams[i] : s));
     }
     if (fork) {
         for (int i = 0; i < ng; ++i) {

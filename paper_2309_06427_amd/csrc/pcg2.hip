@@ -761,7 +761,9 @@ __device__ __forceinline__ Outcome solve_problem(const SolveArgs &a, const Prob<
     return o;
 }
 
-template <typename TI, int BLOCK>
+// One launch per solve group; NX > 0: every problem of the launch has state
+// size NX (compiled in), NX = 0: any state size.
+template <typename TI, int BLOCK, int NX>
 __global__ __launch_bounds__(BLOCK, 2) void k_pcg2(SolveArgs a) {
     using TM = TI;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -769,7 +771,7 @@ __global__ __launch_bounds__(BLOCK, 2) void k_pcg2(SolveArgs a) {
     __shared__ TI redT[3 * (BLOCK / kWave)];
     const int tid = threadIdx.x;
     const int p = a.order[blockIdx.x];
-    const int N = a.N[p], nx = a.nx[p];
+    const int N = a.N[p], nx = NX > 0 ? NX : a.nx[p];
     const int n = N * nx;
     const int64_t ob = a.off_blk[p], ov = a.off_v[p];
     Prob<TI> q;
@@ -822,14 +824,7 @@ __global__ __launch_bounds__(BLOCK, 2) void k_pcg2(SolveArgs a) {
     } else if (gg == 0.0) {
         for (int row = tid; row < n; row += BLOCK) q.lam[row] = 0.0;
     } else {
-        // state sizes with a compiled-in specialisation; others use the runtime path
-        switch (nx) {
-            case 6: o = solve_problem<TI, BLOCK, 6>(a, q, nx, smem_raw, red64, redT); break;
-            case 14: o = solve_problem<TI, BLOCK, 14>(a, q, nx, smem_raw, red64, redT); break;
-            case 26: o = solve_problem<TI, BLOCK, 26>(a, q, nx, smem_raw, red64, redT); break;
-            case 36: o = solve_problem<TI, BLOCK, 36>(a, q, nx, smem_raw, red64, redT); break;
-            default: o = solve_problem<TI, BLOCK, 0>(a, q, nx, smem_raw, red64, redT); break;
-        }
+        o = solve_problem<TI, BLOCK, NX>(a, q, nx, smem_raw, red64, redT);
     }
     if (tid == 0) {
         a.iters[p] = o.total;
@@ -866,38 +861,50 @@ int pcg2_lds(int nx_max, bool fp32, int threads) {
     return bytes;
 }
 
-template <typename TI, int BLOCK>
+template <typename TI, int BLOCK, int NX>
 static hipError_t launch2_t(const SolveArgs &a, int nprob, hipStream_t s) {
     // all the LDS a workgroup may have is allowed once; each launch asks for
     // its own size (launches of other sizes may be in flight on other streams)
     static int allowed = 0;
+    const void *f = (const void *)k_pcg2<TI, BLOCK, NX>;
     if (allowed == 0) {
         hipFuncAttributes fa;
-        hipError_t e = hipFuncGetAttributes(&fa, (const void *)k_pcg2<TI, BLOCK>);
+        hipError_t e = hipFuncGetAttributes(&fa, f);
         if (e != hipSuccess) return e;
         const int cap = 160 * 1024 - (int)fa.sharedSizeBytes;
-        e = hipFuncSetAttribute((const void *)k_pcg2<TI, BLOCK>, hipFuncAttributeMaxDynamicSharedMemorySize, cap);
+        e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, cap);
         if (e != hipSuccess) return e;
         allowed = cap;
     }
     if (a.lds_bytes > allowed) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_pcg2<TI, BLOCK>), dim3(nprob), dim3(BLOCK), a.lds_bytes, s, a);
+    hipLaunchKernelGGL((k_pcg2<TI, BLOCK, NX>), dim3(nprob), dim3(BLOCK), a.lds_bytes, s, a);
     return hipGetLastError();
+}
+
+template <typename TI, int BLOCK>
+static hipError_t launch2_nx(const SolveArgs &a, int nprob, int nx, hipStream_t s) {
+    switch (nx) {  // state sizes with a compiled-in specialisation; others use the runtime path
+        case 6: return launch2_t<TI, BLOCK, 6>(a, nprob, s);
+        case 14: return launch2_t<TI, BLOCK, 14>(a, nprob, s);
+        case 26: return launch2_t<TI, BLOCK, 26>(a, nprob, s);
+        case 36: return launch2_t<TI, BLOCK, 36>(a, nprob, s);
+        default: return launch2_t<TI, BLOCK, 0>(a, nprob, s);
+    }
 }
 
 bool pcg2_threads_ok(int threads) { return threads == 128 || threads == 256; }
 
-hipError_t launch_pcg2(const SolveArgs &a, int nprob, bool fp32, int threads, hipStream_t s) {
+hipError_t launch_pcg2(const SolveArgs &a, int nprob, bool fp32, int threads, int nx, hipStream_t s) {
     if (nprob == 0) return hipSuccess;
     if (fp32) {
         switch (threads) {
-            case 128: return launch2_t<float, 128>(a, nprob, s);
-            case 256: return launch2_t<float, 256>(a, nprob, s);
+            case 128: return launch2_nx<float, 128>(a, nprob, nx, s);
+            case 256: return launch2_nx<float, 256>(a, nprob, nx, s);
         }
     } else {
         switch (threads) {
-            case 128: return launch2_t<double, 128>(a, nprob, s);
-            case 256: return launch2_t<double, 256>(a, nprob, s);
+            case 128: return launch2_nx<double, 128>(a, nprob, nx, s);
+            case 256: return launch2_nx<double, 256>(a, nprob, nx, s);
         }
     }
     return hipErrorInvalidValue;

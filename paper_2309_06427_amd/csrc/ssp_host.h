@@ -96,7 +96,7 @@ hipError_t launch_coop(const SolveArgs &a, unsigned *flags, unsigned long long *
 constexpr int kFusedLdsCap = 160 * 1024 - 256;
 
 // Fused single-sweep PCG with the preconditioner applied from D^-1 and S.
-hipError_t launch_pcg2(const SolveArgs &a, int nprob, bool fp32, int threads, hipStream_t s);
+hipError_t launch_pcg2(const SolveArgs &a, int nprob, bool fp32, int threads, int nx, hipStream_t s);
 int pcg2_lds(int nx_max, bool fp32, int threads);  // 0 if the mapping cannot hold one knot
 // Knots per step the fused kernel uses for state size nx (< 1: cannot run).
 int pcg2_steps_for(int nx, bool fp32, int threads, int lds_bytes);
