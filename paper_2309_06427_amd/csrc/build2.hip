@@ -104,10 +104,10 @@ __device__ __forceinline__ bool gj_inverse(double (&a)[NX], int i, bool row, int
                     a[j] = j == k ? inv : pr[j] * inv;
                 });
             } else {
-                const double f = a[k];
+                const double g = a[k] * inv;  // row multiple of the unscaled pivot row
                 static_for<0, NX>([&](auto jc) {
                     constexpr int j = decltype(jc)::value;
-                    a[j] = j == k ? -f * inv : a[j] - f * (pr[j] * inv);
+                    a[j] = j == k ? -g : fma(-g, pr[j], a[j]);
                 });
             }
         }
