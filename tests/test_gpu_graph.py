@@ -85,3 +85,31 @@ def test_graph_with_warm_start_matches_eager():
         out = db.results()
         for k in ("lam", "iters", "relres", "status", "outer"):
             assert np.array_equal(out[k], ref[k]), (rep, k)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_refine64"])
+def test_graph_replays_cooperative_solve(prec):
+    """A single long problem (the cooperative kernel: tagged cross-workgroup
+    records and a tag counter that carries across launches) replays from a
+    graph to the eager bits, with eager solves of the same batch between."""
+    from paper_2309_06427_amd import solver
+    b = inputs.pack([inputs.draw_problem(np.random.default_rng(21), 300, 26, 13)])
+    db = solver.DeviceBatch(b)
+
+    def step():
+        db.build("sym", prec)
+        db.solve(1e-6)
+
+    step()
+    ref = db.results()
+    assert db.solver.solve_kernel()[0] == 3 and ref["status"][0] & ~16 == 0
+    g = _capture(step)
+    for rep in range(3):
+        db.build("add", prec)
+        db.solve(1e-6)
+        assert db.results()["status"][0] & ~16 == 0
+        db.lam.fill_(5.0)
+        g.replay()
+        out = db.results()
+        for k in ("lam", "iters", "relres", "status", "outer"):
+            assert np.array_equal(out[k], ref[k]), (rep, k)
