@@ -23,6 +23,7 @@ namespace ssp {
 namespace {
 
 constexpr int kThreads = 128;
+constexpr int kGjBlock = 2;  // pivots per LDS exchange of the Gauss-Jordan inverses
 
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 
@@ -110,6 +111,105 @@ __device__ __forceinline__ bool gj_inverse(double (&a)[NX], int i, bool row, int
                     a[j] = j == k ? -g : fma(-g, pr[j], a[j]);
                 });
             }
+        }
+    });
+    return ok;
+}
+
+// The same inverse with BK pivots per exchange: the pivot lanes of a block
+// k0 .. k0+bk-1 publish their rows in LDS once; every lane inverts the bk x bk
+// pivot block B itself (Gauss-Jordan on scalars, the same pivots as the
+// one-at-a-time elimination, checked for positivity) and applies the whole
+// block: a non-pivot row becomes a - c P with c = a_K B^-1 (P: the pivot
+// rows, K: the block's columns, which become -c), pivot row m becomes
+// (B^-1 P)_m (its K columns (B^-1)_m), written as a - g P with
+// g = e_m - (B^-1)_m since a = P_m.  M: the knot's LDS buffer, whose first
+// BK rows hold the pivot rows.  Returns false if a pivot is not positive.
+template <int NX, int BK>
+__device__ __forceinline__ bool gj_inverse_blocked(double (&a)[NX], int i, bool row, int n, double *M) {
+    constexpr int NP = Lane<NX>::NP;
+    bool ok = true;
+    static_for<0, (NX + BK - 1) / BK>([&](auto bc) {
+        constexpr int k0 = decltype(bc)::value * BK;
+        constexpr int bk = NX - k0 < BK ? NX - k0 : BK;
+        if (k0 < n) {
+            const int me = (row && i >= k0 && i < k0 + bk && i < n) ? i - k0 : -1;
+            if (me >= 0) lds_put_row<NX>(M + me * NP, a);
+            wave_sync();
+            // B^-1 of the valid part of the block (m < n - k0); the rest acts as identity
+            double B[bk][bk];
+            static_for<0, bk>([&](auto mc) {
+                constexpr int m = decltype(mc)::value;
+                static_for<0, bk>([&](auto qc) {
+                    constexpr int q = decltype(qc)::value;
+                    const bool v = k0 + m < n && k0 + q < n;
+                    B[m][q] = v ? M[m * NP + k0 + q] : (m == q ? 1.0 : 0.0);
+                });
+            });
+            static_for<0, bk>([&](auto pc) {
+                constexpr int pv = decltype(pc)::value;
+                if (!(B[pv][pv] > 0.0)) ok = false;
+                const double inv = 1.0 / B[pv][pv];
+                static_for<0, bk>([&](auto qc) {
+                    constexpr int q = decltype(qc)::value;
+                    B[pv][q] = q == pv ? inv : B[pv][q] * inv;
+                });
+                static_for<0, bk>([&](auto mc) {
+                    constexpr int m = decltype(mc)::value;
+                    if (m != pv) {
+                        const double f = B[m][pv];
+                        static_for<0, bk>([&](auto qc) {
+                            constexpr int q = decltype(qc)::value;
+                            B[m][q] = q == pv ? -f * inv : fma(-f, B[pv][q], B[m][q]);
+                        });
+                    }
+                });
+            });
+            // g: c = a_K B^-1 for a non-pivot row, e_me - (B^-1)_me for pivot row me
+            double g[bk], kc[bk];
+            static_for<0, bk>([&](auto mc) {
+                constexpr int m = decltype(mc)::value;
+                double c = 0.0;
+                static_for<0, bk>([&](auto qc) {
+                    constexpr int q = decltype(qc)::value;
+                    c = fma(a[k0 + q], B[q][m], c);
+                });
+                double bm = 0.0;  // (B^-1)[me][m]
+                static_for<0, bk>([&](auto qc) {
+                    constexpr int q = decltype(qc)::value;
+                    if (me == q) bm = B[q][m];
+                });
+                g[m] = me >= 0 ? ((me == m ? 1.0 : 0.0) - bm) : c;
+                kc[m] = me >= 0 ? bm : -c;  // the new K column m of this row
+                if (k0 + m >= n) g[m] = 0.0;
+            });
+            // a_j -= sum_m g_m P_mj outside the block's columns, read two entries at a time
+            static_for<0, NX / 2>([&](auto hc) {
+                constexpr int j = 2 * decltype(hc)::value;
+                double s0 = a[j], s1 = a[j + 1];
+                static_for<0, bk>([&](auto mc) {
+                    constexpr int m = decltype(mc)::value;
+                    const f64x2 v = *(const f64x2 *)(M + m * NP + j);
+                    s0 = fma(-g[m], v.x, s0);
+                    s1 = fma(-g[m], v.y, s1);
+                });
+                a[j] = s0;
+                a[j + 1] = s1;
+            });
+            if constexpr (NX % 2) {
+                constexpr int j = NX - 1;
+                double s0 = a[j];
+                static_for<0, bk>([&](auto mc) {
+                    constexpr int m = decltype(mc)::value;
+                    s0 = fma(-g[m], M[m * NP + j], s0);
+                });
+                a[j] = s0;
+            }
+            static_for<0, bk>([&](auto mc) {
+                constexpr int m = decltype(mc)::value;
+                if (k0 + m < n) a[k0 + m] = kc[m];
+            });
+            wave_sync();  // the pivot rows are read before the next block's are written
         }
     });
     return ok;
@@ -229,13 +329,13 @@ __global__ __launch_bounds__(kThreads) void k_build_inv_nx(BuildArgs a, const in
     double r[NX];
     const int64_t oq = a.off_nn[p] + (int64_t)ln.knot * nn + ln.i * NX;
     if (ln.row) load_row<NX>(a.Q + oq, NX, r);
-    ok = gj_inverse<NX>(r, ln.i, ln.row, NX, M) && ok;
+    ok = gj_inverse_blocked<NX, kGjBlock>(r, ln.i, ln.row, NX, M) && ok;
     if (ln.row) store_row<NX>(a.Qinv + oq, NX, r);
     if (nu > 0) {
         const bool rrow = ln.row && ln.knot < N - 1 && ln.i < nu;
         const int64_t orr = a.off_uu[p] + (int64_t)ln.knot * nu * nu + ln.i * nu;
         if (rrow) load_row<NX>(a.R + orr, nu, r);
-        const bool okr = gj_inverse<NX>(r, ln.i, rrow, nu, M);
+        const bool okr = gj_inverse_blocked<NX, kGjBlock>(r, ln.i, rrow, nu, M);
         if (ln.knot < N - 1) ok = okr && ok;
         if (rrow) store_row<NX>(a.Rinv + orr, nu, r);
     }
@@ -292,7 +392,7 @@ __global__ __launch_bounds__(kThreads) void k_build_asm_nx(BuildArgs a, const in
     }
     symmetrise<NX>(d, i, ln.row, M);  // exactly symmetric before the upper triangle is kept
     if (ln.row) store_split_packed_row<TM, NX>(blk, a.SDlo ? a.SDlo + od : nullptr, i, d);
-    const bool ok = gj_inverse<NX>(d, i, ln.row, NX, M);
+    const bool ok = gj_inverse_blocked<NX, kGjBlock>(d, i, ln.row, NX, M);
     symmetrise<NX>(d, i, ln.row, M);
     if (ln.row) store_split_packed_row<TM, NX>(blk + bp + bs, (float *)nullptr, i, d);
     if (ln.row && !ok) atomicOr(a.status + p, kNotSpd);
