@@ -214,3 +214,26 @@ def test_autotune_keeps_results_valid_and_reports_a_mapping():
         st, lam = oracle.direct(D, L, pr["gamma"])
         err = np.linalg.norm(seg(b, out["lam"], p) - lam) / np.linalg.norm(lam)
         assert err < 1e-3, (p, err)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_refine64"])
+def test_not_spd_detected_in_compiled_state_sizes(prec):
+    """The register-resident assembly (nx in {6, 14, 26}) flags a Q_k or R_k
+    with a non-positive pivot anywhere in its blocked elimination, like the
+    oracle; the other problems of the batch are unaffected."""
+    rng = np.random.default_rng
+    probs = []
+    for s, nx in enumerate((6, 14, 26, 6, 14, 26, 26)):
+        probs.append(inputs.draw_problem(rng(40 + s), 9, nx, nx // 2))
+    probs[0]["Q"][3][2, 2] = -1.0                  # a negative diagonal inside a pivot block
+    probs[1]["Q"][0] = -np.eye(14)                 # indefinite first knot
+    probs[2]["R"][5][12, 12] = -5.0                # indefinite control cost, last row of R_k
+    probs[3]["Q"][8] = np.zeros((6, 6))            # singular last knot
+    probs[4]["R"][2][0, 0] = 0.0                   # zero pivot at the start of R_k
+    b = inputs.pack(probs)
+    out = solve_gpu(b, "sym", prec, 1e-8 if prec == "fp64" else 1e-6)
+    ref = oracle.solve_batch(b, "sym", prec, tol=1e-8 if prec == "fp64" else 1e-6)
+    assert list(out["status"][:5]) == [1, 1, 1, 1, 1] == list(ref["status"][:5])
+    assert (out["status"][5:] & ~16 == 0).all() and list(ref["status"][5:]) == [0, 0]
+    for p in range(5):
+        assert not seg(b, out["lam"], p).any() and np.isnan(out["relres"][p])
