@@ -243,7 +243,11 @@ __global__ __launch_bounds__(kCoopThreads) void k_coop(CoopArgs ca) {
         TM *dst = base(q);
         for (int t = threadIdx.x; t < cnt; t += blockDim.x) dst[t] = src[t];
     }
+    // a workgroup that starts after another one has already given up (the
+    // launch has failed) publishes nothing, so no stale tag can outlive it
+    if (threadIdx.x == 0) s_ok = get(ca.flags + kErr) == 0u;
     __syncthreads();
+    const bool started_ok = s_ok != 0;
     const TM *Dk = base(sl), *Lk = Lof(sl), *Dik = Diof(sl);
     const TM *Lk1 = sl + 1 < S ? Lof(sl + 1) : nullptr;  // L_{k+1}
     TM rdi[RN], rd[RN], rl0[RN], rl1[RN];
@@ -365,15 +369,15 @@ __global__ __launch_bounds__(kCoopThreads) void k_coop(CoopArgs ca) {
             if (a.use_lambda0 == 1 && !isfinite(get(lam + e))) bad = 1.0;
             if (a.use_lambda0 == 0) put(lam + e, 0.0);
         }
-        double t[3];
-        alive = grid_sum3(gg, bad, 0.0, t, false, nullptr, wdummy);
+        double t[3] = {0.0, 0.0, 0.0};
+        alive = started_ok && grid_sum3(gg, bad, 0.0, t, false, nullptr, wdummy);
         gnorm = sqrt(t[0]);
         if (st == kOk && (!isfinite(gnorm) || t[1] != 0.0)) {
             st = kNonFinite;
             rnorm = NAN;
         }
     }
-    if (st == kOk && gnorm == 0.0) {
+    if (st == kOk && alive && gnorm == 0.0) {
         if (own) put(lam + e, 0.0);
     } else if (st == kOk && alive) {
         const int max_iter = a.max_iter > 0 ? a.max_iter : 10 * n;
