@@ -354,3 +354,44 @@ def test_batch_driver_matches_single_calls():
         _, lam, it = oracle.pcg(*built(p, "sym"), p["gamma"], tol=1e-9)
         assert it == res["iters"][i]
         assert np.array_equal(lam, res["lam"][b.off_v[i]:b.off_v[i + 1]])
+
+
+def test_refinement_falls_back_to_block_jacobi_after_a_float_breakdown():
+    """On an ill-conditioned problem (kappa(Q_k) up to 1e6) the float symmetric
+    stair loses definiteness: alone it breaks down, while the FP64 operator
+    converges.  Under refinement the oracle then goes on with block-Jacobi
+    (status bit PC_FALLBACK) and reaches the FP64 tolerance, which block-Jacobi
+    from the start also does, in more iterations."""
+    from paper_2309_06427_amd import inputs
+    # problem 226 of the kappa(Q) <= 1e6 workload (1024 x N=128, nx=26, nu=12, seed 3), drawn alone
+    child = np.random.SeedSequence(3).spawn(1024)[226]
+    b = inputs.pack([inputs.draw_problem(np.random.default_rng(child), 128, 26, 12, "logcond", 1e6)])
+    p = b.problem(0)
+    st, D, L, Di, M = oracle.build(p["A"], p["B"], p["Q"], p["R"], "sym")
+    assert st == oracle.OK
+    assert oracle.pcg(D, L, Di, M, p["gamma"], tol=1e-6)[0] == oracle.OK       # FP64: fine
+    assert oracle.pcg_mixed(D, L, Di, M, p["gamma"], tol=1e-6, refine=False)[0] == oracle.BREAKDOWN
+    st, lam, iters, outer = oracle.pcg_mixed(D, L, Di, M, p["gamma"], tol=1e-6, refine=True)
+    assert st == oracle.PC_FALLBACK and oracle.relres(D, L, p["gamma"], lam) <= 1e-6
+    st_bj, lam_bj, it_bj, _ = oracle.pcg_mixed(D, L, Di, np.zeros_like(M), p["gamma"], tol=1e-6, refine=True)
+    assert st_bj == oracle.OK and it_bj > iters
+    # the batch driver reports the same
+    r = oracle.solve_batch(b, "sym", "fp32_refine64", tol=1e-6)
+    assert r["status"][0] == oracle.PC_FALLBACK and r["relres"][0] <= 1e-6
+
+
+def test_warm_start_fallback_gives_the_cold_solve():
+    """A start whose residual is not below ||gamma|| is dropped for zero
+    (status bit WARM_FALLBACK) and the solve is then the cold one, bit for
+    bit; a start at the solution takes no iterations and no fallback."""
+    from paper_2309_06427_amd import inputs
+    b = inputs.batch(5, seed=12, N_range=(10, 40), nx_choices=(6, 14))
+    cold = oracle.solve_batch(b, "sym", "fp32_refine64", tol=1e-6)
+    bad = 1e3 * np.random.default_rng(1).standard_normal(b.gamma.shape[0])
+    warm = oracle.solve_batch(b, "sym", "fp32_refine64", tol=1e-6, lam0=bad, fallback=True)
+    assert (warm["status"] == oracle.WARM_FALLBACK).all()
+    np.testing.assert_array_equal(warm["lam"], cold["lam"])
+    np.testing.assert_array_equal(warm["iters"], cold["iters"])
+    exact = oracle.solve_batch(b, "sym", "fp64", tol=1e-13)
+    good = oracle.solve_batch(b, "sym", "fp32_refine64", tol=1e-6, lam0=exact["lam"], fallback=True)
+    assert (good["status"] == 0).all() and (good["iters"] == 0).all()
