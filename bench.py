@@ -27,7 +27,7 @@ HBM_PEAK_GBS = 8000.0
 # WRITE_SIZE (KiB per dispatch), each scaled by what the counter reads for a
 # plain copy of known size (2.0 and 1.0), keyed by the workload/settings and by
 # a hash of the kernel's sources: a changed kernel reports null.
-SOLVE_SOURCES = ("pcg2.hip", "ssp_device.h", "ssp_sweep.h", "ssp_host.h")
+SOLVE_SOURCES = ("pcg2.hip", "ssp_device.h", "ssp_sweep.h", "ssp_host.h", "host.hip")
 MEASURED_TRAFFIC = {
     # (workload, pc, precision, kernel): (sources sha256[:16], bytes of one solve, all its dispatches)
     ("batch4096_ragged", "sym", "fp32_refine64", 0):
