@@ -103,6 +103,22 @@ ssp_status ssp_build(ssp_batch *b, ssp_precon pc, ssp_precision prec, const doub
                      const double *B, const double *Q, const double *R, int32_t *prob_status,
                      void *stream);
 
+/* Build from a symmetric block-tridiagonal matrix given by its blocks
+ * instead of the per-knot dynamics: D holds S[k][k] (k = 0..N-1) and Lsub
+ * holds S[k][k-1] (k = 1..N-1; block 0 is not read), both device FP64,
+ * nx x nx row-major blocks at the problem's off_nn offsets of ssp_layout
+ * (the layout of Q).  Each D_k is used as (D_k + D_k^T) / 2.  Stores S,
+ * D_k^-1 and the preconditioner pc (Sec. II-C, III, IV) in the precision of
+ * prec exactly as ssp_build does after assembling S, so ssp_solve,
+ * ssp_export and the warm start work on the result unchanged.
+ * prob_status: device int32[nprob], overwritten with SSP_P_OK or
+ * SSP_P_NOT_SPD (some D_k is not positive definite).  Every D_k of an SPD S
+ * is SPD, but not conversely: an S that is not SPD with SPD diagonal blocks
+ * passes here and ssp_solve reports what its iteration meets (typically
+ * SSP_P_BREAKDOWN or SSP_P_MAXITER). */
+ssp_status ssp_build_from_blocks(ssp_batch *b, ssp_precon pc, ssp_precision prec, const double *D,
+                                 const double *Lsub, int32_t *prob_status, void *stream);
+
 /* Solve S lambda = gamma for every problem with PCG (Sec. II-B) to
  * ||gamma - S lambda||_2 <= rel_tol * ||gamma||_2, using the preconditioner
  * and precision of the last ssp_build.

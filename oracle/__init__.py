@@ -48,6 +48,8 @@ def lib():
         ip = C.POINTER(C.c_int)
         L.ssp_oracle_build.argtypes = [i, i, i, d, d, d, d, i, d, d, d, d]
         L.ssp_oracle_build.restype = i
+        L.ssp_oracle_precond.argtypes = [i, i, i, d, d, d, d]
+        L.ssp_oracle_precond.restype = i
         L.ssp_oracle_btmv.argtypes = [i, i, d, d, d, d]
         L.ssp_oracle_pcg.argtypes = [i, i, d, d, d, d, d, C.c_double, i, d, ip]
         L.ssp_oracle_pcg.restype = i
@@ -88,6 +90,19 @@ def build(A, B, Q, R, pc: str = "sym"):
     st = lib().ssp_oracle_build(N, nx, nu, _dp(A), _dp(B), _dp(Q), _dp(R), PC[pc],
                                 _dp(D), _dp(L), _dp(Di), _dp(M))
     return st, D, L, Di, M
+
+
+def precond(D, L, pc: str = "sym"):
+    """Preconditioner of a block-tridiagonal S given by blocks (N, nx, nx):
+    D[k] = S[k][k], L[k] = S[k][k-1] (L[0] unused), with D[k] taken as
+    (D[k] + D[k]^T) / 2.  Returns (status, Dinv, M) with M[k] = Phi^-1[k][k-1].
+    """
+    D, L = map(_f64, (D, L))
+    D = _f64(0.5 * (D + D.transpose(0, 2, 1)))
+    N, nx = D.shape[0], D.shape[1]
+    Di, M = np.zeros((N, nx, nx)), np.zeros((N, nx, nx))
+    st = lib().ssp_oracle_precond(N, nx, PC[pc], _dp(D), _dp(L), _dp(Di), _dp(M))
+    return st, Di, M
 
 
 def btmv(Dg, Sb, x):

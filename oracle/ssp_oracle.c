@@ -124,6 +124,36 @@ static void matmul(int m, int k, int n, const double *X, const double *Y, int ty
 
 /* ---------------------------------------------------------------- build --- */
 
+/* The preconditioner of a block-tridiagonal S given by its diagonal blocks D
+ * and sub-diagonal blocks L (N blocks nx x nx each, L[0] unused): Dinv =
+ * D_k^-1 (Eq. jacobi; also the diagonal blocks of both stair forms) and
+ * M = Phi^-1[k][k-1] (Eq. stair_inv and the Sec. IV form; zero for
+ * block-Jacobi, M[0] = 0).  Returns OR_NOT_SPD if some D_k is not SPD. */
+int ssp_oracle_precond(int N, int nx, int pc, const double *D, const double *L, double *Dinv, double *M) {
+    const size_t nn = (size_t)nx * nx;
+    double *T1 = malloc(sizeof(double) * nn), *T2 = malloc(sizeof(double) * nn);
+    int st = OR_OK;
+
+    /* D_k^-1: block-Jacobi inverse and the diagonal of both stair forms */
+    for (int k = 0; k < N && st == OR_OK; ++k)
+        if (spd_inv(nx, D + k * nn, Dinv + k * nn)) st = OR_NOT_SPD;
+
+    /* sub-diagonal blocks of Phi^-1 (Eq. stair_inv and the Sec. IV form) */
+    if (st == OR_OK) {
+        memset(M, 0, sizeof(double) * nn);
+        for (int k = 1; k < N; ++k) {
+            double *Mk = M + k * nn;
+            if (pc == OR_PC_BJ) { memset(Mk, 0, sizeof(double) * nn); continue; }
+            matmul(nx, nx, nx, Dinv + k * nn, L + k * nn, 0, T1);       /* D_k^-1 L_k */
+            matmul(nx, nx, nx, T1, Dinv + (k - 1) * nn, 0, T2);         /* ... D_{k-1}^-1 */
+            double scale = (pc == OR_PC_ADD) ? -0.5 : -1.0;
+            for (size_t e = 0; e < nn; ++e) Mk[e] = scale * T2[e];
+        }
+    }
+    free(T1); free(T2);
+    return st;
+}
+
 /* Assemble S (D, L) and the preconditioner (Dinv, M) of one problem.
  * A, Q: N blocks nx x nx; B: N blocks nx x nu; R: N blocks nu x nu.
  * D, L, Dinv, M: N blocks nx x nx each (L[0] = M[0] = 0).
@@ -164,22 +194,7 @@ int ssp_oracle_build(int N, int nx, int nu, const double *A, const double *B, co
         }
     }
 
-    /* D_k^-1: block-Jacobi inverse and the diagonal of both stair forms */
-    for (int k = 0; k < N && st == OR_OK; ++k)
-        if (spd_inv(nx, D + k * nn, Dinv + k * nn)) st = OR_NOT_SPD;
-
-    /* sub-diagonal blocks of Phi^-1 (Eq. stair_inv and the Sec. IV form) */
-    if (st == OR_OK) {
-        memset(M, 0, sizeof(double) * nn);
-        for (int k = 1; k < N; ++k) {
-            double *Mk = M + k * nn;
-            if (pc == OR_PC_BJ) { memset(Mk, 0, sizeof(double) * nn); continue; }
-            matmul(nx, nx, nx, Dinv + k * nn, L + k * nn, 0, T1);       /* D_k^-1 L_k */
-            matmul(nx, nx, nx, T1, Dinv + (k - 1) * nn, 0, T2);         /* ... D_{k-1}^-1 */
-            double scale = (pc == OR_PC_ADD) ? -0.5 : -1.0;
-            for (size_t e = 0; e < nn; ++e) Mk[e] = scale * T2[e];
-        }
-    }
+    if (st == OR_OK) st = ssp_oracle_precond(N, nx, pc, D, L, Dinv, M);
     free(Qinv); free(Rinv); free(T1); free(T2); free(BR);
     return st;
 }

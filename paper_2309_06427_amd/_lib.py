@@ -28,6 +28,7 @@ SIGNATURES = {
     "ssp_batch_destroy": (C.c_int, [_vp]),
     "ssp_layout": (C.c_int, [_vp, _pi64, _pi64, _pi64, _pi64]),
     "ssp_build": (C.c_int, [_vp, C.c_int, C.c_int, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "ssp_build_from_blocks": (C.c_int, [_vp, C.c_int, C.c_int, _vp, _vp, _vp, _vp]),
     "ssp_solve": (C.c_int, [_vp, _d, _i32, _vp, _vp, C.c_int, _vp, _vp, _vp, _vp]),
     "ssp_export": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp]),
     "ssp_solve_outer": (C.c_int, [_vp, _vp, _vp]),

@@ -221,6 +221,47 @@ __global__ __launch_bounds__(T) void k_build_S(BuildArgs a) {
     if (!ok && threadIdx.x == 0) atomicOr(a.status + p, kNotSpd);
 }
 
+// S given directly by its blocks (D_k, and L_k = S[k][k-1] for k >= 1, FP64
+// row-major at the problem's off_nn): stores D_k (symmetrised) and L_k like
+// phase 2, and D_k^-1.  One workgroup per knot of the batch.
+template <typename TM>
+__global__ __launch_bounds__(T) void k_build_blocks(BuildArgs a, const double *D, const double *Lsub) {
+    extern __shared__ double sm[];
+    int p, k;
+    knot_of(a, p, k);
+    const int nx = a.nx[p], nn = nx * nx;
+    const int64_t o = a.off_nn[p] + (int64_t)k * nn;
+    const int bs = block_stride(nx, sizeof(TM)), bp = packed_stride(nx, sizeof(TM));
+    const int64_t os = a.off_blk[p] + (int64_t)k * bs;  // remainder of L_k
+    const int64_t od = a.off_pk[p] + (int64_t)k * bp;   // remainder of D_k (packed)
+    TM *blk = (TM *)a.B3 + a.off_b3[p] + (int64_t)k * (2 * bp + bs);  // D_k (packed), L_k, D_k^-1 (packed)
+    double *Dm = sm, *col = sm + nn;
+    team_load(Dm, D + o, nn);
+    if (k > 0) {
+        store_split(blk + bp, a.SLlo ? a.SLlo + os : nullptr, Lsub + o, nn, 1.0);
+    } else {
+        for (int e = threadIdx.x; e < nn; e += T) {
+            blk[bp + e] = (TM)0;
+            if (a.SLlo) a.SLlo[os + e] = 0.f;
+        }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < nn; e += T) {
+        const int i = e / nx, j = e - i * nx;
+        if (i < j) {
+            const double s = 0.5 * (Dm[i * nx + j] + Dm[j * nx + i]);
+            Dm[i * nx + j] = s;
+            Dm[j * nx + i] = s;
+        }
+    }
+    __syncthreads();
+    store_split_packed(blk, a.SDlo ? a.SDlo + od : nullptr, Dm, nx);
+    __syncthreads();
+    const bool ok = team_spd_inverse(Dm, col, nx);
+    store_split_packed(blk + bp + bs, (float *)nullptr, Dm, nx);
+    if (!ok && threadIdx.x == 0) atomicOr(a.status + p, kNotSpd);
+}
+
 // Phase 3 (explicit stair blocks, built only when asked for): the
 // sub-diagonal blocks of Phi^-1 in TM, from the stored D^-1 and L (with
 // L's FP32 remainder), multiplied in FP64.
@@ -307,6 +348,20 @@ hipError_t launch_build(const BuildArgs &a, int64_t knots, int nx_max, int nu_ma
         hipLaunchKernelGGL(k_build_S<float>, grid, block, l2, s, a);
     else
         hipLaunchKernelGGL(k_build_S<double>, grid, block, l2, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_build_blocks(const BuildArgs &a, const double *D, const double *Lsub, int64_t knots, bool fp32,
+                              hipStream_t s) {
+    if (knots == 0) return hipSuccess;
+    const size_t l1 = lds_phase1(a.mx);
+    const void *f = fp32 ? (const void *)k_build_blocks<float> : (const void *)k_build_blocks<double>;
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)l1);
+    if (e) return e;
+    if (fp32)
+        hipLaunchKernelGGL(k_build_blocks<float>, dim3((unsigned)knots), dim3(T), l1, s, a, D, Lsub);
+    else
+        hipLaunchKernelGGL(k_build_blocks<double>, dim3((unsigned)knots), dim3(T), l1, s, a, D, Lsub);
     return hipGetLastError();
 }
 

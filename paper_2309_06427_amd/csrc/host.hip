@@ -502,6 +502,28 @@ ssp_status ssp_build(ssp_batch *b, ssp_precon pc, ssp_precision prec, const doub
     return SSP_OK;
 }
 
+ssp_status ssp_build_from_blocks(ssp_batch *b, ssp_precon pc, ssp_precision prec, const double *D,
+                                 const double *Lsub, int32_t *prob_status, void *stream) {
+    if (!b || !D || !Lsub || !prob_status) return SSP_ERR_ARG;
+    if (pc < SSP_PC_BLOCK_JACOBI || pc > SSP_PC_SYM_STAIR) return SSP_ERR_ARG;
+    if (prec < SSP_FP64 || prec > SSP_FP32_REFINE64) return SSP_ERR_ARG;
+    DevGuard g(b->device);
+    hipStream_t s = (hipStream_t)stream;
+    const bool fp32 = prec != SSP_FP64;
+    ssp_status rc = alloc_storage(b, fp32);
+    if (rc != SSP_OK) return rc;
+    b->built = false;
+    b->m_valid = false;
+    b->pc = pc;
+    b->prec = prec;
+    SSP_HIP(ssp::launch_fill_i32(prob_status, 0, b->P, s));
+    ssp::BuildArgs a = build_args(b);
+    a.status = prob_status;
+    SSP_HIP(ssp::launch_build_blocks(a, D, Lsub, b->knots, fp32, s));
+    b->built = true;
+    return SSP_OK;
+}
+
 ssp_status ssp_solve(ssp_batch *b, double rel_tol, int32_t max_iter, const double *gamma, double *lambda,
                      int use_lambda0, int32_t *iters, double *relres, int32_t *prob_status, void *stream) {
     if (!b || !gamma || !lambda || !iters || !relres || !prob_status) return SSP_ERR_ARG;

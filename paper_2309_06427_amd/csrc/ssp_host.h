@@ -60,6 +60,10 @@ constexpr int kBuildClasses = 4;
 extern const int kBuildSizes[kBuildClasses];
 int build_knots_per_item(int nx);
 hipError_t launch_build_class(int cls, const BuildArgs &a, const int2 *items, int nitems, bool fp32, hipStream_t s);
+// S from caller-given blocks D_k, L_k (every knot of the batch): stored D,
+// L and D^-1 as the assembly stores them.
+hipError_t launch_build_blocks(const BuildArgs &a, const double *D, const double *Lsub, int64_t knots, bool fp32,
+                               hipStream_t s);
 // Explicit stair blocks from the stored D^-1 and L (every knot of the batch).
 hipError_t launch_build_phi(const BuildArgs &a, int64_t knots, int nx_max, bool fp32, hipStream_t s);
 // Copy one stored block kind to the caller's FP64 layout (full nx x nx

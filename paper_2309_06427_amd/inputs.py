@@ -135,6 +135,65 @@ def pack(probs: Sequence[dict]) -> Batch:
                  gamma=cat("gamma"), off_nn=off_nn, off_nu=off_nu, off_uu=off_uu, off_v=off_v)
 
 
+@dataclasses.dataclass
+class BlockBatch:
+    """Ragged batch of symmetric block-tridiagonal matrices given by blocks:
+    ``D[off_nn[p] : off_nn[p+1]]`` holds S[k][k] (k = 0..N-1) and ``L`` at the
+    same offsets S[k][k-1] (block 0 zero), nx x nx row-major; ``gamma`` at
+    ``off_v`` as in :class:`Batch`."""
+
+    N: np.ndarray       # int32 [P]
+    nx: np.ndarray      # int32 [P]
+    D: np.ndarray       # float64 flat
+    L: np.ndarray
+    gamma: np.ndarray
+    off_nn: np.ndarray  # int64 [P+1]
+    off_v: np.ndarray
+
+    @property
+    def P(self) -> int:
+        return int(self.N.shape[0])
+
+    def problem(self, p: int) -> dict:
+        N, nx = int(self.N[p]), int(self.nx[p])
+        sl = lambda arr, off, blk: arr[off[p]:off[p + 1]].reshape((N,) + blk)
+        return dict(N=N, nx=nx, D=sl(self.D, self.off_nn, (nx, nx)), L=sl(self.L, self.off_nn, (nx, nx)),
+                    gamma=self.gamma[self.off_v[p]:self.off_v[p + 1]])
+
+
+def draw_block_tridiag(rng: np.random.Generator, N: int, nx: int, margin: float = 0.5) -> dict:
+    """Blocks of a random SPD block-tridiagonal matrix not built from dynamics:
+    L_k (k >= 1) with iid N(0, 1/nx) entries, D_k = W_k W_k^T / nx + c_k I with
+    W_k iid N(0,1) and c_k = ||L_k||_2 + ||L_{k+1}||_2 + margin, so every block
+    row is diagonally dominant in the 2-norm (block Gershgorin) and the matrix
+    is SPD.  Draw order: L, W, gamma."""
+    L = rng.standard_normal((N, nx, nx)) / np.sqrt(nx)
+    L[0] = 0.0
+    W = rng.standard_normal((N, nx, nx))
+    nrm = np.linalg.norm(L, ord=2, axis=(1, 2))
+    c = nrm + np.append(nrm[1:], 0.0) + margin
+    D = W @ np.swapaxes(W, 1, 2) / nx + c[:, None, None] * np.eye(nx)[None]
+    D = 0.5 * (D + np.swapaxes(D, 1, 2))
+    gamma = rng.standard_normal(N * nx)
+    return dict(N=N, nx=nx, D=D, L=L, gamma=gamma)
+
+
+def block_batch(Ns: Sequence[int], nxs: Sequence[int], seed: int, margin: float = 0.5) -> BlockBatch:
+    """Problems of sizes (Ns[i], nxs[i]) from :func:`draw_block_tridiag`, problem i
+    seeded with child i of ``SeedSequence(seed)``."""
+    kids = np.random.SeedSequence(seed).spawn(len(Ns))
+    probs = [draw_block_tridiag(np.random.default_rng(k), int(n), int(x), margin) for k, n, x in zip(kids, Ns, nxs)]
+    P = len(probs)
+    N = np.array([q["N"] for q in probs], dtype=np.int32)
+    nx = np.array([q["nx"] for q in probs], dtype=np.int32)
+    off_nn = np.zeros(P + 1, dtype=np.int64)
+    off_nn[1:] = np.cumsum(N.astype(np.int64) * nx * nx)
+    off_v = np.zeros(P + 1, dtype=np.int64)
+    off_v[1:] = np.cumsum(N.astype(np.int64) * nx)
+    cat = lambda key: np.concatenate([q[key].ravel() for q in probs]) if P else np.zeros(0)
+    return BlockBatch(N=N, nx=nx, D=cat("D"), L=cat("L"), gamma=cat("gamma"), off_nn=off_nn, off_v=off_v)
+
+
 def single(N: int, nx: int, nu: int, seed: int, qmode: str = "wishart",
            qcond_max: float = 1e4) -> Batch:
     """One problem drawn from ``default_rng(seed)`` (the plain single solve)."""

@@ -58,6 +58,10 @@ class BatchSolver:
         check(_lib.load().ssp_build(self._h, PC[pc], PREC[precision], _ptr(A), _ptr(B), _ptr(Q), _ptr(R),
                                     _ptr(status), _stream(stream)), "ssp_build")
 
+    def build_from_blocks(self, pc: str, precision: str, D, Lsub, status, stream=None):
+        check(_lib.load().ssp_build_from_blocks(self._h, PC[pc], PREC[precision], _ptr(D), _ptr(Lsub),
+                                                _ptr(status), _stream(stream)), "ssp_build_from_blocks")
+
     def solve(self, tol: float, max_iter: int, gamma, lam, use_lambda0: int, iters, relres, status,
               stream=None):
         """use_lambda0: 0 zero start, 1 start from lam, 2 start from lam with
@@ -161,6 +165,32 @@ class DeviceBatch:
         self.solver.export(which, d, o)
         torch.cuda.synchronize()
         return d.cpu().numpy(), o.cpu().numpy()
+
+
+class DeviceBlockBatch(DeviceBatch):
+    """A batch of block-tridiagonal matrices given by their blocks
+    (:class:`paper_2309_06427_amd.inputs.BlockBatch`) resident on the GPU; the
+    build takes S as given instead of assembling it from dynamics."""
+
+    def __init__(self, batch, device: int = 0):
+        import torch
+        self.batch = batch
+        dev = torch.device("cuda", device)
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev)
+        self.D, self.L, self.gamma = (t(x) for x in (batch.D, batch.L, batch.gamma))
+        self.solver = BatchSolver(batch.N, batch.nx, np.zeros_like(batch.N), device)
+        for mine, theirs in ((self.solver.off_nn, batch.off_nn), (self.solver.off_v, batch.off_v)):
+            if not np.array_equal(mine, theirs):
+                raise ValueError("batch packing does not match the library layout")
+        P = batch.P
+        self.lam = torch.zeros_like(self.gamma)
+        self.iters = torch.zeros(P, dtype=torch.int32, device=dev)
+        self.relres = torch.zeros(P, dtype=torch.float64, device=dev)
+        self.status = torch.zeros(P, dtype=torch.int32, device=dev)
+        self.outer = torch.zeros(P, dtype=torch.int32, device=dev)
+
+    def build(self, pc: str = "sym", precision: str = "fp32_refine64", stream=None):
+        self.solver.build_from_blocks(pc, precision, self.D, self.L, self.status, stream)
 
 
 def solve(batch, pc: str = "sym", precision: str = "fp32_refine64", tol: float = 1e-6, max_iter: int = 0,

@@ -395,3 +395,33 @@ def test_warm_start_fallback_gives_the_cold_solve():
     exact = oracle.solve_batch(b, "sym", "fp64", tol=1e-13)
     good = oracle.solve_batch(b, "sym", "fp32_refine64", tol=1e-6, lam0=exact["lam"], fallback=True)
     assert (good["status"] == 0).all() and (good["iters"] == 0).all()
+
+
+# ------------------------------------------- preconditioner of a given S (blocks in)
+
+@pytest.mark.parametrize("N,nx,seed", [(1, 3, 0), (2, 4, 1), (7, 5, 2), (10, 6, 3)])
+def test_precond_of_given_blocks_equals_paper_definitions(N, nx, seed):
+    """For an SPD block-tridiagonal S that does not come from dynamics, the
+    preconditioner built from its blocks alone matches the dense definitions:
+    Phi_sym^-1 = Psi_l^-1 + Psi_r^-1 - D^-1 (Sec. IV), Phi_add^-1 = (Psi_l^-1 + Psi_r^-1)/2
+    (Sec. III), block-Jacobi = block-diag(S)^-1 (Eq. jacobi)."""
+    q = inputs.block_batch([N], [nx], seed).problem(0)
+    S = dense.assemble(q["D"], q["L"])
+    Dm = dense.block_diag_part(S, nx)
+    Pl, Pr = dense.stair(S, nx, "l"), dense.stair(S, nx, "r")
+    inv = np.linalg.inv
+    want = {"sym": inv(Pl) + inv(Pr) - inv(Dm), "add": 0.5 * (inv(Pl) + inv(Pr)), "bj": inv(Dm)}
+    for pc, W in want.items():
+        st, Di, M = oracle.precond(q["D"], q["L"], pc)
+        assert st == oracle.OK
+        got = dense.assemble(Di, M)
+        assert np.abs(got - W).max() <= 1e-11 * np.abs(W).max(), pc
+
+
+def test_precond_of_given_blocks_flags_an_indefinite_diagonal_block():
+    """A diagonal block with a negative eigenvalue cannot belong to an SPD S: NOT_SPD."""
+    q = inputs.block_batch([6], [4], 7).problem(0)
+    D = q["D"].copy()
+    D[3] -= 2.0 * np.linalg.eigvalsh(D[3]).max() * np.eye(4)
+    st, _, _ = oracle.precond(D, q["L"], "sym")
+    assert st == oracle.NOT_SPD
