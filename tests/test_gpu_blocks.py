@@ -137,3 +137,22 @@ def test_blocks_indefinite_diagonal_block_is_not_spd(prec):
     others = np.arange(b.P) != bad
     assert (out["status"][others] == 0).all()
     assert out["relres"][others].max() <= 1e-6 * 1.0001
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-9), ("fp32_refine64", 1e-6)])
+def test_blocks_single_long_problem_cooperative(prec, tol):
+    """One long problem built from blocks runs the cooperative solve (several
+    workgroups) and matches the oracle's direct solution."""
+    b = inputs.block_batch([160], [14], 9)
+    db = _dev(b, "sym", prec)
+    db.solve(tol)
+    out = db.results()
+    assert db.solver.solve_kernel()[0] == 3
+    assert out["status"][0] == 0
+    assert out["relres"][0] <= tol * 1.0001
+    q = b.problem(0)
+    _, x = oracle.direct(q["D"], q["L"], q["gamma"])
+    from tests import dense
+    ev = np.linalg.eigvalsh(dense.assemble(q["D"], q["L"]))
+    err = np.linalg.norm(out["lam"] - x) / np.linalg.norm(x)
+    assert err <= ev[-1] / ev[0] * tol * 1.01
