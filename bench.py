@@ -31,7 +31,7 @@ SOLVE_SOURCES = ("pcg2.hip", "ssp_device.h", "ssp_sweep.h", "ssp_host.h", "host.
 MEASURED_TRAFFIC = {
     # (workload, pc, precision, kernel): (sources sha256[:16], bytes of one solve, all its dispatches)
     ("batch4096_ragged", "sym", "fp32_refine64", 0):
-        ("bb4ea3e858399ac9", (21506964.4375 * 2.0 + 5561625.78125 * 1.0) * 1024),
+        ("4271748e2a8a1ed3", (21505446.3125 * 2.0 + 5561210.09375 * 1.0) * 1024),
 }
 
 
