@@ -162,8 +162,16 @@ def main() -> int:
         x = torch.ones(n, dtype=torch.float32, device="cuda")
         y = torch.empty_like(x)
         out = {}
+        from paper_2309_06427_amd import _lib
+
+        lib = _lib.load()
+
+        def own_copy():
+            _lib.check(lib.ssp_copy_bytes(x.data_ptr(), y.data_ptr(), n * 4,
+                                          torch.cuda.current_stream().cuda_stream), "ssp_copy_bytes")
+
         for name, fn, moved in (("read", lambda: x.sum(), n * 4), ("write", lambda: y.fill_(1.0), n * 4),
-                                ("copy", lambda: y.copy_(x), 2 * n * 4)):
+                                ("copy", lambda: y.copy_(x), 2 * n * 4), ("own_copy", own_copy, 2 * n * 4)):
             for _ in range(3):
                 fn()
             best = float("inf")

@@ -49,6 +49,7 @@ SIGNATURES = {
     "ssp_set_group_mapping": (C.c_int, [_vp, _i32, _i32, _i32]),
     "ssp_get_mapping": (C.c_int, [_vp, _i32, _pi32, _pi32, _pi32, C.POINTER(_f), _pi32]),
     "ssp_solve_kernel": (C.c_int, [_vp, _pi32, _pi32, _pi32]),
+    "ssp_copy_bytes": (C.c_int, [_vp, _vp, _i64, _vp]),
     "ssp_status_str": (C.c_char_p, [C.c_int]),
     "ssp_last_error": (C.c_char_p, []),
 }
