@@ -271,7 +271,8 @@ ssp_status ssp_solve_kernel(const ssp_batch *b, int32_t *kernel, int32_t *W, int
 /* Device-to-device copy of `bytes` bytes (a multiple of 16; src and dst
  * 16-byte aligned, not overlapping) with a plain streaming kernel, on
  * `stream`.  It is the library's own measure of the practical HBM rate that
- * the solve's measured traffic is compared with; nothing else calls it. */
+ * the solve's measured traffic is compared with; the library itself never
+ * calls it. */
 ssp_status ssp_copy_bytes(const void *src, void *dst, int64_t bytes, void *stream);
 
 const char *ssp_status_str(ssp_status s);
