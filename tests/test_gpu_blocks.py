@@ -86,11 +86,16 @@ def test_blocks_build_fp32_storage_keeps_S_to_fp64():
             assert np.abs(got - want).max() <= tol * np.abs(want).max(), i
 
 
+@pytest.mark.parametrize("kernel", [0, 1])
 @pytest.mark.parametrize("pc", ["bj", "add", "sym"])
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-9), ("fp32_refine64", 1e-6)])
-def test_blocks_solve_matches_direct_solution(pc, prec, tol):
+def test_blocks_solve_matches_direct_solution(pc, prec, tol, kernel):
+    """Fused kernel (0) and the explicit-block kernel (1, stair blocks built on
+    demand from the stored D^-1 and L) on S given by blocks."""
     b = _batch(3)
     db = _dev(b, pc, prec)
+    if kernel:
+        db.solver.set_mapping(128, 0, kernel)
     db.solve(tol)
     out = db.results()
     assert (out["status"] == 0).all(), out["status"]
