@@ -56,6 +56,9 @@ enum {
     SSP_P_MAXITER = 2,   /* max_iter inner iterations or max refinement steps reached */
     SSP_P_NONFINITE = 3, /* NaN/Inf in gamma, lambda0 or a recurrence scalar */
     SSP_P_BREAKDOWN = 4, /* p^T S p <= 0 or r^T z <= 0 inside PCG */
+    SSP_P_INACCURATE = 5, /* FP64 or FP32 without refinement: the inner solve met
+                             rel_tol on its recurrence residual but the true FP64
+                             residual did not (relres > rel_tol) */
     SSP_P_WARM_FALLBACK = 8, /* bit OR-ed onto the status: the warm start did not
                                 reduce the residual and the solve started from 0 */
     SSP_P_PC_FALLBACK = 16   /* bit OR-ed onto the status (FP32 with refinement):
@@ -132,8 +135,10 @@ ssp_status ssp_build_from_blocks(ssp_batch *b, ssp_precon pc, ssp_precision prec
  *             status carries SSP_P_WARM_FALLBACK
  *   iters:    device int32[nprob], inner PCG iterations (S-products)
  *   relres:   device FP64[nprob], final true relative residual in FP64
- *   prob_status: device int32[nprob], in = build status (problems that
- *             failed to build are skipped), out = solve status.
+ *   prob_status: device int32[nprob], in = build status (a problem whose
+ *             status has low bits SSP_P_NOT_SPD is skipped: lambda = 0,
+ *             iters = 0, relres = NaN; any other incoming value, e.g. an
+ *             earlier solve's status, is ignored), out = solve status.
  *   max_iter: cap on the inner iterations per problem (<= 0: 10 * N * nx).
  * FP32_REFINE64 runs at most 5 refinement steps; the inner relative
  * tolerance of step j is clamp(0.5 * rel_tol * ||gamma|| / ||r_j||, 1e-6, 1).

@@ -18,10 +18,13 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "ssp_oracle.c")
 _LIB = os.path.join(_HERE, "libssp_oracle.so")
 
-OK, NOT_SPD, MAXITER, NONFINITE, BREAKDOWN = 0, 1, 2, 3, 4
+OK, NOT_SPD, MAXITER, NONFINITE, BREAKDOWN, INACCURATE = 0, 1, 2, 3, 4, 5
 WARM_FALLBACK = 8  # OR-ed onto a status: the warm start was replaced by zero
 PC_FALLBACK = 16   # OR-ed: the refinement went on with block-Jacobi after a float breakdown
-PC = {"bj": 0, "add": 1, "sym": 2}
+# bj: block-Jacobi, add / sym: additive / symmetric stair, jacobi: scalar
+# Jacobi, poly2 / poly3: Neumann polynomial of degree 2 / 3 with Psi = D
+PC = {"bj": 0, "add": 1, "sym": 2, "jacobi": 3, "poly2": 4, "poly3": 5}
+POLY_DEGREE = {"poly2": 2, "poly3": 3}
 PREC = {"fp64": 0, "fp32": 1, "fp32_refine64": 2}
 # refinement constants: inner tolerance tau_j = clamp(THETA*tol*|g|/|r_j|, TAU_MIN, 1)
 THETA, TAU_MIN, MAX_OUTER = 0.5, 1e-6, 5
@@ -51,15 +54,20 @@ def lib():
         L.ssp_oracle_precond.argtypes = [i, i, i, d, d, d, d]
         L.ssp_oracle_precond.restype = i
         L.ssp_oracle_btmv.argtypes = [i, i, d, d, d, d]
-        L.ssp_oracle_pcg.argtypes = [i, i, d, d, d, d, d, C.c_double, i, d, ip]
+        L.ssp_oracle_pcg.argtypes = [i, i, d, d, d, d, i, d, C.c_double, i, d, ip]
         L.ssp_oracle_pcg.restype = i
-        L.ssp_oracle_pcg_mixed.argtypes = [i, i, d, d, d, d, d, C.c_double, i, i, i,
+        L.ssp_oracle_pcg_mixed.argtypes = [i, i, d, d, d, d, i, d, C.c_double, i, i, i,
                                            C.c_double, C.c_double, d, ip, ip]
         L.ssp_oracle_pcg_mixed.restype = i
         L.ssp_oracle_relres.argtypes = [i, i, d, d, d, d]
         L.ssp_oracle_relres.restype = C.c_double
         L.ssp_oracle_direct.argtypes = [i, i, d, d, d, d]
         L.ssp_oracle_direct.restype = i
+        L.ssp_oracle_apply_precond.argtypes = [i, i, d, d, d, i, d, d]
+        L.ssp_oracle_kkt_rhs.argtypes = [i, i, i, d, d, d, d, d, d, d, d]
+        L.ssp_oracle_kkt_rhs.restype = i
+        L.ssp_oracle_kkt_recover.argtypes = [i, i, i, d, d, d, d, d, d, d, d, d]
+        L.ssp_oracle_kkt_recover.restype = i
         L.ssp_oracle_solve_batch.argtypes = [i, ip, ip, ip, i64, i64, i64, i64, d, d, d, d, d,
                                              i, i, C.c_double, i, i, C.c_double, C.c_double,
                                              i, d, ip, ip, d, ip]
@@ -114,30 +122,65 @@ def btmv(Dg, Sb, x):
     return y
 
 
-def pcg(D, L, Dinv, M, gamma, tol=1e-8, max_iter=None, lam0=None):
-    """FP64 PCG; returns (status, lam, iters)."""
+def pcg(D, L, Dinv, M, gamma, tol=1e-8, max_iter=None, lam0=None, poly=0):
+    """FP64 PCG; returns (status, lam, iters).  poly = 0: Phi^-1 is the
+    block-tridiagonal (Dinv, M); poly = m >= 1: the Neumann polynomial of
+    degree m with Psi = D (M ignored)."""
     D, L, Dinv, M, gamma = map(_f64, (D, L, Dinv, M, gamma))
     N, nx = D.shape[0], D.shape[1]
     lam = np.zeros(N * nx) if lam0 is None else _f64(lam0).copy()
     it = C.c_int(0)
     mi = 10 * N * nx if max_iter is None else max_iter
-    st = lib().ssp_oracle_pcg(N, nx, _dp(D), _dp(L), _dp(Dinv), _dp(M), _dp(gamma), tol, mi,
+    st = lib().ssp_oracle_pcg(N, nx, _dp(D), _dp(L), _dp(Dinv), _dp(M), int(poly), _dp(gamma), tol, mi,
                               _dp(lam), C.byref(it))
     return st, lam, it.value
 
 
 def pcg_mixed(D, L, Dinv, M, gamma, tol=1e-6, max_iter=None, refine=True, lam0=None,
-              max_outer=MAX_OUTER, theta=THETA, tau_min=TAU_MIN):
+              max_outer=MAX_OUTER, theta=THETA, tau_min=TAU_MIN, poly=0):
     """Float inner PCG with optional FP64 refinement; returns (status, lam, iters, outer)."""
     D, L, Dinv, M, gamma = map(_f64, (D, L, Dinv, M, gamma))
     N, nx = D.shape[0], D.shape[1]
     lam = np.zeros(N * nx) if lam0 is None else _f64(lam0).copy()
     it, ou = C.c_int(0), C.c_int(0)
     mi = 10 * N * nx if max_iter is None else max_iter
-    st = lib().ssp_oracle_pcg_mixed(N, nx, _dp(D), _dp(L), _dp(Dinv), _dp(M), _dp(gamma), tol, mi,
+    st = lib().ssp_oracle_pcg_mixed(N, nx, _dp(D), _dp(L), _dp(Dinv), _dp(M), int(poly), _dp(gamma), tol, mi,
                                     int(refine), max_outer, theta, tau_min, _dp(lam),
                                     C.byref(it), C.byref(ou))
     return st, lam, it.value, ou.value
+
+
+def apply_precond(L, Dinv, M, r, poly=0):
+    """z = Phi^-1 r exactly as the oracle's PCG applies it (L: S's
+    sub-diagonal blocks, used by the polynomial forms)."""
+    L, Dinv, M, r = map(_f64, (L, Dinv, M, r))
+    N, nx = Dinv.shape[0], Dinv.shape[1]
+    z = np.zeros(N * nx)
+    lib().ssp_oracle_apply_precond(N, nx, _dp(Dinv), _dp(M), _dp(L), int(poly), _dp(r.ravel()), _dp(z))
+    return z
+
+
+def kkt_rhs(A, B, Q, R, q, r, c):
+    """gamma = c - C G^-1 g for one problem (Eq. schur with the zeta blocks);
+    A, Q: (N, nx, nx), B: (N, nx, nu), R: (N, nu, nu); q, c: N*nx; r: N*nu
+    (block N-1 unused).  Returns (status, gamma)."""
+    A, B, Q, R, q, r, c = map(_f64, (A, B, Q, R, q, r, c))
+    N, nx, nu = A.shape[0], A.shape[1], B.shape[2]
+    g = np.zeros(N * nx)
+    st = lib().ssp_oracle_kkt_rhs(N, nx, nu, _dp(A), _dp(B), _dp(Q), _dp(R), _dp(q.ravel()), _dp(r.ravel()),
+                                  _dp(c.ravel()), _dp(g))
+    return st, g
+
+
+def kkt_recover(A, B, Q, R, q, r, lam):
+    """dz* = G^-1 (g - C^T lambda*) with lambda* = -lam (the library's sign);
+    returns (status, dx (N*nx), du (N*nu, block N-1 zero))."""
+    A, B, Q, R, q, r, lam = map(_f64, (A, B, Q, R, q, r, lam))
+    N, nx, nu = A.shape[0], A.shape[1], B.shape[2]
+    dx, du = np.zeros(N * nx), np.zeros(max(N * nu, 1))
+    st = lib().ssp_oracle_kkt_recover(N, nx, nu, _dp(A), _dp(B), _dp(Q), _dp(R), _dp(q.ravel()),
+                                      _dp(r.ravel() if r.size else np.zeros(1)), _dp(lam.ravel()), _dp(dx), _dp(du))
+    return st, dx, du[:N * nu]
 
 
 def relres(D, L, gamma, lam) -> float:

@@ -21,6 +21,13 @@
  *     explicit block form.
  *   Sec. II-B: PCG needs only products with S and Phi^-1 plus reductions (the
  *     recurrences are the textbook preconditioned CG the paper cites).
+ *   Sec. II-C, Eq. (jacobi): scalar Jacobi Phi = diag(S).
+ *   Sec. II-C, Eq. (polynomial_precon): with the splitting S = Psi - P,
+ *     Psi = D (block diagonal) and P = D - S, the degree-m preconditioner is
+ *     (I + Psi^-1 P + ... + (Psi^-1 P)^m) Psi^-1; it is applied by the Horner
+ *     recurrence z_0 = D^-1 r, z_{j+1} = D^-1 (r - O z_j) with O = S - D.
+ *   Sec. II-A, Eq. (schur) and the zeta block definitions: the right-hand
+ *     side gamma = c - C G^-1 g and the recovery dz = G^-1 (g - C^T lambda*).
  *
  * Indexing reading (N knots -> N block rows k = 0..N-1):
  *   D_0 = Q_0^-1
@@ -45,9 +52,14 @@
 #define OR_WARM_FALLBACK 8 /* OR-ed: the warm start was replaced by zero */
 #define OR_PC_FALLBACK 16  /* OR-ed: the solve went on with block-Jacobi after a float breakdown */
 
+#define OR_INACCURATE 5 /* one solve without refinement: recurrence met tol, true residual did not */
+
 #define OR_PC_BJ 0
 #define OR_PC_ADD 1
 #define OR_PC_SYM 2
+#define OR_PC_JACOBI 3 /* scalar Jacobi: Phi = diag(S) */
+#define OR_PC_POLY2 4  /* Neumann polynomial of degree 2 in Psi^-1 P, Psi = D */
+#define OR_PC_POLY3 5  /* ... of degree 3 */
 
 #define OR_FP64 0
 #define OR_FP32 1
@@ -138,12 +150,21 @@ int ssp_oracle_precond(int N, int nx, int pc, const double *D, const double *L, 
     for (int k = 0; k < N && st == OR_OK; ++k)
         if (spd_inv(nx, D + k * nn, Dinv + k * nn)) st = OR_NOT_SPD;
 
-    /* sub-diagonal blocks of Phi^-1 (Eq. stair_inv and the Sec. IV form) */
+    /* scalar Jacobi (Eq. jacobi with Phi = diag(S)): Dinv holds 1 / S_ii */
+    if (st == OR_OK && pc == OR_PC_JACOBI)
+        for (int k = 0; k < N; ++k)
+            for (int i = 0; i < nx; ++i)
+                for (int j = 0; j < nx; ++j)
+                    Dinv[k * nn + i * nx + j] = (i == j) ? 1.0 / D[k * nn + i * nx + i] : 0.0;
+
+    /* sub-diagonal blocks of Phi^-1 (Eq. stair_inv and the Sec. IV form);
+     * zero for block-Jacobi, scalar Jacobi and the polynomial forms, which
+     * are not block tridiagonal and are applied by their recurrence */
     if (st == OR_OK) {
         memset(M, 0, sizeof(double) * nn);
         for (int k = 1; k < N; ++k) {
             double *Mk = M + k * nn;
-            if (pc == OR_PC_BJ) { memset(Mk, 0, sizeof(double) * nn); continue; }
+            if (pc != OR_PC_ADD && pc != OR_PC_SYM) { memset(Mk, 0, sizeof(double) * nn); continue; }
             matmul(nx, nx, nx, Dinv + k * nn, L + k * nn, 0, T1);       /* D_k^-1 L_k */
             matmul(nx, nx, nx, T1, Dinv + (k - 1) * nn, 0, T2);         /* ... D_{k-1}^-1 */
             double scale = (pc == OR_PC_ADD) ? -0.5 : -1.0;
@@ -231,6 +252,80 @@ static void btmv_f(int N, int nx, const float *Dg, const float *Sb, const float 
         }
 }
 
+/* z = Phi^-1 r.  poly = 0: Phi^-1 is the block-tridiagonal matrix with
+ * diagonal blocks Dinv and sub-diagonal blocks M (block-Jacobi, scalar
+ * Jacobi, both stairs).  poly = m >= 1: the Neumann polynomial
+ * sum_{i=0..m} (D^-1 P)^i D^-1 of Eq. (polynomial_precon) with Psi = D,
+ * P = D - S = -O, by Horner: z = D^-1 r, then m times z = D^-1 (r - O z).
+ * L holds S's sub-diagonal blocks (O's); t: one scratch vector. */
+static void apply_precond(int N, int nx, const double *Dinv, const double *M, const double *L, int poly,
+                          const double *r, double *z, double *t) {
+    const size_t nn = (size_t)nx * nx;
+    if (poly == 0) { ssp_oracle_btmv(N, nx, Dinv, M, r, z); return; }
+    for (int k = 0; k < N; ++k)
+        for (int i = 0; i < nx; ++i) {
+            double s = 0.0;
+            for (int j = 0; j < nx; ++j) s += Dinv[k * nn + i * nx + j] * r[k * nx + j];
+            z[k * nx + i] = s;
+        }
+    for (int it = 0; it < poly; ++it) {
+        /* t = r - O z, with O z the block-tridiagonal product with zero diagonal */
+        for (int k = 0; k < N; ++k)
+            for (int i = 0; i < nx; ++i) {
+                double s = 0.0;
+                if (k > 0)
+                    for (int j = 0; j < nx; ++j) s += L[k * nn + i * nx + j] * z[(k - 1) * nx + j];
+                if (k + 1 < N)
+                    for (int j = 0; j < nx; ++j) s += L[(k + 1) * nn + j * nx + i] * z[(k + 1) * nx + j];
+                t[k * nx + i] = r[k * nx + i] - s;
+            }
+        for (int k = 0; k < N; ++k)
+            for (int i = 0; i < nx; ++i) {
+                double s = 0.0;
+                for (int j = 0; j < nx; ++j) s += Dinv[k * nn + i * nx + j] * t[k * nx + j];
+                z[k * nx + i] = s;
+            }
+    }
+}
+
+/* Exported for tests: z = Phi^-1 r as the PCG applies it. */
+void ssp_oracle_apply_precond(int N, int nx, const double *Dinv, const double *M, const double *L, int poly,
+                              const double *r, double *z) {
+    double *t = malloc(sizeof(double) * (size_t)N * nx);
+    apply_precond(N, nx, Dinv, M, L, poly, r, z, t);
+    free(t);
+}
+
+/* The same in float (the inner solve of mixed precision). */
+static void apply_precond_f(int N, int nx, const float *Dinv, const float *M, const float *L, int poly,
+                            const float *r, float *z, float *t) {
+    const size_t nn = (size_t)nx * nx;
+    if (poly == 0) { btmv_f(N, nx, Dinv, M, r, z); return; }
+    for (int k = 0; k < N; ++k)
+        for (int i = 0; i < nx; ++i) {
+            float s = 0.0f;
+            for (int j = 0; j < nx; ++j) s += Dinv[k * nn + i * nx + j] * r[k * nx + j];
+            z[k * nx + i] = s;
+        }
+    for (int it = 0; it < poly; ++it) {
+        for (int k = 0; k < N; ++k)
+            for (int i = 0; i < nx; ++i) {
+                float s = 0.0f;
+                if (k > 0)
+                    for (int j = 0; j < nx; ++j) s += L[k * nn + i * nx + j] * z[(k - 1) * nx + j];
+                if (k + 1 < N)
+                    for (int j = 0; j < nx; ++j) s += L[(k + 1) * nn + j * nx + i] * z[(k + 1) * nx + j];
+                t[k * nx + i] = r[k * nx + i] - s;
+            }
+        for (int k = 0; k < N; ++k)
+            for (int i = 0; i < nx; ++i) {
+                float s = 0.0f;
+                for (int j = 0; j < nx; ++j) s += Dinv[k * nn + i * nx + j] * t[k * nx + j];
+                z[k * nx + i] = s;
+            }
+    }
+}
+
 static double dot(size_t n, const double *a, const double *b) {
     double s = 0.0;
     for (size_t i = 0; i < n; ++i) s += a[i] * b[i];
@@ -256,11 +351,12 @@ static int all_finite(size_t n, const double *a) {
  * on the recurrence residual, checked before every S-product.  *iters counts
  * the S-products after the initial residual.  Returns a status code. */
 int ssp_oracle_pcg(int N, int nx, const double *D, const double *L, const double *Dinv,
-                   const double *M, const double *gamma, double tol, int max_iter, double *lam,
+                   const double *M, int poly, const double *gamma, double tol, int max_iter, double *lam,
                    int *iters) {
     const size_t n = (size_t)N * nx;
     double *r = malloc(sizeof(double) * n), *z = malloc(sizeof(double) * n);
     double *p = malloc(sizeof(double) * n), *q = malloc(sizeof(double) * n);
+    double *t = malloc(sizeof(double) * n);
     int st = OR_OK, it = 0;
     *iters = 0;
     if (!all_finite(n, gamma) || !all_finite(n, lam)) { st = OR_NONFINITE; goto done; }
@@ -268,7 +364,7 @@ int ssp_oracle_pcg(int N, int nx, const double *D, const double *L, const double
     if (gnorm == 0.0) { memset(lam, 0, sizeof(double) * n); goto done; }
     ssp_oracle_btmv(N, nx, D, L, lam, q);
     for (size_t i = 0; i < n; ++i) r[i] = gamma[i] - q[i];
-    ssp_oracle_btmv(N, nx, Dinv, M, r, z);
+    apply_precond(N, nx, Dinv, M, L, poly, r, z, t);
     memcpy(p, z, sizeof(double) * n);
     double rz = dot(n, r, z);
     for (;;) {
@@ -282,7 +378,7 @@ int ssp_oracle_pcg(int N, int nx, const double *D, const double *L, const double
         if (!(pq > 0.0) || !(rz > 0.0)) { st = isfinite(pq) ? OR_BREAKDOWN : OR_NONFINITE; break; }
         double alpha = rz / pq;
         for (size_t i = 0; i < n; ++i) { lam[i] += alpha * p[i]; r[i] -= alpha * q[i]; }
-        ssp_oracle_btmv(N, nx, Dinv, M, r, z);
+        apply_precond(N, nx, Dinv, M, L, poly, r, z, t);
         double rz_new = dot(n, r, z);
         double beta = rz_new / rz;
         rz = rz_new;
@@ -290,7 +386,7 @@ int ssp_oracle_pcg(int N, int nx, const double *D, const double *L, const double
     }
 done:
     *iters = it;
-    free(r); free(z); free(p); free(q);
+    free(r); free(z); free(p); free(q); free(t);
     return st;
 }
 
@@ -299,17 +395,17 @@ done:
  * scaled to unit 2-norm in FP64 before rounding to float (so tiny or huge
  * residuals neither underflow nor overflow) and d is scaled back in FP64.
  * Used as the inner solve of mixed precision. */
-static int pcg_f32(int N, int nx, const float *D, const float *L, const float *Dinv, const float *M,
+static int pcg_f32(int N, int nx, const float *D, const float *L, const float *Dinv, const float *M, int poly,
                    const double *rhs, double tol, int max_iter, double *d_out, int *iters) {
     const size_t n = (size_t)N * nx;
     float *r = malloc(sizeof(float) * n), *z = malloc(sizeof(float) * n);
     float *p = malloc(sizeof(float) * n), *q = malloc(sizeof(float) * n);
-    float *d = calloc(n, sizeof(float));
+    float *d = calloc(n, sizeof(float)), *t = malloc(sizeof(float) * n);
     int st = OR_OK, it = 0;
     const double scale = sqrt(dot(n, rhs, rhs));
     for (size_t i = 0; i < n; ++i) r[i] = (float)(rhs[i] / scale);
     const float bnorm = sqrtf(dot_f(n, r, r));
-    btmv_f(N, nx, Dinv, M, r, z);
+    apply_precond_f(N, nx, Dinv, M, L, poly, r, z, t);
     memcpy(p, z, sizeof(float) * n);
     float rz = dot_f(n, r, z);
     for (;;) {
@@ -323,7 +419,7 @@ static int pcg_f32(int N, int nx, const float *D, const float *L, const float *D
         if (!(pq > 0.0f) || !(rz > 0.0f)) { st = isfinite(pq) ? OR_BREAKDOWN : OR_NONFINITE; break; }
         float alpha = rz / pq;
         for (size_t i = 0; i < n; ++i) { d[i] += alpha * p[i]; r[i] -= alpha * q[i]; }
-        btmv_f(N, nx, Dinv, M, r, z);
+        apply_precond_f(N, nx, Dinv, M, L, poly, r, z, t);
         float rz_new = dot_f(n, r, z);
         float beta = rz_new / rz;
         rz = rz_new;
@@ -331,7 +427,7 @@ static int pcg_f32(int N, int nx, const float *D, const float *L, const float *D
     }
     for (size_t i = 0; i < n; ++i) d_out[i] = scale * (double)d[i];
     *iters = it;
-    free(r); free(z); free(p); free(q); free(d);
+    free(r); free(z); free(p); free(q); free(d); free(t);
     return st;
 }
 
@@ -341,10 +437,12 @@ static int pcg_f32(int N, int nx, const float *D, const float *L, const float *D
  *     tau_j = clamp(theta * tol * ||gamma|| / ||r_j||, tau_min, 1);
  *   lam_{j+1} = lam_j + d in FP64.
  * refine = 0 runs one inner solve only (plain FP32 mode).
+ * refine = 0 ends with OR_INACCURATE if the true residual then misses tol.
  * Under refinement an inner breakdown (p^T S p <= 0 or r^T z <= 0 in float,
  * a loss of float accuracy for an SPD S) ends that inner solve; the step
- * still updates lam and the loop goes on.  Under a stair preconditioner
- * (M != 0) the breakdown also replaces it by block-Jacobi (M = 0), whose
+ * still updates lam and the loop goes on.  Under a stair or polynomial
+ * preconditioner (M != 0 or poly > 0) the breakdown also replaces it by
+ * block-Jacobi (M = 0, poly = 0), whose
  * float operator stays positive definite far longer, for the rest of the
  * solve, with a fresh budget of refinement steps; the status then carries
  * OR_PC_FALLBACK.  Under block-Jacobi, BREAKDOWN is reported if the next FP64
@@ -352,7 +450,7 @@ static int pcg_f32(int N, int nx, const float *D, const float *L, const float *D
  * *iters is the total number of inner S-products, *outer the refinement
  * steps taken. */
 int ssp_oracle_pcg_mixed(int N, int nx, const double *D, const double *L, const double *Dinv,
-                         const double *M, const double *gamma, double tol, int max_iter,
+                         const double *M, int poly, const double *gamma, double tol, int max_iter,
                          int refine, int max_outer, double theta, double tau_min, double *lam,
                          int *iters, int *outer) {
     const size_t n = (size_t)N * nx, nb = (size_t)N * nx * nx;
@@ -365,6 +463,7 @@ int ssp_oracle_pcg_mixed(int N, int nx, const double *D, const double *L, const 
         Df[e] = (float)D[e]; Lf[e] = (float)L[e]; DIf[e] = (float)Dinv[e]; Mf[e] = (float)M[e];
         if (M[e] != 0.0) stair = 1;
     }
+    if (poly > 0) stair = 1;
     *iters = 0;
     *outer = 0;
     if (!all_finite(n, gamma) || !all_finite(n, lam)) { st = OR_NONFINITE; goto done; }
@@ -376,7 +475,7 @@ int ssp_oracle_pcg_mixed(int N, int nx, const double *D, const double *L, const 
         double rnorm = sqrt(dot(n, r, r));
         if (!isfinite(rnorm)) { st = OR_NONFINITE; break; }
         if (rnorm <= tol * gnorm) break;
-        if (steps > 0 && !refine) break;
+        if (steps > 0 && !refine) { st = OR_INACCURATE; break; }
         if (broke && !(rnorm < prev)) { st = OR_BREAKDOWN; break; }
         if (steps - base >= max_outer) { st = OR_MAXITER; break; }
         prev = rnorm;
@@ -384,13 +483,14 @@ int ssp_oracle_pcg_mixed(int N, int nx, const double *D, const double *L, const 
         if (refine && tau < tau_min) tau = tau_min;
         if (tau > 1.0) tau = 1.0;
         int it = 0;
-        int ist = pcg_f32(N, nx, Df, Lf, DIf, Mf, r, tau, max_iter - total, d, &it);
+        int ist = pcg_f32(N, nx, Df, Lf, DIf, Mf, poly, r, tau, max_iter - total, d, &it);
         total += it;
         ++steps;
         for (size_t i = 0; i < n; ++i) lam[i] += d[i];
         broke = refine && ist == OR_BREAKDOWN;
         if (broke && stair && !fell) {
             memset(Mf, 0, sizeof(float) * nb);  /* go on with block-Jacobi */
+            poly = 0;
             fell = OR_PC_FALLBACK;
             broke = 0;
             base = steps;
@@ -479,6 +579,100 @@ done:
     return st;
 }
 
+/* ------------------------------------------------------------ KKT step --- */
+
+/* The paper writes the KKT system of the QP as [G C^T; C 0] [dz; lambda*] =
+ * [g; c] (Eq. schur: S = -C G^-1 C^T, gamma = c - C G^-1 g,
+ * dz* = G^-1 (g - C^T lambda*)), with G = blkdiag(Q_0, R_0, ..., R_{N-2},
+ * Q_{N-1}) and g = (q_0, r_0, ..., r_{N-2}, q_{N-1}).  Its block form of
+ * gamma, c + (-Q_0^-1 q_0, zeta_0, zeta_1, ...) with
+ * zeta_k = A_k Q_k^-1 q_k + B_k R_k^-1 r_k - Q_{k+1}^-1 q_{k+1}, fixes the
+ * sign of C: block row 0 is +I on x_0 and block row k + 1 is
+ * (-A_k, -B_k, +I) on (x_k, u_k, x_{k+1}).  (S does not depend on that
+ * sign.)  The library's lambda solves the negated system, lambda = -lambda*.
+ *
+ * gamma (N nx) from q (N nx), r (N nu; block N-1 unused) and c (N nx):
+ *   gamma_0 = c_0 - Q_0^-1 q_0,   gamma_k = c_k + zeta_{k-1}  (k >= 1).
+ * Returns OR_NOT_SPD if a Q_k or R_k (k <= N-2) is not SPD. */
+int ssp_oracle_kkt_rhs(int N, int nx, int nu, const double *A, const double *B, const double *Q,
+                       const double *R, const double *q, const double *r, const double *c, double *gamma) {
+    const size_t nn = (size_t)nx * nx, nuu = (size_t)nu * nu;
+    double *Qi = malloc(sizeof(double) * nn), *Ri = malloc(sizeof(double) * (nuu ? nuu : 1));
+    double *v = malloc(sizeof(double) * nx), *w = malloc(sizeof(double) * (nu ? nu : 1));
+    int st = OR_OK;
+    for (int k = 0; k < N * nx; ++k) gamma[k] = c[k];
+    for (int k = 0; k < N && st == OR_OK; ++k) {
+        /* -Q_k^-1 q_k enters row k */
+        if (spd_inv(nx, Q + k * nn, Qi)) { st = OR_NOT_SPD; break; }
+        for (int i = 0; i < nx; ++i) {
+            double t = 0.0;
+            for (int j = 0; j < nx; ++j) t += Qi[i * nx + j] * q[k * nx + j];
+            v[i] = t;
+            gamma[k * nx + i] -= t;
+        }
+        if (k + 1 >= N) break;
+        /* A_k Q_k^-1 q_k + B_k R_k^-1 r_k enters row k + 1 */
+        if (nu > 0) {
+            if (spd_inv(nu, R + k * nuu, Ri)) { st = OR_NOT_SPD; break; }
+            for (int i = 0; i < nu; ++i) {
+                double t = 0.0;
+                for (int j = 0; j < nu; ++j) t += Ri[i * nu + j] * r[(size_t)k * nu + j];
+                w[i] = t;
+            }
+        }
+        for (int i = 0; i < nx; ++i) {
+            double t = 0.0;
+            for (int j = 0; j < nx; ++j) t += A[k * nn + i * nx + j] * v[j];
+            for (int j = 0; j < nu; ++j) t += B[(size_t)k * nx * nu + i * nu + j] * w[j];
+            gamma[(k + 1) * nx + i] += t;
+        }
+    }
+    free(Qi); free(Ri); free(v); free(w);
+    return st;
+}
+
+/* dz* = G^-1 (g - C^T lambda*) with lambda* = -lam:
+ *   dx_k = Q_k^-1 (q_k + lam_k - A_k^T lam_{k+1})   (no lam_N term at k = N-1),
+ *   du_k = R_k^-1 (r_k - B_k^T lam_{k+1})           (k <= N-2; du_{N-1} = 0).
+ * dx: N nx, du: N nu.  Returns OR_NOT_SPD as kkt_rhs does. */
+int ssp_oracle_kkt_recover(int N, int nx, int nu, const double *A, const double *B, const double *Q,
+                           const double *R, const double *q, const double *r, const double *lam,
+                           double *dx, double *du) {
+    const size_t nn = (size_t)nx * nx, nuu = (size_t)nu * nu;
+    double *Mi = malloc(sizeof(double) * (nn > nuu ? nn : (nuu ? nuu : 1)));
+    double *t = malloc(sizeof(double) * (nx > nu ? nx : (nu ? nu : 1)));
+    int st = OR_OK;
+    for (int k = 0; k < N && st == OR_OK; ++k) {
+        for (int i = 0; i < nx; ++i) {
+            double s = q[k * nx + i] + lam[k * nx + i];
+            if (k + 1 < N)
+                for (int j = 0; j < nx; ++j) s -= A[k * nn + j * nx + i] * lam[(k + 1) * nx + j];
+            t[i] = s;
+        }
+        if (spd_inv(nx, Q + k * nn, Mi)) { st = OR_NOT_SPD; break; }
+        for (int i = 0; i < nx; ++i) {
+            double s = 0.0;
+            for (int j = 0; j < nx; ++j) s += Mi[i * nx + j] * t[j];
+            dx[k * nx + i] = s;
+        }
+        for (int i = 0; i < nu; ++i) du[(size_t)k * nu + i] = 0.0;
+        if (k + 1 >= N || nu == 0) continue;
+        for (int i = 0; i < nu; ++i) {
+            double s = r[(size_t)k * nu + i];
+            for (int j = 0; j < nx; ++j) s -= B[(size_t)k * nx * nu + j * nu + i] * lam[(k + 1) * nx + j];
+            t[i] = s;
+        }
+        if (spd_inv(nu, R + k * nuu, Mi)) { st = OR_NOT_SPD; break; }
+        for (int i = 0; i < nu; ++i) {
+            double s = 0.0;
+            for (int j = 0; j < nu; ++j) s += Mi[i * nu + j] * t[j];
+            du[(size_t)k * nu + i] = s;
+        }
+    }
+    free(Mi); free(t);
+    return st;
+}
+
 /* --------------------------------------------------------------- batch --- */
 
 /* Build and solve every problem of a packed ragged batch, one problem per
@@ -505,6 +699,7 @@ void ssp_oracle_solve_batch(int P, const int *Ns, const int *nxs, const int *nus
         int it = 0, ou = 0;
         int st = ssp_oracle_build(N, nx, nu, A + off_nn[p], B + off_nu[p], Q + off_nn[p],
                                   R + off_uu[p], pc, D, L, Di, M);
+        const int poly = pc == OR_PC_POLY2 ? 2 : pc == OR_PC_POLY3 ? 3 : 0;
         int fell_back = 0;
         if (st == OR_OK && warm_fallback) {
             /* a warm start whose residual is not below ||gamma|| is replaced by zero */
@@ -516,14 +711,16 @@ void ssp_oracle_solve_batch(int P, const int *Ns, const int *nxs, const int *nus
         }
         if (st == OR_OK) {
             if (precision == OR_FP64) {
-                st = ssp_oracle_pcg(N, nx, D, L, Di, M, g, tol, max_iter, x, &it);
+                st = ssp_oracle_pcg(N, nx, D, L, Di, M, poly, g, tol, max_iter, x, &it);
                 ou = 1;
             } else {
-                st = ssp_oracle_pcg_mixed(N, nx, D, L, Di, M, g, tol, max_iter,
+                st = ssp_oracle_pcg_mixed(N, nx, D, L, Di, M, poly, g, tol, max_iter,
                                           precision == OR_FP32_REFINE64, max_outer, theta, tau_min,
                                           x, &it, &ou);
             }
             relres[p] = ssp_oracle_relres(N, nx, D, L, g, x);
+            /* one FP64 solve: the recurrence residual met tol, the true one must too */
+            if (precision == OR_FP64 && st == OR_OK && relres[p] > tol) st = OR_INACCURATE;
         } else {
             relres[p] = NAN;
         }

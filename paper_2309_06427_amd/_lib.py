@@ -11,7 +11,7 @@ import os
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsymstair.so")
 
 SSP_OK, SSP_ERR_ARG, SSP_ERR_ALLOC, SSP_ERR_HIP, SSP_ERR_STATE = range(5)
-SSP_P_OK, SSP_P_NOT_SPD, SSP_P_MAXITER, SSP_P_NONFINITE, SSP_P_BREAKDOWN = range(5)
+SSP_P_OK, SSP_P_NOT_SPD, SSP_P_MAXITER, SSP_P_NONFINITE, SSP_P_BREAKDOWN, SSP_P_INACCURATE = range(6)
 SSP_P_WARM_FALLBACK = 8
 SSP_P_PC_FALLBACK = 16
 SSP_PC_BLOCK_JACOBI, SSP_PC_STAIR_ADD, SSP_PC_SYM_STAIR = range(3)

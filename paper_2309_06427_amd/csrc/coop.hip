@@ -355,8 +355,8 @@ __global__ __launch_bounds__(kCoopThreads) void k_coop(CoopArgs ca) {
     };
     TI wdummy = TI(0);
 
-    int st = a.status[p];
-    const bool failed_build = st != kOk;
+    const bool failed_build = build_failed(a.status[p]);
+    int st = failed_build ? kNotSpd : kOk;
     int total = 0, steps = 0;
     double rnorm = 0.0, gnorm = 0.0;
     bool fallback = false, pc_fallback = false, alive = true;
@@ -447,7 +447,10 @@ __global__ __launch_bounds__(kCoopThreads) void k_coop(CoopArgs ca) {
                 break;
             }
             if (rnorm <= a.tol * gnorm) break;
-            if (steps > 0 && !a.refine) break;
+            if (steps > 0 && !a.refine) {
+                st = kInaccurate;
+                break;
+            }
             if (broke && !(rnorm < prev)) {
                 st = kBreakdown;
                 break;

@@ -44,8 +44,8 @@ __global__ __launch_bounds__(BLOCK) void k_pcg(SolveArgs a) {
     const double *gam = a.gamma + ov;
     double *r64 = a.r64 + ov;
 
-    int st = a.status[p];
-    if (st != kOk) {
+    int st = kOk;
+    if (build_failed(a.status[p])) {
         for (int row = tid; row < n; row += BLOCK) lam[row] = 0.0;
         if (tid == 0) {
             a.iters[p] = 0;
@@ -96,17 +96,20 @@ __global__ __launch_bounds__(BLOCK) void k_pcg(SolveArgs a) {
         double prev = INFINITY;
         for (;;) {
             // true residual r = gamma - S lambda in FP64
-            double rr64 = 0.0;
+            double rr64 = 0.0, gg64 = 0.0;  // ||r||^2 and ||gamma||^2 over the same rows in the same order
             bt_sweep<double, TM, BLOCK, 0>(
                 N, g64, SD, ks3, SDlo, bp, SL, ks3, SLlo, true, (double *)smem_raw, [&](int row) { return lam[row]; },
                 [&](int row, double y, double) {
-                    const double r = gam[row] - y;
+                    const double gv = gam[row];
+                    const double r = gv - y;
                     r64[row] = r;
                     rr64 += r * r;
+                    gg64 += gv * gv;
                 });
-            rr64 = block_sum<BLOCK>(rr64, red64);
+            block_sum2<BLOCK>(rr64, gg64, red64);
             rnorm = sqrt(rr64);
-            if (steps == 0 && a.use_lambda0 == 2 && !(rnorm < gnorm)) {
+            // kept only if strictly below ||gamma|| (lambda0 = 0 ties and falls back)
+            if (steps == 0 && a.use_lambda0 == 2 && !(rnorm < sqrt(gg64))) {
                 // a warm start that does not reduce the residual is replaced by zero
                 for (int row = tid; row < n; row += BLOCK) {
                     lam[row] = 0.0;
@@ -125,7 +128,10 @@ __global__ __launch_bounds__(BLOCK) void k_pcg(SolveArgs a) {
                 break;
             }
             if (rnorm <= a.tol * gnorm) break;
-            if (steps > 0 && !a.refine) break;
+            if (steps > 0 && !a.refine) {
+                st = kInaccurate;
+                break;
+            }
             if (broke && !(rnorm < prev)) {
                 st = kBreakdown;
                 break;

@@ -485,14 +485,22 @@ __host__ __device__ inline int residual_knots_per_step(int nx, int block, int ld
     return C;
 }
 
+// This thread's parts of ||r||^2 and ||gamma||^2 from one residual pass,
+// both summed over the same rows in the same order, so that a start whose
+// residual is exactly gamma (lambda = 0) gives two equal norms.
+struct ResNorms {
+    double rr, gg;
+};
+
 // r = gamma - S lambda in FP64 with S read as hi + lo (FP32 storage) or
 // FP64, pipelined like the fused pass: the next step's D and L blocks are
 // prefetched into registers while the current step computes, then stored
 // into an LDS ring as FP64.  Step c stores knots [k0, k1) and forms r one
-// knot behind (r_k needs L_{k+1}).  Writes r64, returns this thread's part of
-// ||r||^2.  The same wave mapping as the fused pass (lane -> knot, row).
+// knot behind (r_k needs L_{k+1}).  Writes r64, returns this thread's parts
+// of ||r||^2 and ||gamma||^2.  The same wave mapping as the fused pass
+// (lane -> knot, row).
 template <typename TM, int BLOCK, int NX>
-__device__ __forceinline__ double residual_pass(int N, int C, const TM *__restrict__ B3,
+__device__ __forceinline__ ResNorms residual_pass(int N, int C, const TM *__restrict__ B3,
                                                 const float *__restrict__ Dlo, const float *__restrict__ Llo,
                                                 const double *__restrict__ lam, const double *__restrict__ gam,
                                                 double *__restrict__ r64, double *smem) {
@@ -558,7 +566,7 @@ __device__ __forceinline__ double residual_pass(int N, int C, const TM *__restri
         });
     };
 
-    double rr = 0.0;
+    double rr = 0.0, gg = 0.0;
     const int nsteps = (N + C - 1) / C;
     __syncthreads();  // lambda rows were just updated by other threads
     issue(0, min(C, N));
@@ -580,16 +588,18 @@ __device__ __forceinline__ double residual_pass(int N, int C, const TM *__restri
             if (k > 0) y += row_dot<NX>(Dk + BP, i, win + slot_of(sw, dk - 1, RL) * NXP, NX);
             if (k + 1 < N)
                 y += col_dot<NX>(ring + slot_of(sb, dk + 1, R) * ss + BP, i, win + slot_of(sw, dk + 1, RL) * NXP, NX);
-            const double r = gam[(int64_t)k * NX + i] - y;
+            const double gv = gam[(int64_t)k * NX + i];
+            const double r = gv - y;
             r64[(int64_t)k * NX + i] = r;
             rr += r * r;
+            gg += gv * gv;
         }
         sb += C;
         if (sb >= R) sb -= R;
         sw += C;
         if (sw >= RL) sw -= RL;
     }
-    return rr;
+    return ResNorms{rr, gg};
 }
 
 // Pointers of one problem inside the batch buffers.
@@ -640,6 +650,7 @@ __device__ __forceinline__ Outcome solve_problem(const SolveArgs &a, const Prob<
     int base = 0;        // refinement steps before that switch
     bool broke = false;  // last inner solve ended in a float breakdown (refinement only)
     double prev = INFINITY;
+    double gsame = q.gnorm;      // ||gamma|| summed like the last residual norm
     const double *rsrc = q.r64;  // where the next inner solve reads its right-hand side
     for (;;) {
         if (o.steps == 0 && a.use_lambda0 == 0) {
@@ -648,25 +659,31 @@ __device__ __forceinline__ Outcome solve_problem(const SolveArgs &a, const Prob<
             o.rnorm = q.gnorm;
         } else {
             // true residual r = gamma - S lambda in FP64
-            double rr64 = 0.0;
+            ResNorms nr{0.0, 0.0};
             if (NX > 0 && Cres >= 1) {
-                rr64 = residual_pass<TM, BLOCK, (NX > 0 ? NX : 2)>(N, Cres, q.B3, q.SDlo, q.SLlo, q.lam, q.gam,
-                                                                   q.r64, (double *)smem_raw);
+                nr = residual_pass<TM, BLOCK, (NX > 0 ? NX : 2)>(N, Cres, q.B3, q.SDlo, q.SLlo, q.lam, q.gam,
+                                                                 q.r64, (double *)smem_raw);
             } else {
                 bt_sweep<double, TM, BLOCK, NX>(
                     N, g64, q.B3, q.ks, q.SDlo, q.bp, q.B3 + q.bp, q.ks, q.SLlo, true, (double *)smem_raw,
                     [&](int row) { return q.lam[row]; },
                     [&](int row, double y, double) {
-                        const double r = q.gam[row] - y;
+                        const double gv = q.gam[row];
+                        const double r = gv - y;
                         q.r64[row] = r;
-                        rr64 += r * r;
+                        nr.rr += r * r;
+                        nr.gg += gv * gv;
                     });
             }
-            rr64 = block_sum<BLOCK>(rr64, red64);
-            o.rnorm = sqrt(rr64);
+            block_sum2<BLOCK>(nr.rr, nr.gg, red64);
+            o.rnorm = sqrt(nr.rr);
+            gsame = sqrt(nr.gg);
             rsrc = q.r64;
         }
-        if (o.steps == 0 && a.use_lambda0 == 2 && !(o.rnorm < q.gnorm)) {
+        // the start is kept only if its residual is strictly below ||gamma||,
+        // both norms summed in the same order (lambda0 = 0 gives a tie and
+        // falls back)
+        if (o.steps == 0 && a.use_lambda0 == 2 && !(o.rnorm < gsame)) {
             // a warm start that does not reduce the residual is replaced by zero
             for (int row = tid; row < n; row += BLOCK) {
                 q.lam[row] = 0.0;
@@ -686,7 +703,10 @@ __device__ __forceinline__ Outcome solve_problem(const SolveArgs &a, const Prob<
             break;
         }
         if (o.rnorm <= a.tol * q.gnorm) break;
-        if (o.steps > 0 && !a.refine) break;
+        if (o.steps > 0 && !a.refine) {
+            o.st = kInaccurate;
+            break;
+        }
         if (broke && !(o.rnorm < prev)) {
             o.st = kBreakdown;
             break;
@@ -785,8 +805,7 @@ __global__ __launch_bounds__(BLOCK, 2) void k_pcg2(SolveArgs a) {
     q.r64 = a.r64 + ov;
 
     Outcome o;
-    o.st = a.status[p];
-    if (o.st != kOk) {
+    if (build_failed(a.status[p])) {
         for (int row = tid; row < n; row += BLOCK) q.lam[row] = 0.0;
         if (tid == 0) {
             a.iters[p] = 0;

@@ -12,8 +12,16 @@ constexpr int kWave = 64;
 
 // Per-problem status codes (numerically equal to the public SSP_P_* values).
 constexpr int kOk = 0, kNotSpd = 1, kMaxIter = 2, kNonFinite = 3, kBreakdown = 4;
+// one inner solve without refinement met the tolerance on its recurrence
+// residual but not on the true FP64 residual
+constexpr int kInaccurate = 5;
 constexpr int kWarmFallback = 8;  // OR-ed flag: the warm start was replaced by zero
 constexpr int kPcFallback = 16;   // OR-ed flag: block-Jacobi took over after a float breakdown
+
+// A solve skips a problem only when its incoming status says the build found
+// a block that is not positive definite; every other code (an earlier
+// solve's iteration limit, breakdown or fallback flags) starts a fresh solve.
+__host__ __device__ inline bool build_failed(int st) { return (st & 7) == kNotSpd; }
 
 // Butterfly sum over the 64 lanes of a wavefront.  Every lane ends with the
 // same bits: each stage adds the same two operands on both partner lanes.

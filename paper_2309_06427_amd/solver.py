@@ -4,6 +4,7 @@ stream, every computation runs in the HIP library.
 from __future__ import annotations
 
 import ctypes as C
+import sys
 
 import numpy as np
 
@@ -41,11 +42,18 @@ class BatchSolver:
         self.off_nn, self.off_nu, self.off_uu, self.off_v = offs
 
     def close(self):
+        """Free the handle's device resources (synchronises the device)."""
         if getattr(self, "_h", None):
             _lib.load().ssp_batch_destroy(self._h)
             self._h = None
 
     def __del__(self):
+        # Never call into HIP while the interpreter shuts down: the runtime's
+        # own exit handlers may already have torn the device state down.
+        # Callers close handles explicitly; an unclosed handle at exit is
+        # reclaimed with the process.
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -128,6 +136,17 @@ class DeviceBatch:
         self.status = torch.zeros(P, dtype=torch.int32, device=dev)
         self.outer = torch.zeros(P, dtype=torch.int32, device=dev)
 
+    def close(self):
+        """Free the library handle now (the tensors go with the object)."""
+        self.solver.close()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+        return False
+
     def build(self, pc: str = "sym", precision: str = "fp32_refine64", stream=None):
         self.solver.build(pc, precision, self.A, self.B, self.Q, self.R, self.status, stream)
 
@@ -196,13 +215,11 @@ class DeviceBlockBatch(DeviceBatch):
 def solve(batch, pc: str = "sym", precision: str = "fp32_refine64", tol: float = 1e-6, max_iter: int = 0,
           lam0=None, device: int = 0) -> dict:
     """Build and solve a packed batch on the GPU; returns numpy results."""
-    db = DeviceBatch(batch, device)
-    db.build(pc, precision)
-    lam0_t = None
-    if lam0 is not None:
-        import torch
-        lam0_t = torch.from_numpy(np.ascontiguousarray(lam0, dtype=np.float64)).to(db.gamma.device)
-    db.solve(tol, max_iter, lam0_t)
-    out = db.results()
-    db.solver.close()
-    return out
+    with DeviceBatch(batch, device) as db:
+        db.build(pc, precision)
+        lam0_t = None
+        if lam0 is not None:
+            import torch
+            lam0_t = torch.from_numpy(np.ascontiguousarray(lam0, dtype=np.float64)).to(db.gamma.device)
+        db.solve(tol, max_iter, lam0_t)
+        return db.results()

@@ -11,6 +11,7 @@ the HIP library; torch only holds device memory.
 from __future__ import annotations
 
 import ctypes as C
+import sys
 import time
 
 import numpy as np
@@ -41,6 +42,9 @@ class WarmStartNet:
             self._h = None
 
     def __del__(self):
+        # no HIP call while the interpreter shuts down (see BatchSolver.__del__)
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:

@@ -52,5 +52,8 @@ def test_precision_sweep_ill_conditioned():
         assert ((out["status"] & ~16) == 0).all(), out["status"]
         assert out["relres"].max() <= 1e-6
     s32 = rows["fp32"]["out"]["status"]
-    assert set(np.unique(s32)) <= {0, 2, 4}
+    assert set(np.unique(s32)) <= {0, 2, 4, 5}
+    # one float solve reports INACCURATE (5) exactly when its true residual misses tol
+    r32 = rows["fp32"]["out"]["relres"]
+    assert np.array_equal(s32 == 5, (r32 > 1e-6) & ((s32 & 7) != 2) & ((s32 & 7) != 4))
     assert np.median(rows["fp32"]["err"]) >= np.median(rows["fp32_refine64"]["err"])
