@@ -59,7 +59,12 @@ def algorithmic_bytes(b, iters, outer, pc: str, precision: str, kernel: int = 0)
     so there are `outer` residual sweeps, `outer + 1` for the explicit one.
     cooperative kernel (3): the blocks are read once into LDS and stay there;
     each FP64 residual reads only the FP32 lo parts (none under FP64 storage).
+    scaled kernel (4): see scaled_bytes (blocks and vectors); this returns
+    their sum.
     """
+    if kernel == 4:
+        blk, vec = scaled_bytes(b, iters, outer, precision)
+        return blk + vec
     N = b.N.astype(np.float64)
     nx = b.nx.astype(np.float64)
     nn = nx * nx
@@ -79,6 +84,34 @@ def algorithmic_bytes(b, iters, outer, pc: str, precision: str, kernel: int = 0)
         inner = e * (it * (nbS + nbP) + st * nbP)
         sweeps = st + 1
     return inner + 8.0 * sweeps * (N * npk + (N - 1) * nn) + 16.0 * N * nx
+
+
+def scaled_bytes(b, iters, outer, precision: str):
+    """Bytes the scaled solve must move per problem, split into block bytes
+    and vector bytes.  Per PCG pass (iters + outer passes: one initial pass
+    per inner solve) it streams Oh_k (N - 1 blocks of nx^2 in the storage
+    type); the update pass reads and writes the six recurrence vectors
+    (12 e bytes per row), the initial pass reads the FP64 scaled residual and
+    writes x, r, u, w (8 + 4 e).  Each outer step reads Z_k twice (N full
+    blocks, the forward and back transform), forms the true residual from D
+    (packed) and L in FP64 (hi + lo, or FP64) except for a zero start's first
+    step, and moves FP64 vectors: residual 24 B per row (lambda, gamma in,
+    r out), transforms 16 + 8 + e + 16 B per row (r in, rh out; x in, lambda
+    read and written).  Once per solve: gamma read for its norm and lambda
+    zeroed (16 B per row)."""
+    N = b.N.astype(np.float64)
+    nx = b.nx.astype(np.float64)
+    nn = nx * nx
+    npk = nx * (nx + 1) / 2
+    e = 8.0 if precision == "fp64" else 4.0
+    it = iters.astype(np.float64)
+    st = outer.astype(np.float64)
+    rows = N * nx
+    passes = it + st
+    sweeps = np.maximum(st - 1, 0)  # zero start: the first outer step takes gamma as its residual
+    blk = e * (N - 1) * nn * passes + 2 * e * N * nn * st + 8.0 * (N * npk + (N - 1) * nn) * sweeps
+    vec = (rows * (12 * e * it + (8 + 4 * e) * st) + rows * (24.0 * sweeps + (40.0 + e) * st) + 16.0 * rows)
+    return blk, vec
 
 
 def load_nets(b, warm: str) -> list:
@@ -118,7 +151,7 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="batch4096_ragged")
-    ap.add_argument("--pc", default="sym", choices=["sym", "add", "bj"])
+    ap.add_argument("--pc", default="sym", choices=["sym", "add", "bj", "jacobi", "poly2", "poly3"])
     ap.add_argument("--precision", default=None, choices=[None, "fp64", "fp32", "fp32_refine64"])
     ap.add_argument("--threads", type=int, default=0)
     ap.add_argument("--lds", type=int, default=0)
@@ -308,6 +341,10 @@ def main() -> int:
         ok = ok and all(r["graph_matches_eager"] for r in runs.values())
     kern, coop_w, coop_g = db.solver.solve_kernel()  # the kernel the solves ran: 1 explicit, 2 fused, 3 cooperative
     bytes_solve = float(algorithmic_bytes(b, res["iters"], res["outer"], args.pc, precision, kern).sum())
+    split = None
+    if kern == 4:
+        bb, vb = scaled_bytes(b, res["iters"], res["outer"], precision)
+        split = {"block_bytes": float(bb.sum()), "vector_bytes": float(vb.sum())}
     rec = MEASURED_TRAFFIC.get((args.workload, args.pc, precision, args.kernel))
     traffic = rec[1] if rec and rec[0] == solve_sources_hash() else None
     solve_avg_s = float(plain["solve_ms"].mean()) / 1e3
@@ -317,13 +354,14 @@ def main() -> int:
     compare = None
     if not args.no_compare:
         compare = {}
-        for pc in ("bj", "add", "sym"):
+        for pc in ("jacobi", "bj", "add", "sym", "poly3"):
             db.build(pc, precision)
             db.solve(tol)
             r = db.results()
             compare[pc] = {"iters_mean": round(float(r["iters"].mean()), 3),
                            "outer_mean": round(float(r["outer"].mean()), 3),
-                           "max_relres": float(r["relres"].max())}
+                           "max_relres": float(r["relres"].max()),
+                           "pc_fallbacks": int(((r["status"] & 16) != 0).sum())}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -339,7 +377,10 @@ def main() -> int:
              "iters_mean": round(float(r["res"]["iters"].mean()), 3),
              "outer_mean": round(float(r["res"]["outer"].mean()), 3),
              "max_relres": float(r["res"]["relres"].max()),
-             "fallbacks": int(((r["res"]["status"] & 8) != 0).sum())}
+             "iters_p50": float(np.percentile(r["res"]["iters"], 50)),
+             "iters_p99": float(np.percentile(r["res"]["iters"], 99)),
+             "fallbacks": int(((r["res"]["status"] & 8) != 0).sum()),
+             "pc_fallbacks": int(((r["res"]["status"] & 16) != 0).sum())}
         if "graph_wall" in r:
             d["ms_per_step_graph"] = round(r["graph_wall"] * 1e3 / args.steps, 4)
             d["graph_matches_eager"] = r["graph_matches_eager"]
@@ -366,8 +407,10 @@ def main() -> int:
             "precision": precision,
             "tol": tol,
             "warm_start": "learned (per-knot network, zero fallback)" if head_mode == "learned" else "zero",
-            "kernel": {1: "explicit", 2: "fused", 3: "cooperative"}[kern],
+            "kernel": {1: "explicit", 2: "fused", 3: "cooperative", 4: "scaled"}[kern],
             "mapping": ({"own_knots_per_workgroup": coop_w, "workgroups": coop_g} if kern == 3 else
+                        dict(zip(("threads", "lds_bytes", "persistent_workgroups"), db.solver.scaled_mapping()[:3]))
+                        if kern == 4 else
                         [{"nx": m[0], "threads": m[1], "lds_bytes": m[2]} for m in mapping] if mapping else None),
             "timing": "hipGraph replay of the whole step" if args.graph else "eager launches",
             "step": ("build (FP64 assembly) + network inference + solve" if head_mode == "learned"
@@ -379,10 +422,11 @@ def main() -> int:
             "learned": summary(runs["learned"]) if "learned" in runs else None,
             "solve_only_solves_per_s": round(b.P / solve_avg_s, 2),
             "solve_algorithmic_bytes": bytes_solve,
+            "solve_bytes_split": split,
             "compare": compare,
         },
         "roofline": {
-            "kernel": {1: "k_pcg", 2: "k_pcg2", 3: "k_coop"}[kern],
+            "kernel": {1: "k_pcg", 2: "k_pcg2", 3: "k_coop", 4: "k_pcg3"}[kern],
             "bound": "hbm",
             "achieved": round(achieved, 2),
             "peak": HBM_PEAK_GBS,
@@ -395,6 +439,10 @@ def main() -> int:
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+    # free the library handles before interpreter shutdown
+    for net in nets:
+        net.close()
+    db.close()
     return 0
 
 

@@ -67,9 +67,13 @@ enum {
 };
 
 typedef enum {
-    SSP_PC_BLOCK_JACOBI = 0, /* Phi^-1 = block-diag(D_k^-1)                      */
-    SSP_PC_STAIR_ADD = 1,    /* Phi^-1 = (Psi_l^-1 + Psi_r^-1) / 2               */
-    SSP_PC_SYM_STAIR = 2     /* Phi^-1 = Psi_l^-1 + Psi_r^-1 - D^-1              */
+    SSP_PC_BLOCK_JACOBI = 0, /* Phi^-1 = block-diag(D_k^-1)          Eq. (jacobi)   */
+    SSP_PC_STAIR_ADD = 1,    /* Phi^-1 = (Psi_l^-1 + Psi_r^-1) / 2   Sec. III       */
+    SSP_PC_SYM_STAIR = 2,    /* Phi^-1 = Psi_l^-1 + Psi_r^-1 - D^-1  Sec. IV        */
+    SSP_PC_SCALAR_JACOBI = 3, /* Phi^-1 = diag(S)^-1                 Eq. (jacobi)   */
+    SSP_PC_NEUMANN2 = 4,     /* Phi^-1 = (I + K + K^2) D^-1, K = D^-1 (D - S):     */
+    SSP_PC_NEUMANN3 = 5      /* (I + K + K^2 + K^3) D^-1; Eq. (polynomial_precon)  */
+                             /* with Psi = D (degree 1 is SSP_PC_SYM_STAIR)        */
 } ssp_precon;
 
 typedef enum {
@@ -101,14 +105,26 @@ ssp_status ssp_layout(const ssp_batch *b, int64_t *off_nn, int64_t *off_nu, int6
  * then store them in the precision `prec` will solve in (FP32 storage keeps
  * the FP64 remainder of S as a second FP32 array for the refinement
  * residual).  A, Q, B, R: device FP64, layout of ssp_layout.  prob_status:
- * device int32[nprob], overwritten with SSP_P_OK or SSP_P_NOT_SPD. */
+ * device int32[nprob], overwritten with SSP_P_OK or SSP_P_NOT_SPD.
+ *
+ * The build also decides which solve runs (see ssp_set_mapping, kernel 4):
+ * the scaled solve, for which it additionally writes Z_k, the lower
+ * Cholesky factor of D_k^-1, and Oh_k = Z_k^T L_k Z_{k-1}, the off-diagonal
+ * blocks of Z^T S Z = I + Oh (Z = blockdiag(Z_k)).  In that basis every
+ * preconditioner above except scalar Jacobi is a polynomial in Oh (block-
+ * Jacobi Z Z^T, symmetric stair Z (I - Oh) Z^T, additive stair
+ * Z (I - Oh/2) Z^T, Neumann degree m Z (sum_{i<=m} (-Oh)^i) Z^T): the same
+ * operators, applied while streaming one nx x nx block per knot.  The
+ * polynomial preconditioners SSP_PC_NEUMANN2/3 exist only there, and need
+ * every problem's nx in {6, 14, 26, 36} with nu <= nx (else SSP_ERR_ARG). */
 ssp_status ssp_build(ssp_batch *b, ssp_precon pc, ssp_precision prec, const double *A,
                      const double *B, const double *Q, const double *R, int32_t *prob_status,
                      void *stream);
 
 /* Build from a symmetric block-tridiagonal matrix given by its blocks
  * instead of the per-knot dynamics: D holds S[k][k] (k = 0..N-1) and Lsub
- * holds S[k][k-1] (k = 1..N-1; block 0 is not read), both device FP64,
+ * holds S[k][k-1] (k = 1..N-1; block 0 is not read), both device FP64
+ * (preconditioners 0 - 3 only; not with kernel 4),
  * nx x nx row-major blocks at the problem's off_nn offsets of ssp_layout
  * (the layout of Q).  Each D_k is used as (D_k + D_k^T) / 2.  Stores S,
  * D_k^-1 and the preconditioner pc (Sec. II-C, III, IV) in the precision of
@@ -160,7 +176,10 @@ ssp_status ssp_solve_outer(const ssp_batch *b, int32_t *outer, void *stream);
  * off = L_k, FP32 storage returns hi + lo), which = 1 -> Phi^-1 (diag =
  * D_k^-1, off = Phi^-1[k][k-1], zero for block-Jacobi), which = 2 -> S as the
  * PCG reads it (the FP32 hi part only under FP32 storage).  which = 1
- * computes the explicit stair blocks if the last build did not. */
+ * computes the explicit stair blocks if the last build did not (SSP_ERR_ARG
+ * for the polynomial preconditioners, which are not block tridiagonal);
+ * which = 3 -> the scaled basis of the last build (diag = Z_k, off = Oh_k;
+ * SSP_ERR_STATE if it was not built). */
 ssp_status ssp_export(ssp_batch *b, int which, double *diag, double *off, void *stream);
 
 /* Kernel-mapping knobs of the batched PCG kernel (the autotuner sets them):
@@ -176,7 +195,14 @@ ssp_status ssp_export(ssp_batch *b, int which, double *diag, double *off, void *
  *       workgroup per problem;
  *   3 = the cooperative solve for a batch of one problem of any length whose
  *       grid fits (else as 0): the same method with the problem's knots
- *       spread over the grid, four per workgroup, and grid-wide barriers.
+ *       spread over the grid, four per workgroup, and grid-wide barriers;
+ *   4 = the scaled solve: one persistent grid for the whole batch, problems
+ *       taken largest first from a device queue, each PCG pass streaming the
+ *       Oh_k blocks of the congruence basis (see ssp_build).  With kernel 0
+ *       the build chooses it for the polynomial preconditioners and for
+ *       block-Jacobi and both stairs under FP32 storage (except a single
+ *       problem of N >= 24 knots, which runs the cooperative solve).
+ * The choice takes effect at the next build.
  * The fused kernel is built for 128 and 256 threads and for knots that fit
  * its LDS rings; otherwise the explicit kernel runs.  Returns SSP_ERR_ARG for
  * an unknown value or a budget that cannot hold one knot of the largest nx. */
@@ -264,9 +290,22 @@ ssp_status ssp_set_group_mapping(ssp_batch *b, int32_t nx, int32_t threads, int3
 ssp_status ssp_get_mapping(const ssp_batch *b, int32_t max_groups, int32_t *nx, int32_t *threads,
                            int32_t *lds_bytes, float *tuned_ms, int32_t *ngroups);
 
+/* Mapping of the scaled solve (kernel 4): threads 128 or 256 and the LDS
+ * budget per workgroup (0 = the largest pipeline step of every state size);
+ * 0, 0 restores the defaults.  ssp_autotune tunes both when the last build
+ * chose the scaled solve.  SSP_ERR_ARG if some state size of the batch gets
+ * no pipeline step from the budget. */
+ssp_status ssp_set_scaled_mapping(ssp_batch *b, int32_t threads, int32_t lds_bytes);
+/* The scaled solve's mapping: threads, LDS bytes, workgroups of the
+ * persistent grid on this device (min(resident workgroups, nprob)) and the
+ * autotuner's best time in ms (0 if not tuned); any pointer may be NULL. */
+ssp_status ssp_get_scaled_mapping(const ssp_batch *b, int32_t *threads, int32_t *lds_bytes, int32_t *grid,
+                                  float *tuned_ms);
+
 /* The kernel the last ssp_solve (or ssp_autotune) of this batch enqueued:
  * 1 explicit two-sweep, 2 fused (one workgroup per problem), 3 cooperative
- * (one problem over the whole grid); 0 before any solve.  *W and *G (may be
+ * (one problem over the whole grid), 4 scaled (persistent grid); 0 before
+ * any solve.  *W and *G (may be
  * NULL) receive the cooperative plan: own knots per workgroup and
  * workgroups (0 for the other kernels). */
 ssp_status ssp_solve_kernel(const ssp_batch *b, int32_t *kernel, int32_t *W, int32_t *G);

@@ -14,10 +14,11 @@ SSP_OK, SSP_ERR_ARG, SSP_ERR_ALLOC, SSP_ERR_HIP, SSP_ERR_STATE = range(5)
 SSP_P_OK, SSP_P_NOT_SPD, SSP_P_MAXITER, SSP_P_NONFINITE, SSP_P_BREAKDOWN, SSP_P_INACCURATE = range(6)
 SSP_P_WARM_FALLBACK = 8
 SSP_P_PC_FALLBACK = 16
-SSP_PC_BLOCK_JACOBI, SSP_PC_STAIR_ADD, SSP_PC_SYM_STAIR = range(3)
+SSP_PC_BLOCK_JACOBI, SSP_PC_STAIR_ADD, SSP_PC_SYM_STAIR, SSP_PC_SCALAR_JACOBI, SSP_PC_NEUMANN2, SSP_PC_NEUMANN3 = range(6)
 SSP_FP64, SSP_FP32, SSP_FP32_REFINE64 = range(3)
 
-PC = {"bj": SSP_PC_BLOCK_JACOBI, "add": SSP_PC_STAIR_ADD, "sym": SSP_PC_SYM_STAIR}
+PC = {"bj": SSP_PC_BLOCK_JACOBI, "add": SSP_PC_STAIR_ADD, "sym": SSP_PC_SYM_STAIR,
+      "jacobi": SSP_PC_SCALAR_JACOBI, "poly2": SSP_PC_NEUMANN2, "poly3": SSP_PC_NEUMANN3}
 PREC = {"fp64": SSP_FP64, "fp32": SSP_FP32, "fp32_refine64": SSP_FP32_REFINE64}
 
 # every symbol the header declares: name -> (restype, argtypes)
@@ -49,6 +50,8 @@ SIGNATURES = {
     "ssp_set_group_mapping": (C.c_int, [_vp, _i32, _i32, _i32]),
     "ssp_get_mapping": (C.c_int, [_vp, _i32, _pi32, _pi32, _pi32, C.POINTER(_f), _pi32]),
     "ssp_solve_kernel": (C.c_int, [_vp, _pi32, _pi32, _pi32]),
+    "ssp_set_scaled_mapping": (C.c_int, [_vp, _i32, _i32]),
+    "ssp_get_scaled_mapping": (C.c_int, [_vp, _pi32, _pi32, _pi32, C.POINTER(_f)]),
     "ssp_copy_bytes": (C.c_int, [_vp, _vp, _i64, _vp]),
     "ssp_status_str": (C.c_char_p, [C.c_int]),
     "ssp_last_error": (C.c_char_p, []),

@@ -276,7 +276,7 @@ __global__ __launch_bounds__(T) void k_build_phi(BuildArgs a) {
     const int64_t os = a.off_blk[p] + (int64_t)k * bs;
     const TM *blk = (const TM *)a.B3 + a.off_b3[p] + (int64_t)k * ks;  // D_k (packed), L_k, D_k^-1 (packed)
     double *Di = sm, *Lm = Di + nn, *Dp = Lm + nn, *T1 = Dp + nn, *T2 = T1 + nn;
-    if (k == 0 || a.pc == 0) {
+    if (k == 0 || (a.pc != 1 && a.pc != 2)) {  // block-diagonal preconditioners (and k = 0)
         for (int e = threadIdx.x; e < nn; e += T) ((TM *)a.PM)[os + e] = (TM)0;
         return;
     }
@@ -314,6 +314,26 @@ __global__ void k_export(BuildArgs a, int which, const TM *hi, const float *lo, 
             v = (double)hi[a.off_blk[p] + (int64_t)k * bs + e];
         }
         dst[o + e] = v;
+    }
+}
+
+// Scalar Jacobi (Eq. (jacobi) with Phi = diag(S)): replace the stored D_k^-1
+// of every knot by diag(1 / (D_k)_ii), (D_k)_ii read as stored hi + lo.  One
+// workgroup per knot.
+template <typename TM>
+__global__ void k_jacobi_diag(BuildArgs a) {
+    int p, k;
+    knot_of(a, p, k);
+    const int nx = a.nx[p], bs = block_stride(nx, sizeof(TM)), bp = packed_stride(nx, sizeof(TM));
+    TM *blk = (TM *)a.B3 + a.off_b3[p] + (int64_t)k * (2 * bp + bs);
+    const float *lo = a.SDlo ? a.SDlo + a.off_pk[p] + (int64_t)k * bp : nullptr;
+    for (int e = threadIdx.x; e < nx * nx; e += T) {
+        const int r = e / nx, c = e - r * nx;
+        if (r > c) continue;
+        const int pi = packed_index(r, c, nx);
+        double v = 0.0;
+        if (r == c) v = 1.0 / ((double)blk[pi] + (lo ? (double)lo[pi] : 0.0));
+        blk[bp + bs + pi] = (TM)v;
     }
 }
 
@@ -386,6 +406,15 @@ hipError_t launch_export(const BuildArgs &a, int which, const void *hi, const fl
     else
         hipLaunchKernelGGL(k_export<double>, dim3((unsigned)knots), dim3(T), 0, s, a, which, (const double *)hi, lo,
                            dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_jacobi_diag(const BuildArgs &a, int64_t knots, bool fp32, hipStream_t s) {
+    if (knots == 0) return hipSuccess;
+    if (fp32)
+        hipLaunchKernelGGL(k_jacobi_diag<float>, dim3((unsigned)knots), dim3(T), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_jacobi_diag<double>, dim3((unsigned)knots), dim3(T), 0, s, a);
     return hipGetLastError();
 }
 

@@ -14,6 +14,11 @@
 // SPD inverses are Gauss-Jordan eliminations without pivoting: for an SPD
 // matrix every pivot is a positive Schur-complement diagonal, so a
 // non-positive pivot flags the matrix as not positive definite.
+//
+// Scaled basis (when asked for): Z_k, the lower Cholesky factor of D_k^-1
+// (D_k^-1 = Z_k Z_k^T), in phase 2, and in phase 3 the off-diagonal blocks
+// Oh_k = Z_k^T L_k Z_{k-1} of the congruence Z^T S Z = I + Oh
+// (Z = blockdiag(Z_k)), which the scaled solve streams instead of D, L, D^-1.
 #include "ssp_device.h"
 #include "ssp_host.h"
 #include "ssp_sweep.h"
@@ -215,6 +220,45 @@ __device__ __forceinline__ bool gj_inverse_blocked(double (&a)[NX], int i, bool 
     return ok;
 }
 
+// Lower Cholesky factor of the SPD matrix whose row i this lane holds in a[]
+// (every lane of the knot holds one row), in place: afterwards a[j] is
+// Z[i][j] (zero above the diagonal) with A = Z Z^T.  Right-looking
+// elimination: at step j the pivot lane publishes its row of the current
+// Schur complement (for a symmetric matrix that row is also the pivot
+// column), every lower row scales its entry j by 1 / sqrt(pivot) and updates
+// its entries right of j.  M: the knot's LDS buffer (pivot row).  Returns
+// false if a pivot is not positive.
+template <int NX>
+__device__ __forceinline__ bool chol_rows(double (&a)[NX], int i, bool row, double *M) {
+    constexpr int NP = Lane<NX>::NP;
+    double *prow = M + NX * NP;
+    bool ok = true;
+    static_for<0, NX>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        if (row && i == j) lds_put_row<NX>(prow, a);
+        wave_sync();
+        const double piv = prow[j];
+        if (!(piv > 0.0)) ok = false;
+        const double rs = 1.0 / sqrt(piv);
+        if (i > j) {
+            const double l = a[j] * rs;
+            a[j] = l;
+            static_for<j + 1, NX>([&](auto kc) {
+                constexpr int k = decltype(kc)::value;
+                a[k] = fma(-l * rs, prow[k], a[k]);
+            });
+        } else if (i == j) {
+            a[j] = piv * rs;
+        }
+        wave_sync();  // the pivot row is read before the next one is written
+    });
+    static_for<0, NX>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        if (j > i) a[j] = 0.0;
+    });
+    return ok;
+}
+
 // out = x M (M: n x NX in LDS, rows of pitch NP), x: this lane's row.
 template <int NX>
 __device__ __forceinline__ void row_times(const double (&x)[NX], const double *M, int n, double (&out)[NX]) {
@@ -392,10 +436,70 @@ __global__ __launch_bounds__(kThreads) void k_build_asm_nx(BuildArgs a, const in
     }
     symmetrise<NX>(d, i, ln.row, M);  // exactly symmetric before the upper triangle is kept
     if (ln.row) store_split_packed_row<TM, NX>(blk, a.SDlo ? a.SDlo + od : nullptr, i, d);
-    const bool ok = gj_inverse_blocked<NX, kGjBlock>(d, i, ln.row, NX, M);
+    bool ok = gj_inverse_blocked<NX, kGjBlock>(d, i, ln.row, NX, M);
     symmetrise<NX>(d, i, ln.row, M);
     if (ln.row) store_split_packed_row<TM, NX>(blk + bp + bs, (float *)nullptr, i, d);
+    if (a.Zs) {
+        // scaled basis: Z_k = chol(D_k^-1), stored full (zeros above the
+        // diagonal) in the storage type and in FP64 for phase 3
+        ok = chol_rows<NX>(d, i, ln.row, M) && ok;
+        if (ln.row) {
+            store_split_row<TM, NX>((TM *)a.Zs + ol + i * NX, (float *)nullptr, d, 1.0);
+            store_row<NX>(a.Zw + a.off_nn[p] + (int64_t)k * nn + i * NX, NX, d);
+        }
+    }
     if (ln.row && !ok) atomicOr(a.status + p, kNotSpd);
+}
+
+// Phase 3 of the scaled basis: Oh_k = Z_k^T L_k Z_{k-1} (k >= 1, Oh_0 = 0)
+// in FP64 from Z (FP64 workspace) and L_k (storage hi + FP32 remainder, or
+// FP64), stored in the storage type.  First X = L_k Z_{k-1} (rows of
+// Z_{k-1} in LDS, lane i's row of L_k), then row i of Z_k^T X = sum_l
+// Z_k[l][i] X[l][:] (rows of X in LDS, column i of Z_k from memory).
+template <typename TM, int NX>
+__global__ __launch_bounds__(kThreads) void k_build_ohat_nx(BuildArgs a, const int2 *items) {
+    constexpr int KN = (kThreads / 64) * Lane<NX>::KW;
+    constexpr int NP = Lane<NX>::NP;
+    __shared__ __align__(16) double sm[KN * knot_lds_doubles<NX>()];
+    const int2 it = items[blockIdx.x];
+    const int p = it.x, N = a.N[p];
+    const Lane<NX> ln = lane_of<NX>(it.y, N);
+    double *M = sm + ln.g * knot_lds_doubles<NX>();
+    const int nn = NX * NX, k = ln.knot, i = ln.i;
+    const int bs = block_stride(NX, sizeof(TM)), bp = packed_stride(NX, sizeof(TM));
+    const int64_t ol = a.off_blk[p] + (int64_t)k * bs;
+    const bool prev = ln.row && k > 0;
+    double x[NX], t[NX];
+    // rows of Z_{k-1}
+    wave_sync();
+    if (prev) store_row<NX>(M + i * NP, NX, *(const double(*)[NX])(a.Zw + a.off_nn[p] + (int64_t)(k - 1) * nn + i * NX));
+    wave_sync();
+    // row i of L_k in FP64
+    if (prev) {
+        const TM *Lk = (const TM *)a.B3 + a.off_b3[p] + (int64_t)k * (2 * bp + bs) + bp + i * NX;
+        const float *lo = a.SLlo ? a.SLlo + ol + i * NX : nullptr;
+        static_for<0, NX>([&](auto jc) {
+            constexpr int j = decltype(jc)::value;
+            x[j] = (double)Lk[j] + (lo ? (double)lo[j] : 0.0);
+        });
+    } else {
+        static_for<0, NX>([&](auto jc) { x[decltype(jc)::value] = 0.0; });
+    }
+    row_times<NX>(x, M, NX, t);  // row i of X = L_k Z_{k-1}
+    wave_sync();
+    if (ln.row) lds_put_row<NX>(M + i * NP, t);
+    wave_sync();
+    // column i of Z_k
+    if (ln.row) {
+        const double *Zk = a.Zw + a.off_nn[p] + (int64_t)k * nn;
+        static_for<0, NX>([&](auto lc) {
+            constexpr int l = decltype(lc)::value;
+            x[l] = Zk[l * NX + i];
+        });
+    }
+    row_times<NX>(x, M, NX, t);  // row i of Z_k^T X
+    if (!prev) static_for<0, NX>([&](auto jc) { t[decltype(jc)::value] = 0.0; });  // Oh_0 = 0
+    if (ln.row) store_split_row<TM, NX>((TM *)a.OH + ol + i * NX, (float *)nullptr, t, 1.0);
 }
 
 template <int NX>
@@ -409,6 +513,26 @@ static hipError_t launch_nx(const BuildArgs &a, const int2 *items, int nitems, b
     else
         hipLaunchKernelGGL((k_build_asm_nx<double, NX>), dim3(nitems), dim3(kThreads), 0, s, a, items);
     return hipGetLastError();
+}
+
+template <int NX>
+static hipError_t launch_ohat_nx(const BuildArgs &a, const int2 *items, int nitems, bool fp32, hipStream_t s) {
+    if (nitems == 0) return hipSuccess;
+    if (fp32)
+        hipLaunchKernelGGL((k_build_ohat_nx<float, NX>), dim3(nitems), dim3(kThreads), 0, s, a, items);
+    else
+        hipLaunchKernelGGL((k_build_ohat_nx<double, NX>), dim3(nitems), dim3(kThreads), 0, s, a, items);
+    return hipGetLastError();
+}
+
+hipError_t launch_build_ohat(int cls, const BuildArgs &a, const int2 *items, int nitems, bool fp32, hipStream_t s) {
+    switch (cls) {
+        case 0: return launch_ohat_nx<6>(a, items, nitems, fp32, s);
+        case 1: return launch_ohat_nx<14>(a, items, nitems, fp32, s);
+        case 2: return launch_ohat_nx<26>(a, items, nitems, fp32, s);
+        case 3: return launch_ohat_nx<36>(a, items, nitems, fp32, s);
+    }
+    return hipErrorInvalidValue;
 }
 
 const int kBuildSizes[kBuildClasses] = {6, 14, 26, 36};

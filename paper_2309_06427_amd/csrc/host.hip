@@ -20,6 +20,15 @@ thread_local std::string ssp_host::g_last_error = "no error";
 
 namespace {
 
+void free_scaled(ssp_batch *b) {
+    for (void *p : {b->Zs, b->OH, (void *)b->Zw, (void *)b->rh64})
+        if (p) (void)hipFree(p);
+    b->Zs = b->OH = nullptr;
+    b->Zw = b->rh64 = nullptr;
+    b->have_scaled = false;
+    b->scaled = false;
+}
+
 void free_storage(ssp_batch *b) {
     for (void *p : {b->B3, b->PM, (void *)b->SDlo, (void *)b->SLlo, b->work})
         if (p) (void)hipFree(p);
@@ -27,6 +36,65 @@ void free_storage(ssp_batch *b) {
     b->SDlo = b->SLlo = nullptr;
     b->have_storage = false;
     b->m_valid = false;
+    free_scaled(b);
+}
+
+// Storage of the scaled basis for the current storage precision.
+ssp_status alloc_scaled(ssp_batch *b) {
+    if (b->have_scaled) return SSP_OK;
+    const size_t elem = b->fp32 ? sizeof(float) : sizeof(double);
+    const size_t nn = (size_t)(b->fp32 ? b->off_blk32 : b->off_blk64)[b->P];
+    if (hipMalloc(&b->Zs, std::max<size_t>(nn, 1) * elem) != hipSuccess ||
+        hipMalloc(&b->OH, std::max<size_t>(nn, 1) * elem) != hipSuccess ||
+        dalloc(&b->Zw, (size_t)b->off_nn[b->P]) != hipSuccess || dalloc(&b->rh64, (size_t)b->off_v[b->P]) != hipSuccess) {
+        free_scaled(b);
+        g_last_error = "hipMalloc of scaled-basis storage failed";
+        return SSP_ERR_ALLOC;
+    }
+    b->have_scaled = true;
+    return SSP_OK;
+}
+
+// Horner steps of the preconditioner polynomial in the scaled basis and
+// the coefficient of each step.
+int poly_steps(ssp_precon pc) {
+    switch (pc) {
+        case SSP_PC_BLOCK_JACOBI: return 0;
+        case SSP_PC_STAIR_ADD:
+        case SSP_PC_SYM_STAIR: return 1;
+        case SSP_PC_NEUMANN2: return 2;
+        case SSP_PC_NEUMANN3: return 3;
+        default: return 0;
+    }
+}
+
+// every problem has a compiled state size (the register-resident assembly,
+// which also builds the scaled basis, and the scaled solve exist for those)
+bool scaled_possible(const ssp_batch *b) {
+    for (int p = 0; p < b->P; ++p) {
+        bool cls = false;
+        for (int c = 0; c < ssp::kBuildClasses; ++c) cls = cls || (b->nx[p] == ssp::kBuildSizes[c] && b->nu[p] <= b->nx[p]);
+        if (!cls) return false;
+    }
+    return true;
+}
+
+// LDS budget of the scaled kernel: the largest step of every state size in
+// the batch (or the tuned / set budget), at least what the FP64 residual's
+// staged fallback needs.
+int scaled_lds(const ssp_batch *b, int threads, int m) {
+    int need = 0;
+    for (const auto &g : b->groups) need = std::max(need, ssp::pcg3_lds(g.nx, b->fp32, threads, m));
+    int l = b->s3_lds > 0 ? b->s3_lds : need;
+    l = std::max(l, ssp::bt_sweep_min_lds(b->nx_max, true, 8));
+    return std::min(l, ssp::kFusedLdsCap);
+}
+
+// the scaled kernel can run every state size of the batch with this budget
+bool scaled_fits(const ssp_batch *b, int threads, int lds, int m) {
+    for (const auto &g : b->groups)
+        if (ssp::pcg3_steps_for(g.nx, b->fp32, threads, lds, m) < 1) return false;
+    return true;
 }
 
 ssp_status alloc_storage(ssp_batch *b, bool fp32) {
@@ -125,6 +193,8 @@ ssp::BuildArgs build_args(const ssp_batch *b) {
     a.SDlo = b->fp32 ? b->SDlo : nullptr;
     a.SLlo = b->fp32 ? b->SLlo : nullptr;
     a.PM = b->PM;
+    a.Zs = a.OH = nullptr;
+    a.Zw = nullptr;
     a.pc = (int)b->pc;
     a.mx = std::max(b->nx_max, b->nu_max);
     return a;
@@ -162,7 +232,9 @@ ssp::SolveArgs solve_args(const ssp_batch *b, double rel_tol, int32_t max_iter, 
     a.B3 = b->B3;
     a.SDlo = b->fp32 ? b->SDlo : nullptr;
     a.SLlo = b->fp32 ? b->SLlo : nullptr;
-    a.pc = (int)b->pc;
+    // the classic kernels apply scalar Jacobi as block-diagonal (its stored
+    // D^-1 blocks are diagonal); the scaled kernel reads poly / pc_c below
+    a.pc = b->pc == SSP_PC_SCALAR_JACOBI ? (int)SSP_PC_BLOCK_JACOBI : (int)b->pc;
     a.gamma = gamma;
     a.lambda = lambda;
     a.use_lambda0 = use_lambda0;
@@ -178,7 +250,33 @@ ssp::SolveArgs solve_args(const ssp_batch *b, double rel_tol, int32_t max_iter, 
     a.work = b->work;
     a.r64 = b->r64;
     a.tot_v = b->off_v[b->P];
+    a.OH = b->OH;
+    a.Z = b->Zs;
+    a.rh64 = b->rh64;
+    a.queue = b->dqueue;
+    a.nprob = b->P;
+    a.poly = poly_steps(b->pc);
+    a.pc_c = b->pc == SSP_PC_STAIR_ADD ? 0.5 : 1.0;
     return a;
+}
+
+// The scaled solve: refinement in FP64 around the float inner solve, or
+// FP64 restarts from the true residual under FP64 storage.
+ssp_status launch_scaled(ssp_batch *b, ssp::SolveArgs a, hipStream_t s) {
+    const int t = b->s3_threads;
+    a.lds_bytes = scaled_lds(b, t, a.poly);
+    if (!scaled_fits(b, t, a.lds_bytes, a.poly)) {
+        g_last_error = "scaled solve: the LDS budget holds no pipeline step of some state size";
+        return SSP_ERR_ARG;
+    }
+    a.refine = b->prec == SSP_FP32 ? 0 : 1;
+    a.max_outer = a.refine ? 5 : 1;
+    a.theta = 0.5;
+    a.tau_min = b->prec == SSP_FP64 ? 1e-15 : 1e-6;
+    SSP_HIP(ssp::launch_fill_i32((int32_t *)b->dqueue, 0, 1, s));
+    SSP_HIP(ssp::launch_pcg3(a, b->fp32, t, 0, s));
+    b->last_kernel = 4;
+    return SSP_OK;
 }
 
 // Candidate LDS budgets of the autotuner for a group at `threads`: the
@@ -228,6 +326,78 @@ ssp_status launch_groups(ssp_batch *b, ssp::SolveArgs a, int which, hipStream_t 
         }
     }
     return SSP_OK;
+}
+
+// Autotuner of the scaled solve: workgroup size and LDS budget (the budget
+// sets the knots per pipeline step of every state size and the workgroups
+// resident per CU).  Each candidate solves the whole batch once untimed and
+// once timed; the fastest is kept and the batch is solved once more with it.
+ssp_status autotune_scaled(ssp_batch *b, double rel_tol, const double *gamma, double *lambda, int32_t *iters,
+                           double *relres, int32_t *prob_status, void *stream) {
+    DevGuard dg(b->device);
+    hipStream_t s = (hipStream_t)stream;
+    int32_t *st0 = nullptr;
+    if (dalloc(&st0, (size_t)b->P) != hipSuccess) {
+        g_last_error = "hipMalloc of status copy failed";
+        return SSP_ERR_ALLOC;
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ssp_status rc = SSP_OK;
+    hipError_t e;
+    auto fail = [&](hipError_t err, const char *what) {
+        if (rc == SSP_OK) rc = hip_fail(err, what);
+    };
+    if ((e = hipMemcpyAsync(st0, prob_status, sizeof(int32_t) * b->P, hipMemcpyDeviceToDevice, s))) fail(e, "status copy");
+    if (rc == SSP_OK && ((e = hipEventCreate(&e0)) || (e = hipEventCreate(&e1)))) fail(e, "hipEventCreate");
+    const ssp::SolveArgs a = solve_args(b, rel_tol, 0, gamma, lambda, 0, iters, relres, prob_status);
+    const int m = poly_steps(b->pc);
+    int best_t = 0, best_l = 0;
+    float best = 0.0f;
+    for (int t : {256, 128}) {
+        b->s3_threads = t;
+        b->s3_lds = 0;
+        const int base = scaled_lds(b, t, m);
+        for (double f : {1.0, 0.8, 0.65, 0.5}) {
+            const int l = std::max((int)(base * f) / 16 * 16, ssp::bt_sweep_min_lds(b->nx_max, true, 8));
+            if (!scaled_fits(b, t, l, m) || (f < 1.0 && l >= base)) continue;
+            b->s3_lds = l;
+            float ms = 0.0f;
+            for (int rep = 0; rep < 2 && rc == SSP_OK; ++rep) {
+                if ((e = hipMemcpyAsync(prob_status, st0, sizeof(int32_t) * b->P, hipMemcpyDeviceToDevice, s))) {
+                    fail(e, "status restore");
+                    break;
+                }
+                if ((e = hipEventRecord(e0, s))) fail(e, "hipEventRecord");
+                if (rc == SSP_OK && (rc = launch_scaled(b, a, s)) != SSP_OK) break;
+                if ((e = hipEventRecord(e1, s)) || (e = hipEventSynchronize(e1)) || (e = hipEventElapsedTime(&ms, e0, e1)))
+                    fail(e, "autotune timing");
+            }
+            if (rc != SSP_OK) break;
+            if (best_t == 0 || ms < best) {
+                best = ms;
+                best_t = t;
+                best_l = l;
+            }
+        }
+        if (rc != SSP_OK) break;
+    }
+    if (best_t) {
+        b->s3_threads = best_t;
+        b->s3_lds = best_l;
+        b->s3_tuned_ms = best;
+    } else {
+        b->s3_threads = 256;
+        b->s3_lds = 0;
+    }
+    if (rc == SSP_OK &&
+        (e = hipMemcpyAsync(prob_status, st0, sizeof(int32_t) * b->P, hipMemcpyDeviceToDevice, s)))
+        fail(e, "status restore");
+    if (rc == SSP_OK) rc = launch_scaled(b, a, s);
+    if (rc == SSP_OK && (e = hipStreamSynchronize(s))) fail(e, "hipStreamSynchronize");
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(st0);
+    return rc;
 }
 
 }  // namespace
@@ -415,7 +585,8 @@ ssp_status ssp_batch_create(int32_t nprob, const int32_t *N, const int32_t *nx, 
     if (rc == SSP_OK) {
         const size_t nn = b->off_nn[nprob], uu = b->off_uu[nprob], nv = b->off_v[nprob];
         if (dalloc(&b->Qinv, nn) != hipSuccess || dalloc(&b->Rinv, uu) != hipSuccess ||
-            dalloc(&b->r64, nv) != hipSuccess || dalloc(&b->douter, (size_t)nprob) != hipSuccess)
+            dalloc(&b->r64, nv) != hipSuccess || dalloc(&b->douter, (size_t)nprob) != hipSuccess ||
+            dalloc(&b->dqueue, 1) != hipSuccess)
             rc = SSP_ERR_ALLOC;
     }
     if (rc != SSP_OK) {
@@ -442,7 +613,7 @@ ssp_status ssp_batch_destroy(ssp_batch *b) {
                         (void *)b->ditems, (void *)b->dgeneric, (void *)b->doff_nn, (void *)b->doff_nu, (void *)b->doff_uu, (void *)b->doff_v,
                         (void *)b->dkoff, (void *)b->doff_blk32, (void *)b->doff_blk64, (void *)b->doff_b3_32, (void *)b->doff_b3_64,
                         (void *)b->doff_pk32, (void *)b->dbar, (void *)b->drec, (void *)b->dwtag, (void *)b->Qinv, (void *)b->Rinv,
-                        (void *)b->r64, (void *)b->douter})
+                        (void *)b->r64, (void *)b->douter, (void *)b->dqueue})
             if (p) (void)hipFree(p);
     }
     delete b;
@@ -463,7 +634,7 @@ ssp_status ssp_set_mapping(ssp_batch *b, int32_t threads, int32_t lds_bytes, int
     if (!b) return SSP_ERR_ARG;
     if (threads != 64 && threads != 128 && threads != 256 && threads != 512) return SSP_ERR_ARG;
     if (lds_bytes < 0 || lds_bytes > 160 * 1024) return SSP_ERR_ARG;
-    if (kernel < 0 || kernel > 3) return SSP_ERR_ARG;
+    if (kernel < 0 || kernel > 4) return SSP_ERR_ARG;
     if (lds_bytes > 0 && lds_bytes < ssp::pcg_min_lds(b->nx_max, true)) return SSP_ERR_ARG;
     b->threads = threads;
     b->lds_bytes = lds_bytes;
@@ -476,17 +647,44 @@ ssp_status ssp_build(ssp_batch *b, ssp_precon pc, ssp_precision prec, const doub
                      const double *Q, const double *R, int32_t *prob_status, void *stream) {
     if (!b || !A || !Q || !prob_status) return SSP_ERR_ARG;
     if (b->nu_max > 0 && (!B || !R)) return SSP_ERR_ARG;
-    if (pc < SSP_PC_BLOCK_JACOBI || pc > SSP_PC_SYM_STAIR) return SSP_ERR_ARG;
+    if (pc < SSP_PC_BLOCK_JACOBI || pc > SSP_PC_NEUMANN3) return SSP_ERR_ARG;
     if (prec < SSP_FP64 || prec > SSP_FP32_REFINE64) return SSP_ERR_ARG;
+    // which solve will run: the scaled one for the polynomial forms, for the
+    // block preconditioners under FP32 storage, and when asked for (kernel 4)
+    const bool poly = pc == SSP_PC_NEUMANN2 || pc == SSP_PC_NEUMANN3;
+    const bool one_long = b->P == 1 && b->N[0] >= 24;  // the cooperative solve's case
+    bool scaled = b->kernel == 4 || poly ||
+                  (b->kernel == 0 && prec != SSP_FP64 && pc != SSP_PC_SCALAR_JACOBI && !one_long);
+    if (pc == SSP_PC_SCALAR_JACOBI) {
+        if (b->kernel == 4) {
+            g_last_error = "scalar Jacobi has no scaled-basis form (use kernel 0, 1 or 2)";
+            return SSP_ERR_ARG;
+        }
+        scaled = false;
+    }
+    if (scaled && !scaled_possible(b)) {
+        if (poly || b->kernel == 4) {
+            g_last_error = "the scaled solve (and the polynomial preconditioners) need state sizes 6, 14, 26 or 36 "
+                           "with nu <= nx";
+            return SSP_ERR_ARG;
+        }
+        scaled = false;
+    }
+    if (poly && (b->kernel == 1 || b->kernel == 2 || b->kernel == 3)) {
+        g_last_error = "the polynomial preconditioners run in the scaled solve only (kernel 0 or 4)";
+        return SSP_ERR_ARG;
+    }
     DevGuard g(b->device);
     hipStream_t s = (hipStream_t)stream;
     const bool fp32 = prec != SSP_FP64;
     ssp_status rc = alloc_storage(b, fp32);
     if (rc != SSP_OK) return rc;
+    if (scaled && (rc = alloc_scaled(b)) != SSP_OK) return rc;
     b->built = false;
     b->m_valid = false;
     b->pc = pc;
     b->prec = prec;
+    b->scaled = scaled;
     SSP_HIP(ssp::launch_fill_i32(prob_status, 0, b->P, s));
     ssp::BuildArgs a = build_args(b);
     a.A = A;
@@ -494,10 +692,20 @@ ssp_status ssp_build(ssp_batch *b, ssp_precon pc, ssp_precision prec, const doub
     a.Q = Q;
     a.R = R;
     a.status = prob_status;
+    if (scaled) {
+        a.Zs = b->Zs;
+        a.OH = b->OH;
+        a.Zw = b->Zw;
+    }
     for (int c = 0; c < ssp::kBuildClasses; ++c)
         SSP_HIP(ssp::launch_build_class(c, a, b->ditems + b->item_off[c], b->item_off[c + 1] - b->item_off[c], fp32,
                                         s));
     SSP_HIP(ssp::launch_build(a, b->n_generic, b->gen_nx_max, b->gen_nu_max, fp32, s));
+    if (scaled)
+        for (int c = 0; c < ssp::kBuildClasses; ++c)
+            SSP_HIP(ssp::launch_build_ohat(c, a, b->ditems + b->item_off[c], b->item_off[c + 1] - b->item_off[c],
+                                           fp32, s));
+    if (pc == SSP_PC_SCALAR_JACOBI) SSP_HIP(ssp::launch_jacobi_diag(a, b->knots, fp32, s));
     b->built = true;
     return SSP_OK;
 }
@@ -505,8 +713,12 @@ ssp_status ssp_build(ssp_batch *b, ssp_precon pc, ssp_precision prec, const doub
 ssp_status ssp_build_from_blocks(ssp_batch *b, ssp_precon pc, ssp_precision prec, const double *D,
                                  const double *Lsub, int32_t *prob_status, void *stream) {
     if (!b || !D || !Lsub || !prob_status) return SSP_ERR_ARG;
-    if (pc < SSP_PC_BLOCK_JACOBI || pc > SSP_PC_SYM_STAIR) return SSP_ERR_ARG;
+    if (pc < SSP_PC_BLOCK_JACOBI || pc > SSP_PC_SCALAR_JACOBI) return SSP_ERR_ARG;
     if (prec < SSP_FP64 || prec > SSP_FP32_REFINE64) return SSP_ERR_ARG;
+    if (b->kernel == 4) {
+        g_last_error = "the scaled solve needs the assembly from dynamics (ssp_build)";
+        return SSP_ERR_ARG;
+    }
     DevGuard g(b->device);
     hipStream_t s = (hipStream_t)stream;
     const bool fp32 = prec != SSP_FP64;
@@ -516,10 +728,12 @@ ssp_status ssp_build_from_blocks(ssp_batch *b, ssp_precon pc, ssp_precision prec
     b->m_valid = false;
     b->pc = pc;
     b->prec = prec;
+    b->scaled = false;
     SSP_HIP(ssp::launch_fill_i32(prob_status, 0, b->P, s));
     ssp::BuildArgs a = build_args(b);
     a.status = prob_status;
     SSP_HIP(ssp::launch_build_blocks(a, D, Lsub, b->knots, fp32, s));
+    if (pc == SSP_PC_SCALAR_JACOBI) SSP_HIP(ssp::launch_jacobi_diag(a, b->knots, fp32, s));
     b->built = true;
     return SSP_OK;
 }
@@ -532,6 +746,7 @@ ssp_status ssp_solve(ssp_batch *b, double rel_tol, int32_t max_iter, const doubl
     DevGuard g(b->device);
     hipStream_t s = (hipStream_t)stream;
     ssp::SolveArgs a = solve_args(b, rel_tol, max_iter, gamma, lambda, use_lambda0, iters, relres, prob_status);
+    if (b->scaled) return launch_scaled(b, a, s);
     if (use_coop(b)) {
         // one long problem: spread its knots over the whole grid
         const int c0 = ssp::coop_clear_first();
@@ -567,8 +782,25 @@ ssp_status ssp_solve_outer(const ssp_batch *b, int32_t *outer, void *stream) {
 }
 
 ssp_status ssp_export(ssp_batch *b, int which, double *diag, double *off, void *stream) {
-    if (!b || !diag || !off || which < 0 || which > 2) return SSP_ERR_ARG;
+    if (!b || !diag || !off || which < 0 || which > 3) return SSP_ERR_ARG;
+    if (which == 3) {
+        if (!b->built) return SSP_ERR_STATE;
+        if (!b->scaled) {
+            g_last_error = "the last build did not write the scaled basis";
+            return SSP_ERR_STATE;
+        }
+        DevGuard g(b->device);
+        hipStream_t s = (hipStream_t)stream;
+        ssp::BuildArgs a = build_args(b);
+        SSP_HIP(ssp::launch_export(a, 3, b->Zs, nullptr, b->fp32, diag, b->knots, s));
+        SSP_HIP(ssp::launch_export(a, 3, b->OH, nullptr, b->fp32, off, b->knots, s));
+        return SSP_OK;
+    }
     if (!b->built) return SSP_ERR_STATE;
+    if (which == 1 && (b->pc == SSP_PC_NEUMANN2 || b->pc == SSP_PC_NEUMANN3)) {
+        g_last_error = "a polynomial preconditioner of degree >= 2 is not block tridiagonal";
+        return SSP_ERR_ARG;
+    }
     DevGuard g(b->device);
     hipStream_t s = (hipStream_t)stream;
     ssp::BuildArgs a = build_args(b);
@@ -590,6 +822,7 @@ ssp_status ssp_autotune(ssp_batch *b, double rel_tol, const double *gamma, doubl
                         double *relres, int32_t *prob_status, void *stream) {
     if (!b || !gamma || !lambda || !iters || !relres || !prob_status || !(rel_tol >= 0.0)) return SSP_ERR_ARG;
     if (!b->built) return SSP_ERR_STATE;
+    if (b->scaled) return autotune_scaled(b, rel_tol, gamma, lambda, iters, relres, prob_status, stream);
     if (b->kernel == 1 || !fused_ok(b) || use_coop(b))  // only the batched fused kernel has a mapping to tune
         return ssp_solve(b, rel_tol, 0, gamma, lambda, 0, iters, relres, prob_status, stream);
     DevGuard dg(b->device);
@@ -684,6 +917,46 @@ ssp_status ssp_get_mapping(const ssp_batch *b, int32_t max_groups, int32_t *nx, 
         if (threads) threads[i] = t;
         if (lds_bytes) lds_bytes[i] = l;
         if (tuned_ms) tuned_ms[i] = b->groups[i].tuned_ms;
+    }
+    return SSP_OK;
+}
+
+ssp_status ssp_set_scaled_mapping(ssp_batch *b, int32_t threads, int32_t lds_bytes) {
+    if (!b) return SSP_ERR_ARG;
+    if (threads == 0 && lds_bytes == 0) {
+        b->s3_threads = 256;
+        b->s3_lds = 0;
+        b->s3_tuned_ms = 0.0f;
+        return SSP_OK;
+    }
+    if ((threads != 128 && threads != 256) || lds_bytes < 0 || lds_bytes > ssp::kFusedLdsCap) return SSP_ERR_ARG;
+    const int m = poly_steps(b->pc);
+    const int l = lds_bytes > 0 ? lds_bytes : 0;
+    const int prev_t = b->s3_threads, prev_l = b->s3_lds;
+    b->s3_threads = threads;
+    b->s3_lds = l;
+    if (!scaled_possible(b) || !scaled_fits(b, threads, scaled_lds(b, threads, m), m)) {
+        b->s3_threads = prev_t;
+        b->s3_lds = prev_l;
+        return SSP_ERR_ARG;
+    }
+    b->s3_tuned_ms = 0.0f;
+    return SSP_OK;
+}
+
+ssp_status ssp_get_scaled_mapping(const ssp_batch *b, int32_t *threads, int32_t *lds_bytes, int32_t *grid,
+                                  float *tuned_ms) {
+    if (!b) return SSP_ERR_ARG;
+    const int t = b->s3_threads, m = poly_steps(b->pc);
+    const int l = scaled_lds(b, t, m);
+    if (threads) *threads = t;
+    if (lds_bytes) *lds_bytes = l;
+    if (tuned_ms) *tuned_ms = b->s3_tuned_ms;
+    if (grid) {
+        DevGuard g(b->device);
+        int cus = 0;
+        const int occ = ssp::pcg3_occupancy(b->fp32, t, l, &cus);
+        *grid = std::min(occ * cus, b->P);
     }
     return SSP_OK;
 }

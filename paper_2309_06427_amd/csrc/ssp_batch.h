@@ -81,6 +81,16 @@ struct ssp_batch {
     void *work = nullptr;
     double *r64 = nullptr;
     int32_t *douter = nullptr;
+    // scaled basis (built when the scaled solve will run): Z_k, Oh_k in the
+    // storage type (full blocks, stride bs), Z_k in FP64 (build only), the
+    // scaled residual and the persistent grid's queue counter
+    void *Zs = nullptr, *OH = nullptr;
+    double *Zw = nullptr, *rh64 = nullptr;
+    unsigned *dqueue = nullptr;
+    bool have_scaled = false;  // Zs/OH/Zw/rh64 allocated for the current storage precision
+    bool scaled = false;       // the last build wrote the scaled basis: ssp_solve runs the scaled kernel
+    int s3_threads = 256, s3_lds = 0;  // mapping of the scaled kernel (0: default budget)
+    float s3_tuned_ms = 0.0f;
     // state
     bool built = false;
     bool m_valid = false;  // explicit stair blocks PM match the last build
@@ -88,12 +98,12 @@ struct ssp_batch {
     ssp_precision prec = SSP_FP64;
     int threads = 128;
     int lds_bytes = 0;  // 0: default
-    int kernel = 0;     // 0 auto, 1 explicit, 2 batched fused, 3 cooperative (one problem)
+    int kernel = 0;     // 0 auto, 1 explicit, 2 batched fused, 3 cooperative (one problem), 4 scaled
     // cooperative solve of a single problem: barrier words and partial sums
     unsigned *dbar = nullptr;
     unsigned long long *drec = nullptr, *dwtag = nullptr;
     int coop_key = -1, coop_W = 0, coop_G = 0;  // cached plan (key: storage precision)
-    int last_kernel = 0;                          // kernel of the last solve: 1 explicit, 2 fused, 3 cooperative
+    int last_kernel = 0;                          // kernel of the last solve: 1 explicit, 2 fused, 3 cooperative, 4 scaled
     // Fused solve groups: the problems of one state size, largest first,
     // launched on their own stream with their own workgroup size and LDS
     // budget (0: derived from threads / lds_bytes above).

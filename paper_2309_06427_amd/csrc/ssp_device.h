@@ -23,6 +23,21 @@ constexpr int kPcFallback = 16;   // OR-ed flag: block-Jacobi took over after a 
 // solve's iteration limit, breakdown or fallback flags) starts a fresh solve.
 __host__ __device__ inline bool build_failed(int st) { return (st & 7) == kNotSpd; }
 
+// A value every lane of the wave holds equally (a workgroup sum, a queue
+// position), moved into scalar registers: branches on it are then uniform
+// for the compiler, which keeps loops that contain workgroup barriers from
+// being restructured around lanes it would otherwise treat as divergent.
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ float uniform(float v) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+__device__ __forceinline__ double uniform(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffffll));
+    const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
 // Butterfly sum over the 64 lanes of a wavefront.  Every lane ends with the
 // same bits: each stage adds the same two operands on both partner lanes.
 template <typename T>

@@ -20,8 +20,13 @@ struct BuildArgs {
     void *B3;            // per knot k: D_k (packed), L_k (full), D_k^-1 (packed), storage type
     float *SDlo, *SLlo;  // FP64 remainders of D_k (packed stride), L_k (stride bs) under FP32 storage
     void *PM;           // explicit Phi^-1[k][k-1] blocks (stride bs; null: not built)
+    // scaled basis (null: not built): Z_k = lower Cholesky factor of D_k^-1
+    // and Oh_k = Z_k^T L_k Z_{k-1} (stride bs, storage type), Z_k in FP64
+    // (layout of Q) for the neighbouring knot's Oh
+    void *Zs, *OH;
+    double *Zw;
     int32_t *status;
-    int pc;  // 0 block-Jacobi, 1 additive stair, 2 symmetric stair
+    int pc;  // 0 block-Jacobi, 1 additive stair, 2 symmetric stair, 3 scalar Jacobi, 4/5 Neumann degree 2/3
     int mx;  // max(nx, nu) over the batch
 };
 
@@ -49,6 +54,13 @@ struct SolveArgs {
     double *r64;   // FP64 residual, tot_v long
     int64_t tot_v;
     int lds_bytes;
+    // scaled solve (congruence basis, persistent grid)
+    const void *OH, *Z;  // Oh_k and Z_k blocks (stride bs, full-block layout off_blk)
+    double *rh64;        // FP64 residual in the scaled basis, Z^T r, tot_v long
+    unsigned *queue;     // next position in `order` (zeroed before every launch)
+    int nprob;           // problems in the queue
+    int poly;            // Horner steps m of the preconditioner polynomial in Oh (0: block-Jacobi)
+    double pc_c;         // coefficient of each Horner step (1; 1/2 for the additive stair)
 };
 
 // Generic assembly (any nx <= 64), one 64-lane workgroup per knot of
@@ -60,6 +72,11 @@ constexpr int kBuildClasses = 4;
 extern const int kBuildSizes[kBuildClasses];
 int build_knots_per_item(int nx);
 hipError_t launch_build_class(int cls, const BuildArgs &a, const int2 *items, int nitems, bool fp32, hipStream_t s);
+// Scaled basis for one compiled state size, after launch_build_class wrote
+// Z_k (a.Zs, a.Zw): Oh_k = Z_k^T L_k Z_{k-1} for the same work items.
+hipError_t launch_build_ohat(int cls, const BuildArgs &a, const int2 *items, int nitems, bool fp32, hipStream_t s);
+// Scalar Jacobi: overwrite every stored D_k^-1 with diag(1 / (D_k)_ii).
+hipError_t launch_jacobi_diag(const BuildArgs &a, int64_t knots, bool fp32, hipStream_t s);
 // S from caller-given blocks D_k, L_k (every knot of the batch): stored D,
 // L and D^-1 as the assembly stores them.
 hipError_t launch_build_blocks(const BuildArgs &a, const double *D, const double *Lsub, int64_t knots, bool fp32,
@@ -106,5 +123,17 @@ int pcg2_lds(int nx_max, bool fp32, int threads);  // 0 if the mapping cannot ho
 int pcg2_steps_for(int nx, bool fp32, int threads, int lds_bytes);
 // Workgroup sizes the fused kernel is compiled for (128, 256).
 bool pcg2_threads_ok(int threads);
+
+// Scaled solve: one persistent grid over every problem (state sizes
+// kBuildSizes only), problems taken from a device queue in `order`.
+// `grid`: workgroups to launch (<= 0: as many as fit on the device at once).
+hipError_t launch_pcg3(const SolveArgs &a, bool fp32, int threads, int grid, hipStream_t s);
+// LDS bytes for the largest pipeline step of state size nx at `threads`
+// with m Horner steps (0 if it cannot run), and the knots per step a budget
+// gives (< 1: cannot run).
+int pcg3_lds(int nx, bool fp32, int threads, int m);
+int pcg3_steps_for(int nx, bool fp32, int threads, int lds_bytes, int m);
+// Workgroups of k_pcg3 resident per CU with this LDS budget, and CUs.
+int pcg3_occupancy(bool fp32, int threads, int lds_bytes, int *cus);
 
 }  // namespace ssp

@@ -99,9 +99,21 @@ class BatchSolver:
                                 C.byref(n)), "ssp_get_mapping")
         return [(int(nx[i]), int(th[i]), int(lds[i]), float(ms[i])) for i in range(k)]
 
+    def set_scaled_mapping(self, threads: int, lds_bytes: int = 0):
+        check(_lib.load().ssp_set_scaled_mapping(self._h, int(threads), int(lds_bytes)), "ssp_set_scaled_mapping")
+
+    def scaled_mapping(self) -> tuple:
+        """(threads, lds_bytes, persistent grid, tuned ms) of the scaled solve."""
+        t, l, g = C.c_int32(), C.c_int32(), C.c_int32()
+        ms = C.c_float()
+        check(_lib.load().ssp_get_scaled_mapping(self._h, C.byref(t), C.byref(l), C.byref(g), C.byref(ms)),
+              "ssp_get_scaled_mapping")
+        return int(t.value), int(l.value), int(g.value), float(ms.value)
+
     def solve_kernel(self) -> tuple:
-        """(kernel, W, G) of the last solve: 1 explicit, 2 fused, 3 cooperative
-        (W own knots per workgroup, G workgroups; 0 otherwise)."""
+        """(kernel, W, G) of the last solve: 1 explicit, 2 fused, 3 cooperative,
+        4 scaled (W own knots per workgroup, G workgroups of the cooperative
+        solve; 0 otherwise)."""
         k, w, g = C.c_int32(), C.c_int32(), C.c_int32()
         check(_lib.load().ssp_solve_kernel(self._h, C.byref(k), C.byref(w), C.byref(g)), "ssp_solve_kernel")
         return int(k.value), int(w.value), int(g.value)

@@ -187,6 +187,9 @@ def test_fallback_restarts_from_zero_like_the_oracle():
     b = inputs.batch(6, 16, N_range=(5, 30), nx_choices=(6, 14))
     rng = np.random.default_rng(0)
     lam0 = 1e3 * rng.standard_normal(b.gamma.shape[0])  # far worse than zero
+    # problem 0: a zero start, whose residual is exactly gamma; the tie is not
+    # "below ||gamma||", so it falls back too (both norms summed in one order)
+    lam0[: b.off_v[1]] = 0.0
     ref0 = oracle.solve_batch(b, "sym", "fp64", 1e-8)
     ref = oracle.solve_batch(b, "sym", "fp64", 1e-8, lam0=lam0, fallback=True)
     assert (ref["status"] == 8).all()
