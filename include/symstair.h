@@ -108,13 +108,15 @@ ssp_status ssp_layout(const ssp_batch *b, int64_t *off_nn, int64_t *off_nu, int6
  * device int32[nprob], overwritten with SSP_P_OK or SSP_P_NOT_SPD.
  *
  * The build also decides which solve runs (see ssp_set_mapping, kernel 4):
- * the scaled solve, for which it additionally writes Z_k, the lower
- * Cholesky factor of D_k^-1, and Oh_k = Z_k^T L_k Z_{k-1}, the off-diagonal
- * blocks of Z^T S Z = I + Oh (Z = blockdiag(Z_k)).  In that basis every
- * preconditioner above except scalar Jacobi is a polynomial in Oh (block-
- * Jacobi Z Z^T, symmetric stair Z (I - Oh) Z^T, additive stair
- * Z (I - Oh/2) Z^T, Neumann degree m Z (sum_{i<=m} (-Oh)^i) Z^T): the same
- * operators, applied while streaming one nx x nx block per knot.  The
+ * the scaled solve, for which it writes, instead of D_k^-1, W_k = C_k^-1 with
+ * C_k the Cholesky factor of D_k (D_k = C_k C_k^T), and Oh_k =
+ * W_k L_k W_{k-1}^T, the off-diagonal blocks of W S W^T = I + Oh
+ * (W = blockdiag(W_k)).  In that basis every preconditioner above except
+ * scalar Jacobi is a polynomial in Oh (block-Jacobi W^T W, symmetric stair
+ * W^T (I - Oh) W, additive stair W^T (I - Oh/2) W, Neumann degree m
+ * W^T (sum_{i<=m} (-Oh)^i) W): the same operators, applied while streaming
+ * one nx x nx block per knot (D_k^-1 = W_k^T W_k is formed when ssp_export
+ * asks for it).  The
  * polynomial preconditioners SSP_PC_NEUMANN2/3 exist only there, and need
  * every problem's nx in {6, 14, 26, 36} with nu <= nx (else SSP_ERR_ARG). */
 ssp_status ssp_build(ssp_batch *b, ssp_precon pc, ssp_precision prec, const double *A,
@@ -178,7 +180,7 @@ ssp_status ssp_solve_outer(const ssp_batch *b, int32_t *outer, void *stream);
  * PCG reads it (the FP32 hi part only under FP32 storage).  which = 1
  * computes the explicit stair blocks if the last build did not (SSP_ERR_ARG
  * for the polynomial preconditioners, which are not block tridiagonal);
- * which = 3 -> the scaled basis of the last build (diag = Z_k, off = Oh_k;
+ * which = 3 -> the scaled basis of the last build (diag = W_k, off = Oh_k;
  * SSP_ERR_STATE if it was not built). */
 ssp_status ssp_export(ssp_batch *b, int which, double *diag, double *off, void *stream);
 

@@ -317,6 +317,26 @@ __global__ void k_export(BuildArgs a, int which, const TM *hi, const float *lo, 
     }
 }
 
+// D_k^-1 = W_k^T W_k (W_k = C_k^-1, D_k = C_k C_k^T) into the stored D_k^-1
+// slot, from W in FP64; one workgroup per knot, W_k in LDS.
+template <typename TM>
+__global__ void k_dinv_from_w(BuildArgs a) {
+    extern __shared__ double sm[];
+    int p, k;
+    knot_of(a, p, k);
+    const int nx = a.nx[p], nn = nx * nx, bs = block_stride(nx, sizeof(TM)), bp = packed_stride(nx, sizeof(TM));
+    TM *blk = (TM *)a.B3 + a.off_b3[p] + (int64_t)k * (2 * bp + bs);
+    team_load(sm, a.Zw + a.off_nn[p] + (int64_t)k * nn, nn);
+    __syncthreads();
+    for (int e = threadIdx.x; e < nn; e += T) {
+        const int r = e / nx, c = e - r * nx;
+        if (r > c) continue;
+        double v = 0.0;
+        for (int l = 0; l < nx; ++l) v += sm[l * nx + r] * sm[l * nx + c];
+        blk[bp + bs + packed_index(r, c, nx)] = (TM)v;
+    }
+}
+
 // Scalar Jacobi (Eq. (jacobi) with Phi = diag(S)): replace the stored D_k^-1
 // of every knot by diag(1 / (D_k)_ii), (D_k)_ii read as stored hi + lo.  One
 // workgroup per knot.
@@ -406,6 +426,16 @@ hipError_t launch_export(const BuildArgs &a, int which, const void *hi, const fl
     else
         hipLaunchKernelGGL(k_export<double>, dim3((unsigned)knots), dim3(T), 0, s, a, which, (const double *)hi, lo,
                            dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_dinv_from_w(const BuildArgs &a, int64_t knots, int nx_max, bool fp32, hipStream_t s) {
+    if (knots == 0) return hipSuccess;
+    const size_t l = sizeof(double) * nx_max * nx_max;
+    if (fp32)
+        hipLaunchKernelGGL(k_dinv_from_w<float>, dim3((unsigned)knots), dim3(T), l, s, a);
+    else
+        hipLaunchKernelGGL(k_dinv_from_w<double>, dim3((unsigned)knots), dim3(T), l, s, a);
     return hipGetLastError();
 }
 

@@ -15,10 +15,11 @@
 // matrix every pivot is a positive Schur-complement diagonal, so a
 // non-positive pivot flags the matrix as not positive definite.
 //
-// Scaled basis (when asked for): Z_k, the lower Cholesky factor of D_k^-1
-// (D_k^-1 = Z_k Z_k^T), in phase 2, and in phase 3 the off-diagonal blocks
-// Oh_k = Z_k^T L_k Z_{k-1} of the congruence Z^T S Z = I + Oh
-// (Z = blockdiag(Z_k)), which the scaled solve streams instead of D, L, D^-1.
+// Scaled basis (when asked for): in phase 2, instead of D_k^-1, the inverse
+// W_k = C_k^-1 of the Cholesky factor C_k of D_k (D_k = C_k C_k^T, W_k lower
+// triangular), and in phase 3 the off-diagonal blocks Oh_k = W_k L_k W_{k-1}^T
+// of the congruence W S W^T = I + Oh (W = blockdiag(W_k)), which the scaled
+// solve streams instead of D, L, D^-1.
 #include "ssp_device.h"
 #include "ssp_host.h"
 #include "ssp_sweep.h"
@@ -220,16 +221,18 @@ __device__ __forceinline__ bool gj_inverse_blocked(double (&a)[NX], int i, bool 
     return ok;
 }
 
-// Lower Cholesky factor of the SPD matrix whose row i this lane holds in a[]
-// (every lane of the knot holds one row), in place: afterwards a[j] is
-// Z[i][j] (zero above the diagonal) with A = Z Z^T.  Right-looking
-// elimination: at step j the pivot lane publishes its row of the current
-// Schur complement (for a symmetric matrix that row is also the pivot
-// column), every lower row scales its entry j by 1 / sqrt(pivot) and updates
-// its entries right of j.  M: the knot's LDS buffer (pivot row).  Returns
-// false if a pivot is not positive.
+// W = C^-1 for the Cholesky factor C of the SPD matrix (A = C C^T) whose
+// row i this lane holds in a[] (every lane of the knot holds one row), in
+// place: afterwards a[] is row i of W (lower triangular).  Forward Gaussian
+// elimination of [A | I] without pivoting (stable for SPD A): at step j the
+// pivot lane publishes its row, lanes below subtract f = a_ij / u_jj times
+// it, which leaves U (upper, pivots u_jj on its diagonal) on the right and
+// E = L^-1 (unit lower) on the left of the same row storage (entry j of a
+// lower row becomes -f, E's new entry; its other entries update alike).
+// With A = L diag(u) L^T, W = diag(u)^-1/2 L^-1.  M: the knot's LDS buffer
+// (pivot row).  Returns false if a pivot is not positive.
 template <int NX>
-__device__ __forceinline__ bool chol_rows(double (&a)[NX], int i, bool row, double *M) {
+__device__ __forceinline__ bool lower_inverse_rows(double (&a)[NX], int i, bool row, double *M) {
     constexpr int NP = Lane<NX>::NP;
     double *prow = M + NX * NP;
     bool ok = true;
@@ -237,24 +240,29 @@ __device__ __forceinline__ bool chol_rows(double (&a)[NX], int i, bool row, doub
         constexpr int j = decltype(jc)::value;
         if (row && i == j) lds_put_row<NX>(prow, a);
         wave_sync();
-        const double piv = prow[j];
-        if (!(piv > 0.0)) ok = false;
-        const double rs = 1.0 / sqrt(piv);
-        if (i > j) {
-            const double l = a[j] * rs;
-            a[j] = l;
-            static_for<j + 1, NX>([&](auto kc) {
-                constexpr int k = decltype(kc)::value;
-                a[k] = fma(-l * rs, prow[k], a[k]);
-            });
-        } else if (i == j) {
-            a[j] = piv * rs;
-        }
+        double pr[NX];
+        lds_row<NX>(prow, pr);
         wave_sync();  // the pivot row is read before the next one is written
+        if (!(pr[j] > 0.0)) ok = false;
+        if (i > j) {
+            const double f = a[j] / pr[j];
+            static_for<0, NX>([&](auto lc) {
+                constexpr int l = decltype(lc)::value;
+                if constexpr (l != j) a[l] = fma(-f, pr[l], a[l]);
+            });
+            a[j] = -f;
+        }
     });
+    // this lane's pivot u_ii sits at a[i]; scale E's row by u_ii^-1/2
+    double u = 0.0;
     static_for<0, NX>([&](auto jc) {
         constexpr int j = decltype(jc)::value;
-        if (j > i) a[j] = 0.0;
+        if (j == i) u = a[j];
+    });
+    const double s = 1.0 / sqrt(u);
+    static_for<0, NX>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        a[j] = j < i ? a[j] * s : (j == i ? s : 0.0);
     });
     return ok;
 }
@@ -436,26 +444,30 @@ __global__ __launch_bounds__(kThreads) void k_build_asm_nx(BuildArgs a, const in
     }
     symmetrise<NX>(d, i, ln.row, M);  // exactly symmetric before the upper triangle is kept
     if (ln.row) store_split_packed_row<TM, NX>(blk, a.SDlo ? a.SDlo + od : nullptr, i, d);
-    bool ok = gj_inverse_blocked<NX, kGjBlock>(d, i, ln.row, NX, M);
-    symmetrise<NX>(d, i, ln.row, M);
-    if (ln.row) store_split_packed_row<TM, NX>(blk + bp + bs, (float *)nullptr, i, d);
+    bool ok;
     if (a.Zs) {
-        // scaled basis: Z_k = chol(D_k^-1), stored full (zeros above the
-        // diagonal) in the storage type and in FP64 for phase 3
-        ok = chol_rows<NX>(d, i, ln.row, M) && ok;
+        // scaled basis: W_k = C_k^-1 instead of D_k^-1, stored full (zeros
+        // above the diagonal) in the storage type and in FP64 for phase 3;
+        // D_k^-1 = W_k^T W_k is formed only on demand
+        ok = lower_inverse_rows<NX>(d, i, ln.row, M);
         if (ln.row) {
             store_split_row<TM, NX>((TM *)a.Zs + ol + i * NX, (float *)nullptr, d, 1.0);
             store_row<NX>(a.Zw + a.off_nn[p] + (int64_t)k * nn + i * NX, NX, d);
         }
+    } else {
+        ok = gj_inverse_blocked<NX, kGjBlock>(d, i, ln.row, NX, M);
+        symmetrise<NX>(d, i, ln.row, M);
+        if (ln.row) store_split_packed_row<TM, NX>(blk + bp + bs, (float *)nullptr, i, d);
     }
     if (ln.row && !ok) atomicOr(a.status + p, kNotSpd);
 }
 
-// Phase 3 of the scaled basis: Oh_k = Z_k^T L_k Z_{k-1} (k >= 1, Oh_0 = 0)
-// in FP64 from Z (FP64 workspace) and L_k (storage hi + FP32 remainder, or
-// FP64), stored in the storage type.  First X = L_k Z_{k-1} (rows of
-// Z_{k-1} in LDS, lane i's row of L_k), then row i of Z_k^T X = sum_l
-// Z_k[l][i] X[l][:] (rows of X in LDS, column i of Z_k from memory).
+// Phase 3 of the scaled basis: Oh_k = W_k L_k W_{k-1}^T (k >= 1, Oh_0 = 0)
+// in FP64 from W (FP64 workspace) and L_k (storage hi + FP32 remainder, or
+// FP64), stored in the storage type.  Both products are row-times-transpose
+// dot products against LDS rows: X = L_k W_{k-1}^T with the rows of W_{k-1}
+// in LDS, then row i of W_k X = sum_l W_k[i][l] X[l][:] with X^T in LDS
+// (lane i stores its row of X as LDS column i) and row i of W_k in registers.
 template <typename TM, int NX>
 __global__ __launch_bounds__(kThreads) void k_build_ohat_nx(BuildArgs a, const int2 *items) {
     constexpr int KN = (kThreads / 64) * Lane<NX>::KW;
@@ -470,35 +482,42 @@ __global__ __launch_bounds__(kThreads) void k_build_ohat_nx(BuildArgs a, const i
     const int64_t ol = a.off_blk[p] + (int64_t)k * bs;
     const bool prev = ln.row && k > 0;
     double x[NX], t[NX];
-    // rows of Z_{k-1}
-    wave_sync();
-    if (prev) store_row<NX>(M + i * NP, NX, *(const double(*)[NX])(a.Zw + a.off_nn[p] + (int64_t)(k - 1) * nn + i * NX));
-    wave_sync();
-    // row i of L_k in FP64
+    static_for<0, NX>([&](auto jc) { t[decltype(jc)::value] = 0.0; });
     if (prev) {
+        load_row<NX>(a.Zw + a.off_nn[p] + (int64_t)(k - 1) * nn + i * NX, NX, x);  // row i of W_{k-1}
+        wave_sync();
+        lds_put_row<NX>(M + i * NP, x);
+        wave_sync();
+        // row i of L_k in FP64
         const TM *Lk = (const TM *)a.B3 + a.off_b3[p] + (int64_t)k * (2 * bp + bs) + bp + i * NX;
-        const float *lo = a.SLlo ? a.SLlo + ol + i * NX : nullptr;
         static_for<0, NX>([&](auto jc) {
             constexpr int j = decltype(jc)::value;
-            x[j] = (double)Lk[j] + (lo ? (double)lo[j] : 0.0);
+            x[j] = (double)Lk[j];
         });
+        if (a.SLlo) {
+            const float *lo = a.SLlo + ol + i * NX;
+            static_for<0, NX>([&](auto jc) {
+                constexpr int j = decltype(jc)::value;
+                x[j] += (double)lo[j];
+            });
+        }
+        row_times_t<NX>(x, M, NX, t);  // t = row i of X = L_k W_{k-1}^T
+        wave_sync();
+        static_for<0, NX>([&](auto jc) {  // X^T: LDS column i
+            constexpr int j = decltype(jc)::value;
+            M[j * NP + i] = t[j];
+        });
+        wave_sync();
+        load_row<NX>(a.Zw + a.off_nn[p] + (int64_t)k * nn + i * NX, NX, x);  // row i of W_k
+        static_for<0, NX>([&](auto jc) { t[decltype(jc)::value] = 0.0; });
+        row_times_t<NX>(x, M, NX, t);  // row i of W_k X
     } else {
-        static_for<0, NX>([&](auto jc) { x[decltype(jc)::value] = 0.0; });
+        // knot 0 (Oh_0 = 0) or a lane without a row: the same ordering points
+        wave_sync();
+        wave_sync();
+        wave_sync();
+        wave_sync();
     }
-    row_times<NX>(x, M, NX, t);  // row i of X = L_k Z_{k-1}
-    wave_sync();
-    if (ln.row) lds_put_row<NX>(M + i * NP, t);
-    wave_sync();
-    // column i of Z_k
-    if (ln.row) {
-        const double *Zk = a.Zw + a.off_nn[p] + (int64_t)k * nn;
-        static_for<0, NX>([&](auto lc) {
-            constexpr int l = decltype(lc)::value;
-            x[l] = Zk[l * NX + i];
-        });
-    }
-    row_times<NX>(x, M, NX, t);  // row i of Z_k^T X
-    if (!prev) static_for<0, NX>([&](auto jc) { t[decltype(jc)::value] = 0.0; });  // Oh_0 = 0
     if (ln.row) store_split_row<TM, NX>((TM *)a.OH + ol + i * NX, (float *)nullptr, t, 1.0);
 }
 

@@ -86,14 +86,17 @@ int scaled_lds(const ssp_batch *b, int threads, int m) {
     int need = 0;
     for (const auto &g : b->groups) need = std::max(need, ssp::pcg3_lds(g.nx, b->fp32, threads, m));
     int l = b->s3_lds > 0 ? b->s3_lds : need;
-    l = std::max(l, ssp::bt_sweep_min_lds(b->nx_max, true, 8));
+    // the FP64 residual needs one knot per step of every state size
+    for (const auto &g : b->groups)
+        while (l < ssp::kFusedLdsCap && ssp::pcg3_residual_steps(g.nx, b->fp32, l) < 1) l += 256;
     return std::min(l, ssp::kFusedLdsCap);
 }
 
 // the scaled kernel can run every state size of the batch with this budget
 bool scaled_fits(const ssp_batch *b, int threads, int lds, int m) {
     for (const auto &g : b->groups)
-        if (ssp::pcg3_steps_for(g.nx, b->fp32, threads, lds, m) < 1) return false;
+        if (ssp::pcg3_steps_for(g.nx, b->fp32, threads, lds, m) < 1 || ssp::pcg3_residual_steps(g.nx, b->fp32, lds) < 1)
+            return false;
     return true;
 }
 
@@ -200,9 +203,23 @@ ssp::BuildArgs build_args(const ssp_batch *b) {
     return a;
 }
 
+// D_k^-1 = W_k^T W_k into the stored blocks after a scaled build, on demand
+ssp_status ensure_dinv(ssp_batch *b, hipStream_t s) {
+    if (b->dinv_valid) return SSP_OK;
+    ssp::BuildArgs a = build_args(b);
+    a.Zw = b->Zw;
+    SSP_HIP(ssp::launch_dinv_from_w(a, b->knots, b->nx_max, b->fp32, s));
+    b->dinv_valid = true;
+    return SSP_OK;
+}
+
 // explicit stair blocks, built on demand from the stored D^-1 and L
 ssp_status ensure_m(ssp_batch *b, hipStream_t s) {
     if (b->m_valid) return SSP_OK;
+    {
+        ssp_status rc = ensure_dinv(b, s);
+        if (rc != SSP_OK) return rc;
+    }
     if (!b->PM) {
         const size_t elem = b->fp32 ? sizeof(float) : sizeof(double);
         const size_t nn = (size_t)(b->fp32 ? b->off_blk32 : b->off_blk64)[b->P];
@@ -357,9 +374,9 @@ ssp_status autotune_scaled(ssp_batch *b, double rel_tol, const double *gamma, do
         b->s3_threads = t;
         b->s3_lds = 0;
         const int base = scaled_lds(b, t, m);
-        for (double f : {1.0, 0.8, 0.65, 0.5}) {
-            const int l = std::max((int)(base * f) / 16 * 16, ssp::bt_sweep_min_lds(b->nx_max, true, 8));
-            if (!scaled_fits(b, t, l, m) || (f < 1.0 && l >= base)) continue;
+        for (double f : {1.0, 1.25, 1.5, 0.8}) {
+            const int l = std::min((int)(base * f) / 16 * 16, ssp::kFusedLdsCap);
+            if (!scaled_fits(b, t, l, m) || (f != 1.0 && l == base)) continue;
             b->s3_lds = l;
             float ms = 0.0f;
             for (int rep = 0; rep < 2 && rc == SSP_OK; ++rep) {
@@ -685,6 +702,7 @@ ssp_status ssp_build(ssp_batch *b, ssp_precon pc, ssp_precision prec, const doub
     b->pc = pc;
     b->prec = prec;
     b->scaled = scaled;
+    b->dinv_valid = !scaled;
     SSP_HIP(ssp::launch_fill_i32(prob_status, 0, b->P, s));
     ssp::BuildArgs a = build_args(b);
     a.A = A;
@@ -729,6 +747,7 @@ ssp_status ssp_build_from_blocks(ssp_batch *b, ssp_precon pc, ssp_precision prec
     b->pc = pc;
     b->prec = prec;
     b->scaled = false;
+    b->dinv_valid = true;
     SSP_HIP(ssp::launch_fill_i32(prob_status, 0, b->P, s));
     ssp::BuildArgs a = build_args(b);
     a.status = prob_status;
@@ -805,6 +824,8 @@ ssp_status ssp_export(ssp_batch *b, int which, double *diag, double *off, void *
     hipStream_t s = (hipStream_t)stream;
     ssp::BuildArgs a = build_args(b);
     if (which == 1) {
+        ssp_status rd = ensure_dinv(b, s);
+        if (rd != SSP_OK) return rd;
         SSP_HIP(ssp::launch_export(a, 2, b->B3, nullptr, b->fp32, diag, b->knots, s));
         ssp_status rc = ensure_m(b, s);
         if (rc != SSP_OK) return rc;

@@ -1,27 +1,27 @@
 // Batched PCG in the block-Jacobi congruence basis, one persistent grid.
 //
-// With D_k^-1 = Z_k Z_k^T (Z_k the lower Cholesky factor of D_k^-1) and
-// Z = blockdiag(Z_k), the congruence Z^T S Z = I + Oh has identity diagonal
-// blocks and the off-diagonal blocks Oh_k = Z_k^T L_k Z_{k-1} (below) and
-// Oh_k^T (above), with O = S - D and Z^T O Z = Oh.  The preconditioners of
-// the paper become polynomials in Oh:
-//   block-Jacobi (Eq. (jacobi)):          D^-1                = Z Z^T,
-//   symmetric stair (Sec. IV):            D^-1 - D^-1 O D^-1  = Z (I - Oh) Z^T,
-//   additive stair (Sec. III):            D^-1 - D^-1 O D^-1/2 = Z (I - Oh/2) Z^T,
+// With D_k = C_k C_k^T (Cholesky) and W_k = C_k^-1, the congruence
+// W S W^T = I + Oh (W = blockdiag(W_k)) has identity diagonal blocks and the
+// off-diagonal blocks Oh_k = W_k L_k W_{k-1}^T (below) and Oh_k^T (above),
+// with O = S - D and W O W^T = Oh; D^-1 = W^T W.  The preconditioners of the
+// paper become polynomials in Oh:
+//   block-Jacobi (Eq. (jacobi)):          D^-1                 = W^T W,
+//   symmetric stair (Sec. IV):            D^-1 - D^-1 O D^-1   = W^T (I - Oh) W,
+//   additive stair (Sec. III):            D^-1 - D^-1 O D^-1/2 = W^T (I - Oh/2) W,
 //   Neumann polynomial of degree m (Eq. (polynomial_precon), Psi = D,
-//   P = D - S = -O):  sum_{i<=m} (D^-1 P)^i D^-1 = Z (sum_{i<=m} (-Oh)^i) Z^T
+//   P = D - S = -O):  sum_{i<=m} (D^-1 P)^i D^-1 = W^T (sum_{i<=m} (-Oh)^i) W
 // (the stair identities are those of Eq. (stair_inv) with S = Psi_l + Psi_r - D).
-// PCG on S lambda = gamma with Phi^-1 = Z q(Oh) Z^T is therefore PCG on
-// (I + Oh) lh = Z^T gamma with the preconditioner q(Oh) and lambda = Z lh:
-// the same iterates in exact arithmetic, with residuals rh = Z^T r.  Each PCG
+// PCG on S lambda = gamma with Phi^-1 = W^T q(Oh) W is therefore PCG on
+// (I + Oh) lh = W gamma with the preconditioner q(Oh) and lambda = W^T lh:
+// the same iterates in exact arithmetic, with residuals rh = W r.  Each PCG
 // pass streams Oh_k only (nx^2 elements per knot instead of D_k, L_k and
 // D_k^-1), and the float operator I + Oh is as well conditioned as
 // block-Jacobi-preconditioned S, whatever the conditioning of the D_k.
 //
 // The refinement loop stays in the original basis: each outer step forms the
 // true residual r = gamma - S lambda in FP64 from D, L (hi + lo), maps it to
-// rh = Z^T r, runs the float PCG on (I + Oh) d = rh / ||rh|| (stopping on the
-// recurrence residual in the scaled basis) and adds ||rh|| Z d to lambda in
+// rh = W r, runs the float PCG on (I + Oh) d = rh / ||rh|| (stopping on the
+// recurrence residual in the scaled basis) and adds ||rh|| W^T d to lambda in
 // FP64.  FP64 storage runs the same loop in FP64 (further outer steps restart
 // the FP64 iteration from the true residual).
 //
@@ -84,6 +84,16 @@ __host__ __device__ inline int knots3(int lds_bytes, int m) {
 template <typename TM, int BLOCK, int NX>
 int lds3_for(int C, int m) {
     return (C + m + 2) * (bstride<TM, NX>() + (m + 1) * vstride<TM, NX>()) * (int)sizeof(TM) + 16;
+}
+
+// Knots per step of residual_lean for an LDS budget: C + 1 knot slots of D
+// (packed) and L in FP64 and a lambda window of C + 2 knots.
+template <typename TM, int NX>
+__host__ __device__ inline int residual3_knots(int lds_bytes) {
+    constexpr int V = vlen<TM>();
+    constexpr int SS = (NX * (NX + 1) / 2 + V - 1) / V * V + bstride<TM, NX>(), NXP = (NX + 1) & ~1;
+    int C = (lds_bytes / 8 - NXP) / (SS + NXP) - 1;
+    return C < 64 ? C : 64;
 }
 
 template <typename TI>
@@ -223,10 +233,10 @@ __device__ __forceinline__ Dots3<TI> scaled_pass(const Geo3 &g, bool init, bool 
                 const int k = lo + kk, dk = k - k0;
                 const int s = slot_of(sb, dk, R);
                 TI t = TI(0);
-                if (k > 0) t += row_dot<NX>(ring + s * BS, i, hin + slot_of(sb, dk - 1, R) * NXP, NX);
+                if (k > 0) t += lean_dot<NX, false>(ring + s * BS, i, hin + slot_of(sb, dk - 1, R) * NXP);
                 if (k + 1 < N) {
                     const int sp = slot_of(sb, dk + 1, R);
-                    t += col_dot<NX>(ring + sp * BS, i, hin + sp * NXP, NX);
+                    t += lean_dot<NX, true>(ring + sp * BS, i, hin + sp * NXP);
                 }
                 const TI rk = win[s * NXP + i];
                 const TI h = rk - cc * t;
@@ -249,10 +259,10 @@ __device__ __forceinline__ Dots3<TI> scaled_pass(const Geo3 &g, bool init, bool 
                 const int s = slot_of(sb, dk, R);
                 const TI uk = u[s * NXP + i];
                 TI w = uk;
-                if (k > 0) w += row_dot<NX>(ring + s * BS, i, u + slot_of(sb, dk - 1, R) * NXP, NX);
+                if (k > 0) w += lean_dot<NX, false>(ring + s * BS, i, u + slot_of(sb, dk - 1, R) * NXP);
                 if (k + 1 < N) {
                     const int sp = slot_of(sb, dk + 1, R);
-                    w += col_dot<NX>(ring + sp * BS, i, u + sp * NXP, NX);
+                    w += lean_dot<NX, true>(ring + sp * BS, i, u + sp * NXP);
                 }
                 d.del += w * uk;
                 v.w[k * NX + i] = w;
@@ -264,7 +274,74 @@ __device__ __forceinline__ Dots3<TI> scaled_pass(const Geo3 &g, bool init, bool 
     return d;
 }
 
-// rh = Z^T r on every knot (Z_k stored full, zero above the diagonal);
+// r = gamma - S lambda in FP64 with S read as D (packed) and L in the
+// storage type plus their FP32 remainders (or FP64), in steps of C knots:
+// the step's D, L (and L of the next knot) are converted to FP64 into LDS
+// with 16-byte loads, lambda of knots k0 - 1 .. k1 into a window, then r is
+// formed for knots [k0, k1).  No loads cross a step, so the pass needs few
+// registers (it runs once per outer step).  Returns this thread's parts of
+// ||r||^2 and ||gamma||^2, summed over the same rows in the same order.
+template <typename TM, int BLOCK, int NX>
+__device__ __forceinline__ ResNorms residual_lean(int N, int C, const TM *__restrict__ B3,
+                                                  const float *__restrict__ Dlo, const float *__restrict__ Llo,
+                                                  const double *__restrict__ lam, const double *__restrict__ gam,
+                                                  double *__restrict__ r64, double *smem) {
+    constexpr int V = vlen<TM>(), KW = 64 / NX, W = BLOCK / 64, NXP = (NX + 1) & ~1;
+    constexpr int BS = bstride<TM, NX>(), BP = (NX * (NX + 1) / 2 + V - 1) / V * V, KS = 2 * BP + BS;
+    constexpr int SS = BP + BS;  // FP64 slot: D packed, then L
+    constexpr bool LO = sizeof(TM) == 4;
+    double *ring = smem, *win = smem + (C + 1) * SS;  // C + 1 knot slots, C + 2 window slots
+    const int lane = threadIdx.x & 63, kloc = lane / NX, i = lane - kloc * NX;
+    const bool lane_ok = kloc < KW;
+    const int kme = (threadIdx.x >> 6) * KW + kloc, group = W * KW;
+    double rr = 0.0, gg = 0.0;
+    __syncthreads();  // lambda rows were just written by other threads
+    for (int k0 = 0; k0 < N; k0 += C) {
+        const int k1 = min(k0 + C, N), kl = min(k1 + 1, N);  // blocks of knots [k0, kl)
+        const int nv = (kl - k0) * (SS / V);
+        for (int q = threadIdx.x; q < nv; q += BLOCK) {
+            const int kk = q / (SS / V), e = (q - kk * (SS / V)) * V;
+            const int64_t k = k0 + kk;
+            const TM *src = B3 + k * KS + e;  // D packed then L: the first SS elements of the knot
+            double *dst = ring + kk * SS + e;
+            if constexpr (LO) {
+                const f32x4 h = *(const f32x4 *)src;
+                const f32x4 l = *(const f32x4 *)(e < BP ? Dlo + k * BP + e : Llo + k * BS + (e - BP));
+                dst[0] = (double)h.x + (double)l.x;
+                dst[1] = (double)h.y + (double)l.y;
+                dst[2] = (double)h.z + (double)l.z;
+                dst[3] = (double)h.w + (double)l.w;
+            } else {
+                const f64x2 h = *(const f64x2 *)src;
+                dst[0] = h.x;
+                dst[1] = h.y;
+            }
+        }
+        const int lo = max(k0 - 1, 0), nl = (kl - lo) * NX;
+        for (int q = threadIdx.x; q < nl; q += BLOCK) {
+            const int kk = q / NX, j = q - kk * NX;
+            win[kk * NXP + j] = lam[(int64_t)lo * NX + q];
+        }
+        __syncthreads();
+        for (int kk = kme; kk < k1 - k0; kk += group) {
+            if (!lane_ok) break;
+            const int k = k0 + kk, wk = k - lo;  // window slot of knot k
+            const double *Dk = ring + kk * SS;
+            double y = lean_sym_dot<NX>(Dk, i, win + wk * NXP);
+            if (k > 0) y += lean_dot<NX, false>(Dk + BP, i, win + (wk - 1) * NXP);
+            if (k + 1 < N) y += lean_dot<NX, true>(ring + (kk + 1) * SS + BP, i, win + (wk + 1) * NXP);
+            const double gv = gam[(int64_t)k * NX + i];
+            const double r = gv - y;
+            r64[(int64_t)k * NX + i] = r;
+            rr += r * r;
+            gg += gv * gv;
+        }
+        __syncthreads();
+    }
+    return ResNorms{rr, gg};
+}
+
+// rh = W r on every knot (W_k stored full, zero above the diagonal);
 // returns this thread's part of ||rh||^2.
 template <typename TM, int BLOCK, int NX>
 __device__ __forceinline__ double zt_apply(int N, const TM *__restrict__ Z, const double *__restrict__ r,
@@ -279,11 +356,11 @@ __device__ __forceinline__ double zt_apply(int N, const TM *__restrict__ Z, cons
             const TM *zk = Z + (int64_t)k * BS;
             const double *rk = r + (int64_t)k * NX;
             double s0 = 0.0, s1 = 0.0;
-            static_for<0, NX / 2>([&](auto lc) {
-                constexpr int l = 2 * decltype(lc)::value;
-                s0 += (double)zk[l * NX + i] * rk[l];
-                s1 += (double)zk[(l + 1) * NX + i] * rk[l + 1];
-            });
+#pragma unroll 4
+            for (int l = 0; l < NX; l += 2) {
+                s0 += (double)zk[i * NX + l] * rk[l];
+                s1 += (double)zk[i * NX + l + 1] * rk[l + 1];
+            }
             const double s = s0 + s1;
             rh[(int64_t)k * NX + i] = s;
             acc += s * s;
@@ -292,7 +369,7 @@ __device__ __forceinline__ double zt_apply(int N, const TM *__restrict__ Z, cons
     return acc;
 }
 
-// lam += scale * Z x on every knot.
+// lam += scale * W^T x on every knot.
 template <typename TM, typename TI, int BLOCK, int NX>
 __device__ __forceinline__ void z_apply_add(int N, const TM *__restrict__ Z, const TI *__restrict__ x, double scale,
                                             double *__restrict__ lam) {
@@ -302,14 +379,14 @@ __device__ __forceinline__ void z_apply_add(int N, const TM *__restrict__ Z, con
     __syncthreads();  // x rows come from other threads
     if (kloc < KW) {
         for (int k = kme; k < N; k += group) {
-            const TM *zk = Z + (int64_t)k * BS + i * NX;
+            const TM *zk = Z + (int64_t)k * BS + i;
             const TI *xk = x + (int64_t)k * NX;
             double s0 = 0.0, s1 = 0.0;
-            static_for<0, NX / 2>([&](auto lc) {
-                constexpr int l = 2 * decltype(lc)::value;
-                s0 += (double)zk[l] * (double)xk[l];
-                s1 += (double)zk[l + 1] * (double)xk[l + 1];
-            });
+#pragma unroll 4
+            for (int l = 0; l < NX; l += 2) {
+                s0 += (double)zk[l * NX] * (double)xk[l];
+                s1 += (double)zk[(l + 1) * NX] * (double)xk[l + 1];
+            }
             lam[(int64_t)k * NX + i] += scale * (s0 + s1);
         }
     }
@@ -344,9 +421,7 @@ __device__ __forceinline__ Outcome3 solve_scaled(const SolveArgs &a, const Prob3
     g.m = a.poly;
     g.C = knots3<TI, BLOCK, NX>(a.lds_bytes, g.m);
     g.R = g.C + g.m + 2;
-    const int Cres = residual_knots_per_step<TI>(NX, BLOCK, a.lds_bytes);
-    const Geo g64 = make_geo<double>(NX, block_stride(NX, sizeof(TI)), true, a.lds_bytes, BLOCK);
-    const int bs = block_stride(NX, sizeof(TI)), bp = packed_stride(NX, sizeof(TI)), ks = 2 * bp + bs;
+    const int Cres = residual3_knots<TI, NX>(a.lds_bytes);
     const TI cc = (TI)a.pc_c;
     int pending = kOk, base = 0;
     int mcur = g.m;  // block-Jacobi (m = 0) after a float breakdown of the polynomial
@@ -358,22 +433,8 @@ __device__ __forceinline__ Outcome3 solve_scaled(const SolveArgs &a, const Prob3
             rsrc = q.gam;
             o.rnorm = q.gnorm;
         } else {
-            ResNorms nr{0.0, 0.0};
-            if (Cres >= 1) {
-                nr = residual_pass<TI, BLOCK, NX>(N, Cres, q.B3, q.SDlo, q.SLlo, q.lam, q.gam, q.r64,
-                                                  (double *)smem_raw);
-            } else {
-                bt_sweep<double, TI, BLOCK, NX>(
-                    N, g64, q.B3, ks, q.SDlo, bp, q.B3 + bp, ks, q.SLlo, true, (double *)smem_raw,
-                    [&](int row) { return q.lam[row]; },
-                    [&](int row, double y, double) {
-                        const double gv = q.gam[row];
-                        const double r = gv - y;
-                        q.r64[row] = r;
-                        nr.rr += r * r;
-                        nr.gg += gv * gv;
-                    });
-            }
+            ResNorms nr = residual_lean<TI, BLOCK, NX>(N, Cres, q.B3, q.SDlo, q.SLlo, q.lam, q.gam, q.r64,
+                                                       (double *)smem_raw);
             block_sum2<BLOCK>(nr.rr, nr.gg, red64);
             o.rnorm = uniform(sqrt(nr.rr));
             gsame = uniform(sqrt(nr.gg));
@@ -414,7 +475,7 @@ __device__ __forceinline__ Outcome3 solve_scaled(const SolveArgs &a, const Prob3
         if (tau < a.tau_min) tau = a.tau_min;
         if (tau > 1.0) tau = 1.0;
 
-        // the right-hand side in the scaled basis
+        // the right-hand side in the scaled basis, rh = W r
         double hh = zt_apply<TI, BLOCK, NX>(N, q.Z, rsrc, q.rh64);
         hh = block_sum<BLOCK>(hh, red64);
         const double hn = uniform(sqrt(hh));
@@ -569,7 +630,7 @@ __device__ __forceinline__ void run_problem3(const SolveArgs &a, int p, int st_i
 // for the compiler too: each workgroup barrier is then reached the same
 // number of times by every wave.
 template <typename TI, int BLOCK>
-__global__ __launch_bounds__(BLOCK, 2) void k_pcg3(SolveArgs a) {
+__global__ __launch_bounds__(BLOCK, 3) void k_pcg3(SolveArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ double red64[2 * (BLOCK / kWave)];
     __shared__ TI redT[3 * (BLOCK / kWave)];
@@ -654,6 +715,16 @@ hipError_t allow_lds(const void *f) {
 }
 
 }  // namespace
+
+int pcg3_residual_steps(int nx, bool fp32, int lds_bytes) {
+    switch (nx) {
+        case 6: return fp32 ? residual3_knots<float, 6>(lds_bytes) : residual3_knots<double, 6>(lds_bytes);
+        case 14: return fp32 ? residual3_knots<float, 14>(lds_bytes) : residual3_knots<double, 14>(lds_bytes);
+        case 26: return fp32 ? residual3_knots<float, 26>(lds_bytes) : residual3_knots<double, 26>(lds_bytes);
+        case 36: return fp32 ? residual3_knots<float, 36>(lds_bytes) : residual3_knots<double, 36>(lds_bytes);
+    }
+    return 0;
+}
 
 int pcg3_steps_for(int nx, bool fp32, int threads, int lds_bytes, int m) {
     return fp32 ? knots3_rt<float>(nx, threads, lds_bytes, m) : knots3_rt<double>(nx, threads, lds_bytes, m);

@@ -89,6 +89,7 @@ struct ssp_batch {
     unsigned *dqueue = nullptr;
     bool have_scaled = false;  // Zs/OH/Zw/rh64 allocated for the current storage precision
     bool scaled = false;       // the last build wrote the scaled basis: ssp_solve runs the scaled kernel
+    bool dinv_valid = false;   // the stored D_k^-1 matches the last build (a scaled build leaves it out)
     int s3_threads = 256, s3_lds = 0;  // mapping of the scaled kernel (0: default budget)
     float s3_tuned_ms = 0.0f;
     // state

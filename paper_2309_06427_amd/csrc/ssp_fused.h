@@ -155,6 +155,50 @@ __device__ __forceinline__ T sym_dot(const T *__restrict__ P, int i, const T *__
     }
 }
 
+// Lean forms of the dot products for passes that must stay within few
+// registers: a loop over pairs of terms (x and row entries read as aligned
+// pairs), partially unrolled, so that the loads in flight are bounded by the
+// unroll factor instead of the whole row.  NX even.
+template <int NX, bool COL, typename T>
+__device__ __forceinline__ T lean_dot(const T *__restrict__ blk, int i, const T *__restrict__ x) {
+    static_assert(NX % 2 == 0, "compiled state sizes are even");
+    using P2 = typename std::conditional<sizeof(T) == 4, f32x2, f64x2>::type;
+    T s0 = T(0), s1 = T(0);
+#pragma unroll 4
+    for (int j = 0; j < NX; j += 2) {
+        const P2 v = *(const P2 *)(x + j);
+        T a0, a1;
+        if constexpr (COL) {
+            a0 = blk[j * NX + i];
+            a1 = blk[(j + 1) * NX + i];
+        } else {
+            const P2 w = *(const P2 *)(blk + i * NX + j);
+            a0 = w.x;
+            a1 = w.y;
+        }
+        s0 += a0 * v.x;
+        s1 += a1 * v.y;
+    }
+    return s0 + s1;
+}
+
+// Row i of a packed symmetric block (upper triangle by rows) times x, lean:
+// entries (j, i) for j < i down the column part, then row i from the diagonal.
+template <int NX, typename T>
+__device__ __forceinline__ T lean_sym_dot(const T *__restrict__ P, int i, const T *__restrict__ x) {
+    T s0 = T(0), s1 = T(0);
+    int pj = i;  // packed index of (0, i), then (j, i) = packed_row(j) + i
+#pragma unroll 2
+    for (int j = 0; j < i; ++j) {
+        s0 += P[pj] * x[j];
+        pj += NX - 1 - j;
+    }
+    const int ri = packed_row(i, NX);
+#pragma unroll 2
+    for (int j = i; j < NX; ++j) s1 += P[ri + j] * x[j];
+    return s0 + s1;
+}
+
 }  // namespace
 
 // 16-byte prefetch registers of the residual pass per array (FP32 storage
@@ -277,10 +321,10 @@ __device__ __forceinline__ ResNorms residual_pass(int N, int C, const TM *__rest
             if (!lane_ok) break;
             const int k = klo + kk, dk = k - k0;
             const double *Dk = ring + slot_of(sb, dk, R) * ss;
-            double y = sym_dot<NX>(Dk, i, win + slot_of(sw, dk, RL) * NXP, NX);  // D_k (packed)
-            if (k > 0) y += row_dot<NX>(Dk + BP, i, win + slot_of(sw, dk - 1, RL) * NXP, NX);
+            double y = lean_sym_dot<NX>(Dk, i, win + slot_of(sw, dk, RL) * NXP);  // D_k (packed)
+            if (k > 0) y += lean_dot<NX, false>(Dk + BP, i, win + slot_of(sw, dk - 1, RL) * NXP);
             if (k + 1 < N)
-                y += col_dot<NX>(ring + slot_of(sb, dk + 1, R) * ss + BP, i, win + slot_of(sw, dk + 1, RL) * NXP, NX);
+                y += lean_dot<NX, true>(ring + slot_of(sb, dk + 1, R) * ss + BP, i, win + slot_of(sw, dk + 1, RL) * NXP);
             const double gv = gam[(int64_t)k * NX + i];
             const double r = gv - y;
             r64[(int64_t)k * NX + i] = r;

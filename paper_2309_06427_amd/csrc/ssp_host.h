@@ -20,9 +20,10 @@ struct BuildArgs {
     void *B3;            // per knot k: D_k (packed), L_k (full), D_k^-1 (packed), storage type
     float *SDlo, *SLlo;  // FP64 remainders of D_k (packed stride), L_k (stride bs) under FP32 storage
     void *PM;           // explicit Phi^-1[k][k-1] blocks (stride bs; null: not built)
-    // scaled basis (null: not built): Z_k = lower Cholesky factor of D_k^-1
-    // and Oh_k = Z_k^T L_k Z_{k-1} (stride bs, storage type), Z_k in FP64
-    // (layout of Q) for the neighbouring knot's Oh
+    // scaled basis (null: not built): W_k = C_k^-1 with D_k = C_k C_k^T
+    // (lower triangular) and Oh_k = W_k L_k W_{k-1}^T (stride bs, storage
+    // type), W_k in FP64 (layout of Q) for the neighbouring knot's Oh; the
+    // stored D_k^-1 is then not written
     void *Zs, *OH;
     double *Zw;
     int32_t *status;
@@ -55,8 +56,8 @@ struct SolveArgs {
     int64_t tot_v;
     int lds_bytes;
     // scaled solve (congruence basis, persistent grid)
-    const void *OH, *Z;  // Oh_k and Z_k blocks (stride bs, full-block layout off_blk)
-    double *rh64;        // FP64 residual in the scaled basis, Z^T r, tot_v long
+    const void *OH, *Z;  // Oh_k and W_k blocks (stride bs, full-block layout off_blk)
+    double *rh64;        // FP64 residual in the scaled basis, W r, tot_v long
     unsigned *queue;     // next position in `order` (zeroed before every launch)
     int nprob;           // problems in the queue
     int poly;            // Horner steps m of the preconditioner polynomial in Oh (0: block-Jacobi)
@@ -75,6 +76,10 @@ hipError_t launch_build_class(int cls, const BuildArgs &a, const int2 *items, in
 // Scaled basis for one compiled state size, after launch_build_class wrote
 // Z_k (a.Zs, a.Zw): Oh_k = Z_k^T L_k Z_{k-1} for the same work items.
 hipError_t launch_build_ohat(int cls, const BuildArgs &a, const int2 *items, int nitems, bool fp32, hipStream_t s);
+// D_k^-1 = W_k^T W_k into the stored D_k^-1 slots after a scaled build
+// (from the FP64 W of a.Zw), for the consumers of D^-1 (export, explicit
+// stair blocks).
+hipError_t launch_dinv_from_w(const BuildArgs &a, int64_t knots, int nx_max, bool fp32, hipStream_t s);
 // Scalar Jacobi: overwrite every stored D_k^-1 with diag(1 / (D_k)_ii).
 hipError_t launch_jacobi_diag(const BuildArgs &a, int64_t knots, bool fp32, hipStream_t s);
 // S from caller-given blocks D_k, L_k (every knot of the batch): stored D,
@@ -133,6 +138,8 @@ hipError_t launch_pcg3(const SolveArgs &a, bool fp32, int threads, int grid, hip
 // gives (< 1: cannot run).
 int pcg3_lds(int nx, bool fp32, int threads, int m);
 int pcg3_steps_for(int nx, bool fp32, int threads, int lds_bytes, int m);
+// Knots per step of the scaled solve's FP64 residual for a budget (< 1: none).
+int pcg3_residual_steps(int nx, bool fp32, int lds_bytes);
 // Workgroups of k_pcg3 resident per CU with this LDS budget, and CUs.
 int pcg3_occupancy(bool fp32, int threads, int lds_bytes, int *cus);
 

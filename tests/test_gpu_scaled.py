@@ -1,10 +1,10 @@
 """The scaled solve (one persistent grid over the batch, PCG in the basis
-Z^T S Z = I + Oh with Z_k the Cholesky factor of D_k^-1) against the CPU oracle.
+W S W^T = I + Oh with W_k = C_k^-1, D_k = C_k C_k^T) against the CPU oracle.
 
 Tolerances
-  * Z_k and Oh_k (FP64 storage): Z_k Z_k^T = D_k^-1 and Oh_k = Z_k^T L_k Z_{k-1}
-    to 1e-11 relative; the preconditioners they apply, assembled densely, equal
-    the oracle's Phi^-1 to 1e-10 (FP64) / 1e-5 (FP32 storage rounding).
+  * W_k and Oh_k (FP64 storage): W_k^T W_k = D_k^-1 and Oh_k = W_k L_k W_{k-1}^T
+    to 1e-10 relative; the preconditioners they apply, assembled densely, equal
+    the oracle's Phi^-1 to 1e-9 (FP64) / 2e-4 (FP32 storage rounding).
   * Solves: true FP64 relative residual <= tol on every problem (the
     library's own check, recomputed here by the oracle from the returned
     lambda) and ||lam - lam*|| / ||lam*|| <= kappa_2(S) * tol against the
@@ -91,9 +91,10 @@ def test_preconditioner_ordering_on_the_gpu():
 
 @pytest.mark.parametrize("prec,rtol", [("fp64", 1e-11), ("fp32_refine64", 2e-6)])
 def test_scaled_basis_blocks(prec, rtol):
-    """Exported Z_k, Oh_k: Z_k lower triangular with Z_k Z_k^T = D_k^-1, Oh_k =
-    Z_k^T L_k Z_{k-1}; Z (I - Oh) Z^T and Z (I - Oh/2) Z^T are the oracle's
-    symmetric and additive stair preconditioners (Sec. IV, Sec. III)."""
+    """Exported W_k, Oh_k: W_k lower triangular with W_k^T W_k = D_k^-1, Oh_k =
+    W_k L_k W_{k-1}^T; W^T (I - Oh) W and W^T (I - Oh/2) W are the oracle's
+    symmetric and additive stair preconditioners (Sec. IV, Sec. III), and the
+    D^-1 exported after the scaled build (formed as W^T W) is the oracle's."""
     from paper_2309_06427_amd import solver
     b = inputs.batch(8, seed=73, N_range=(2, 12), nx_choices=CLASSES)
     n = int(b.off_nn[-1])
@@ -103,8 +104,11 @@ def test_scaled_basis_blocks(prec, rtol):
         Zf = torch.empty(n, dtype=torch.float64, device="cuda")
         Of = torch.empty(n, dtype=torch.float64, device="cuda")
         db.solver.export(3, Zf, Of)
+        Df = torch.empty(n, dtype=torch.float64, device="cuda")
+        Mf = torch.empty(n, dtype=torch.float64, device="cuda")
+        db.solver.export(1, Df, Mf)
         torch.cuda.synchronize()
-        Zf, Of = Zf.cpu().numpy(), Of.cpu().numpy()
+        Zf, Of, Df, Mf = Zf.cpu().numpy(), Of.cpu().numpy(), Df.cpu().numpy(), Mf.cpu().numpy()
     for i in range(b.P):
         p = b.problem(i)
         N, nx = int(b.N[i]), int(b.nx[i])
@@ -113,19 +117,23 @@ def test_scaled_basis_blocks(prec, rtol):
         _, D, L, Di, Msym = oracle.build(p["A"], p["B"], p["Q"], p["R"], "sym")
         _, _, _, _, Madd = oracle.build(p["A"], p["B"], p["Q"], p["R"], "add")
         assert not np.triu(Z, 1).any()
+        Dig = Df[b.off_nn[i]:b.off_nn[i + 1]].reshape(N, nx, nx)
+        Mg = Mf[b.off_nn[i]:b.off_nn[i + 1]].reshape(N, nx, nx)
+        assert np.abs(Dig - Di).max() <= rtol * 100 * np.abs(Di).max()
+        assert np.abs(Mg - Msym).max() <= rtol * 100 * max(np.abs(Msym).max(), 1e-30)
         for k in range(N):
             scale = np.abs(Di[k]).max()
-            assert np.abs(Z[k] @ Z[k].T - Di[k]).max() <= rtol * 10 * scale, (i, k)
+            assert np.abs(Z[k].T @ Z[k] - Di[k]).max() <= rtol * 10 * scale, (i, k)
         assert not Oh[0].any()
         for k in range(1, N):
-            want = Z[k].T @ L[k] @ Z[k - 1]
+            want = Z[k] @ L[k] @ Z[k - 1].T
             assert np.abs(Oh[k] - want).max() <= rtol * 10 * max(np.abs(want).max(), 1e-30), (i, k)
         Zd = np.zeros((N * nx, N * nx))
         for k in range(N):
             Zd[k * nx:(k + 1) * nx, k * nx:(k + 1) * nx] = Z[k]
         Od = dense.assemble(np.zeros_like(Oh), Oh)
         for c, M in ((1.0, Msym), (0.5, Madd)):
-            got = Zd @ (np.eye(N * nx) - c * Od) @ Zd.T
+            got = Zd.T @ (np.eye(N * nx) - c * Od) @ Zd
             want = dense.assemble(Di, M)
             assert np.abs(got - want).max() <= rtol * 100 * np.abs(want).max(), (i, c)
 
