@@ -85,7 +85,10 @@ typedef enum {
 /* Create a batch handle on HIP device `device` for `nprob` >= 1 problems of
  * sizes N[p], nx[p], nu[p] (HOST arrays, copied).  Allocates the metadata;
  * matrix storage is allocated by the first ssp_build.  *out receives the
- * handle (NULL on failure). */
+ * handle (NULL on failure).  SSP_ERR_ARG for N < 1, nx outside 1..64, nu
+ * outside 0..64, more than 2^31 - 1 knots in all, or when the per-knot FP64
+ * assembly's 8 (4 nx^2 + 2 nx nu + nu^2 + nx) bytes (largest nx, nu of the
+ * batch) exceed 160 KiB of LDS (e.g. nx = 64 allows nu <= 26). */
 ssp_status ssp_batch_create(int32_t nprob, const int32_t *N, const int32_t *nx, const int32_t *nu,
                             int device, ssp_batch **out);
 
@@ -95,10 +98,14 @@ ssp_status ssp_batch_destroy(ssp_batch *b);
 
 /* Packing offsets (HOST int64 arrays of nprob + 1 entries, any may be NULL):
  * problem p's A and Q blocks start at element off_nn[p], its B blocks at
- * off_nu[p], its R blocks at off_uu[p], its gamma / lambda entries at
- * off_v[p]; entry nprob is the total element count of each array. */
+ * off_nu[p], its R blocks at off_uu[p], its gamma / lambda (and state
+ * vector q, c, dx) entries at off_v[p], its control vectors (r, du: N nu
+ * entries) at off_u[p]; entry nprob is the total element count of each
+ * array.  The layout is the block structure of Sec. II-A: N block rows of
+ * state size nx, N - 1 controls of size nu (the last control block is
+ * padding). */
 ssp_status ssp_layout(const ssp_batch *b, int64_t *off_nn, int64_t *off_nu, int64_t *off_uu,
-                      int64_t *off_v);
+                      int64_t *off_v, int64_t *off_u);
 
 /* Build S and Phi^-1 (Sec. II-A block formulas; Sec. III / IV
  * preconditioners) from the per-knot blocks, entirely on the device in FP64,
@@ -168,6 +175,30 @@ ssp_status ssp_build_from_blocks(ssp_batch *b, ssp_precon pc, ssp_precision prec
 ssp_status ssp_solve(ssp_batch *b, double rel_tol, int32_t max_iter, const double *gamma,
                      double *lambda, int use_lambda0, int32_t *iters, double *relres,
                      int32_t *prob_status, void *stream);
+
+/* The KKT step around the solve (Sec. II-A, Eq. (schur) and the zeta blocks).
+ * The KKT system is [G C^T; C 0] [dz; lambda*] = [g; c] with
+ * G = blkdiag(Q_0, R_0, ..., R_{N-2}, Q_{N-1}), g = (q_0, r_0, ..., q_{N-1}) and
+ * C the dynamics constraints (block row 0: +I on x_0; block row k + 1:
+ * -A_k, -B_k, +I on x_k, u_k, x_{k+1}), the sign the paper's block form of
+ * gamma fixes.  Both calls need the Q_k^-1, R_k^-1 of the preceding ssp_build
+ * of this handle (SSP_ERR_STATE after ssp_build_from_blocks or before any
+ * build) and take the same A, B device arrays; all vectors are device FP64
+ * in the layout of ssp_layout (q, c, gamma, lambda, dx: off_v; r, du:
+ * off_u).  Numerically they follow the build: a problem flagged NOT_SPD
+ * there gets meaningless values.
+ *
+ * ssp_kkt_rhs: gamma = c - C G^-1 g, i.e. gamma_0 = c_0 - Q_0^-1 q_0 and
+ * gamma_k = c_k + zeta_{k-1} with zeta_k = A_k Q_k^-1 q_k + B_k R_k^-1 r_k
+ * - Q_{k+1}^-1 q_{k+1}; r's last block per problem is not read. */
+ssp_status ssp_kkt_rhs(ssp_batch *b, const double *A, const double *B, const double *q, const double *r,
+                       const double *c, double *gamma, void *stream);
+/* ssp_kkt_recover: dz* = G^-1 (g - C^T lambda*) for the solution lambda of
+ * ssp_solve (lambda* = -lambda):
+ *   dx_k = Q_k^-1 (q_k + lambda_k - A_k^T lambda_{k+1})  (k = N-1: no lambda_N term),
+ *   du_k = R_k^-1 (r_k - B_k^T lambda_{k+1})             (k <= N-2; du_{N-1} = 0). */
+ssp_status ssp_kkt_recover(ssp_batch *b, const double *A, const double *B, const double *q, const double *r,
+                           const double *lambda, double *dx, double *du, void *stream);
 
 /* Refinement steps (outer FP64 residual corrections) each problem took in
  * the last ssp_solve: copied into the caller's device int32[nprob]. */

@@ -27,7 +27,9 @@ _pi32, _pi64 = C.POINTER(C.c_int32), C.POINTER(C.c_int64)
 SIGNATURES = {
     "ssp_batch_create": (C.c_int, [_i32, _pi32, _pi32, _pi32, C.c_int, C.POINTER(_vp)]),
     "ssp_batch_destroy": (C.c_int, [_vp]),
-    "ssp_layout": (C.c_int, [_vp, _pi64, _pi64, _pi64, _pi64]),
+    "ssp_layout": (C.c_int, [_vp, _pi64, _pi64, _pi64, _pi64, _pi64]),
+    "ssp_kkt_rhs": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "ssp_kkt_recover": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "ssp_build": (C.c_int, [_vp, C.c_int, C.c_int, _vp, _vp, _vp, _vp, _vp, _vp]),
     "ssp_build_from_blocks": (C.c_int, [_vp, C.c_int, C.c_int, _vp, _vp, _vp, _vp]),
     "ssp_solve": (C.c_int, [_vp, _d, _i32, _vp, _vp, C.c_int, _vp, _vp, _vp, _vp]),

@@ -456,6 +456,7 @@ ssp_status ssp_batch_create(int32_t nprob, const int32_t *N, const int32_t *nx, 
     b->off_nu.assign(nprob + 1, 0);
     b->off_uu.assign(nprob + 1, 0);
     b->off_v.assign(nprob + 1, 0);
+    b->off_u.assign(nprob + 1, 0);
     b->koff.assign(nprob + 1, 0);
     for (int p = 0; p < nprob; ++p) {
         const int64_t n = N[p], x = nx[p], u = nu[p];
@@ -463,6 +464,7 @@ ssp_status ssp_batch_create(int32_t nprob, const int32_t *N, const int32_t *nx, 
         b->off_nu[p + 1] = b->off_nu[p] + n * x * u;
         b->off_uu[p + 1] = b->off_uu[p] + n * u * u;
         b->off_v[p + 1] = b->off_v[p] + n * x;
+        b->off_u[p + 1] = b->off_u[p] + n * u;
         b->koff[p + 1] = b->koff[p] + n;
         b->nx_max = std::max(b->nx_max, (int)x);
         b->nu_max = std::max(b->nu_max, (int)u);
@@ -484,6 +486,8 @@ ssp_status ssp_batch_create(int32_t nprob, const int32_t *N, const int32_t *nx, 
     const int64_t asm_bytes = 8 * (4ll * b->nx_max * b->nx_max + 2ll * b->nx_max * b->nu_max +
                                    (int64_t)b->nu_max * b->nu_max + b->nx_max);
     if (b->knots > INT32_MAX || asm_bytes > 160 * 1024) {
+        g_last_error = b->knots > INT32_MAX ? "more than 2^31 - 1 knots in the batch"
+                                            : "nx_max, nu_max: the per-knot FP64 assembly needs more than 160 KiB of LDS";
         delete b;
         return SSP_ERR_ARG;
     }
@@ -582,6 +586,7 @@ ssp_status ssp_batch_create(int32_t nprob, const int32_t *N, const int32_t *nx, 
     up(&b->doff_nu, b->off_nu.data(), nprob + 1);
     up(&b->doff_uu, b->off_uu.data(), nprob + 1);
     up(&b->doff_v, b->off_v.data(), nprob + 1);
+    up(&b->doff_u, b->off_u.data(), nprob + 1);
     up(&b->dkoff, b->koff.data(), nprob + 1);
     up(&b->doff_blk32, b->off_blk32.data(), nprob + 1);
     up(&b->doff_blk64, b->off_blk64.data(), nprob + 1);
@@ -630,16 +635,18 @@ ssp_status ssp_batch_destroy(ssp_batch *b) {
                         (void *)b->ditems, (void *)b->dgeneric, (void *)b->doff_nn, (void *)b->doff_nu, (void *)b->doff_uu, (void *)b->doff_v,
                         (void *)b->dkoff, (void *)b->doff_blk32, (void *)b->doff_blk64, (void *)b->doff_b3_32, (void *)b->doff_b3_64,
                         (void *)b->doff_pk32, (void *)b->dbar, (void *)b->drec, (void *)b->dwtag, (void *)b->Qinv, (void *)b->Rinv,
-                        (void *)b->r64, (void *)b->douter, (void *)b->dqueue})
+                        (void *)b->r64, (void *)b->douter, (void *)b->dqueue, (void *)b->doff_u})
             if (p) (void)hipFree(p);
     }
     delete b;
     return SSP_OK;
 }
 
-ssp_status ssp_layout(const ssp_batch *b, int64_t *off_nn, int64_t *off_nu, int64_t *off_uu, int64_t *off_v) {
+ssp_status ssp_layout(const ssp_batch *b, int64_t *off_nn, int64_t *off_nu, int64_t *off_uu, int64_t *off_v,
+                      int64_t *off_u) {
     if (!b) return SSP_ERR_ARG;
     const size_t cnt = (size_t)b->P + 1;
+    if (off_u) std::memcpy(off_u, b->off_u.data(), cnt * sizeof(int64_t));
     if (off_nn) std::memcpy(off_nn, b->off_nn.data(), cnt * sizeof(int64_t));
     if (off_nu) std::memcpy(off_nu, b->off_nu.data(), cnt * sizeof(int64_t));
     if (off_uu) std::memcpy(off_uu, b->off_uu.data(), cnt * sizeof(int64_t));
@@ -703,6 +710,7 @@ ssp_status ssp_build(ssp_batch *b, ssp_precon pc, ssp_precision prec, const doub
     b->prec = prec;
     b->scaled = scaled;
     b->dinv_valid = !scaled;
+    b->have_qr = true;
     SSP_HIP(ssp::launch_fill_i32(prob_status, 0, b->P, s));
     ssp::BuildArgs a = build_args(b);
     a.A = A;
@@ -748,6 +756,7 @@ ssp_status ssp_build_from_blocks(ssp_batch *b, ssp_precon pc, ssp_precision prec
     b->prec = prec;
     b->scaled = false;
     b->dinv_valid = true;
+    b->have_qr = false;
     SSP_HIP(ssp::launch_fill_i32(prob_status, 0, b->P, s));
     ssp::BuildArgs a = build_args(b);
     a.status = prob_status;
@@ -939,6 +948,38 @@ ssp_status ssp_get_mapping(const ssp_batch *b, int32_t max_groups, int32_t *nx, 
         if (lds_bytes) lds_bytes[i] = l;
         if (tuned_ms) tuned_ms[i] = b->groups[i].tuned_ms;
     }
+    return SSP_OK;
+}
+
+ssp_status ssp_kkt_rhs(ssp_batch *b, const double *A, const double *B, const double *q, const double *r,
+                       const double *c, double *gamma, void *stream) {
+    if (!b || !A || !q || !c || !gamma) return SSP_ERR_ARG;
+    if (b->nu_max > 0 && (!B || !r)) return SSP_ERR_ARG;
+    if (!b->built || !b->have_qr) {
+        g_last_error = "ssp_kkt_rhs needs a preceding ssp_build (its Q^-1, R^-1)";
+        return SSP_ERR_STATE;
+    }
+    DevGuard g(b->device);
+    ssp::BuildArgs a = build_args(b);
+    a.A = A;
+    a.B = B;
+    SSP_HIP(ssp::launch_kkt_rhs(a, b->doff_v, b->doff_u, q, r, c, gamma, b->knots, (hipStream_t)stream));
+    return SSP_OK;
+}
+
+ssp_status ssp_kkt_recover(ssp_batch *b, const double *A, const double *B, const double *q, const double *r,
+                           const double *lambda, double *dx, double *du, void *stream) {
+    if (!b || !A || !q || !lambda || !dx) return SSP_ERR_ARG;
+    if (b->nu_max > 0 && (!B || !r || !du)) return SSP_ERR_ARG;
+    if (!b->built || !b->have_qr) {
+        g_last_error = "ssp_kkt_recover needs a preceding ssp_build (its Q^-1, R^-1)";
+        return SSP_ERR_STATE;
+    }
+    DevGuard g(b->device);
+    ssp::BuildArgs a = build_args(b);
+    a.A = A;
+    a.B = B;
+    SSP_HIP(ssp::launch_kkt_recover(a, b->doff_v, b->doff_u, q, r, lambda, dx, du, b->knots, (hipStream_t)stream));
     return SSP_OK;
 }
 

@@ -49,7 +49,7 @@ struct ssp_batch {
     int device = 0;
     int P = 0;
     std::vector<int32_t> N, nx, nu;
-    std::vector<int64_t> off_nn, off_nu, off_uu, off_v, koff;
+    std::vector<int64_t> off_nn, off_nu, off_uu, off_v, off_u, koff;  // off_u: control vectors (N nu)
     std::vector<int64_t> off_blk32, off_blk64;  // full-block offsets (padded stride bs)
     std::vector<int64_t> off_b3_32, off_b3_64;  // solve-array offsets (knot stride)
     std::vector<int64_t> off_pk32;              // packed-block offsets (D remainders, FP32 storage)
@@ -67,6 +67,7 @@ struct ssp_batch {
     // global knot lists per state size (built on first use by the warm start)
     std::vector<std::pair<int, std::pair<int32_t *, int64_t>>> nx_knots;
     int64_t *doff_nn = nullptr, *doff_nu = nullptr, *doff_uu = nullptr, *doff_v = nullptr, *dkoff = nullptr;
+    int64_t *doff_u = nullptr;
     int64_t *doff_blk32 = nullptr, *doff_blk64 = nullptr;
     int64_t *doff_b3_32 = nullptr, *doff_b3_64 = nullptr, *doff_pk32 = nullptr;
     // FP64 build workspaces
@@ -94,6 +95,7 @@ struct ssp_batch {
     float s3_tuned_ms = 0.0f;
     // state
     bool built = false;
+    bool have_qr = false;  // Q^-1, R^-1 of the last build are in Qinv, Rinv (ssp_build, not from blocks)
     bool m_valid = false;  // explicit stair blocks PM match the last build
     ssp_precon pc = SSP_PC_SYM_STAIR;
     ssp_precision prec = SSP_FP64;

@@ -94,6 +94,16 @@ hipError_t launch_build_phi(const BuildArgs &a, int64_t knots, int nx_max, bool 
 hipError_t launch_export(const BuildArgs &a, int which, const void *hi, const float *lo, bool fp32, double *dst,
                          int64_t knots, hipStream_t s);
 hipError_t launch_fill_i32(int32_t *dst, int32_t v, int64_t n, hipStream_t s);
+
+// KKT step around the solve (FP64, every knot of the batch): gamma from q,
+// r, c, and dx, du from lambda, with the Q^-1, R^-1 of the last build
+// (a.Qinv, a.Rinv) and the caller's A, B (a.A, a.B).  Vector offsets:
+// off_v (state, N nx per problem), off_u (control, N nu per problem).
+hipError_t launch_kkt_rhs(const BuildArgs &a, const int64_t *off_v, const int64_t *off_u, const double *q,
+                          const double *r, const double *c, double *gamma, int64_t knots, hipStream_t s);
+hipError_t launch_kkt_recover(const BuildArgs &a, const int64_t *off_v, const int64_t *off_u, const double *q,
+                              const double *r, const double *lam, double *dx, double *du, int64_t knots,
+                              hipStream_t s);
 hipError_t launch_fill_f64(double *dst, double v, int64_t n, hipStream_t s);
 
 // Explicit two-sweep PCG (stored Phi^-1 blocks).

@@ -36,10 +36,10 @@ class BatchSolver:
         p32 = lambda a: a.ctypes.data_as(C.POINTER(C.c_int32))
         check(L.ssp_batch_create(self.P, p32(N), p32(nx), p32(nu), device, C.byref(h)), "ssp_batch_create")
         self._h = h
-        offs = [np.zeros(self.P + 1, dtype=np.int64) for _ in range(4)]
+        offs = [np.zeros(self.P + 1, dtype=np.int64) for _ in range(5)]
         p64 = lambda a: a.ctypes.data_as(C.POINTER(C.c_int64))
         check(L.ssp_layout(h, *(p64(o) for o in offs)), "ssp_layout")
-        self.off_nn, self.off_nu, self.off_uu, self.off_v = offs
+        self.off_nn, self.off_nu, self.off_uu, self.off_v, self.off_u = offs
 
     def close(self):
         """Free the handle's device resources (synchronises the device)."""
@@ -124,6 +124,14 @@ class BatchSolver:
     def export(self, which: int, diag, off, stream=None):
         check(_lib.load().ssp_export(self._h, which, _ptr(diag), _ptr(off), _stream(stream)), "ssp_export")
 
+    def kkt_rhs(self, A, B, q, r, c, gamma, stream=None):
+        check(_lib.load().ssp_kkt_rhs(self._h, _ptr(A), _ptr(B), _ptr(q), _ptr(r), _ptr(c), _ptr(gamma),
+                                      _stream(stream)), "ssp_kkt_rhs")
+
+    def kkt_recover(self, A, B, q, r, lam, dx, du, stream=None):
+        check(_lib.load().ssp_kkt_recover(self._h, _ptr(A), _ptr(B), _ptr(q), _ptr(r), _ptr(lam), _ptr(dx),
+                                          _ptr(du), _stream(stream)), "ssp_kkt_recover")
+
 
 class DeviceBatch:
     """A packed input batch (see :mod:`paper_2309_06427_amd.inputs`) resident on
@@ -174,6 +182,19 @@ class DeviceBatch:
         self.solver.solve(tol, max_iter, self.gamma, self.lam, use, self.iters, self.relres,
                           self.status, stream)
         self.solver.solve_outer(self.outer, stream)
+
+    def kkt_rhs(self, q, r, c, stream=None):
+        """gamma = c - C G^-1 g into self.gamma from device vectors q, r, c
+        (layouts off_v, off_u, off_v); needs a preceding build."""
+        self.solver.kkt_rhs(self.A, self.B, q, r, c, self.gamma, stream)
+
+    def kkt_recover(self, q, r, stream=None):
+        """(dx, du) = G^-1 (g - C^T lambda*) from the current self.lam."""
+        import torch
+        dx = torch.empty_like(self.gamma)
+        du = torch.zeros(max(int(self.solver.off_u[-1]), 1), dtype=torch.float64, device=self.gamma.device)
+        self.solver.kkt_recover(self.A, self.B, q, r, self.lam, dx, du, stream)
+        return dx, du
 
     def autotune(self, tol: float = 1e-6, stream=None) -> list:
         """Pick the fused kernel's mapping per state size on this batch (after a build)."""
