@@ -33,6 +33,7 @@
 #ifndef SYMSTAIR_H
 #define SYMSTAIR_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -175,6 +176,28 @@ ssp_status ssp_build_from_blocks(ssp_batch *b, ssp_precon pc, ssp_precision prec
 ssp_status ssp_solve(ssp_batch *b, double rel_tol, int32_t max_iter, const double *gamma,
                      double *lambda, int use_lambda0, int32_t *iters, double *relres,
                      int32_t *prob_status, void *stream);
+
+/* ssp_solve for callers that cannot allocate device memory at call time
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): same arguments, kernels and results, but the solve workspace
+ * (the persistent grid's work counter, the FP64 residual vectors and the
+ * seven inner-precision vectors, about 72 bytes per entry of lambda in FP64
+ * storage, 44 in FP32 storage) lives in one fixed array of
+ * SSP_NOALLOC_SCRATCH_BYTES per device, held from the library's first use
+ * on that device to the end of the process.  The call itself allocates
+ * nothing: no hipMalloc, hipFree or allocating library routine.
+ * Errors: SSP_ERR_ARG (checked first) when the batch needs more workspace
+ * than the array holds; SSP_ERR_STATE as for ssp_solve, and when the
+ * explicit-block kernel would first have to allocate its stair blocks (run
+ * one ssp_solve or ssp_export with the handle before).  Every call on a
+ * device shares that device's array (the work counter is reset by a fill
+ * kernel at each call; the vectors are written before they are read): calls
+ * whose execution overlaps on one device, from any handle, thread or
+ * stream, race and give undefined results. */
+#define SSP_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+ssp_status ssp_solve_noalloc(ssp_batch *b, double rel_tol, int32_t max_iter, const double *gamma,
+                             double *lambda, int use_lambda0, int32_t *iters, double *relres,
+                             int32_t *prob_status, void *stream);
 
 /* The KKT step around the solve (Sec. II-A, Eq. (schur) and the zeta blocks).
  * The KKT system is [G C^T; C 0] [dz; lambda*] = [g; c] with

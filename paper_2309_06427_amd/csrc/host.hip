@@ -290,7 +290,7 @@ ssp_status launch_scaled(ssp_batch *b, ssp::SolveArgs a, hipStream_t s) {
     a.max_outer = a.refine ? 5 : 1;
     a.theta = 0.5;
     a.tau_min = b->prec == SSP_FP64 ? 1e-15 : 1e-6;
-    SSP_HIP(ssp::launch_fill_i32((int32_t *)b->dqueue, 0, 1, s));
+    SSP_HIP(ssp::launch_fill_i32((int32_t *)a.queue, 0, 1, s));
     SSP_HIP(ssp::launch_pcg3(a, b->fp32, t, 0, s));
     b->last_kernel = 4;
     return SSP_OK;
@@ -616,6 +616,12 @@ ssp_status ssp_batch_create(int32_t nprob, const int32_t *N, const int32_t *nx, 
         ssp_batch_destroy(b);
         return rc;
     }
+    {
+        // device address of this device's fixed solve workspace (the
+        // allocation-free solve entry point), looked up once per device
+        DevGuard g(device);
+        (void)scratch_init(device);
+    }
     *out = b;
     return SSP_OK;
 }
@@ -766,14 +772,43 @@ ssp_status ssp_build_from_blocks(ssp_batch *b, ssp_precon pc, ssp_precision prec
     return SSP_OK;
 }
 
-ssp_status ssp_solve(ssp_batch *b, double rel_tol, int32_t max_iter, const double *gamma, double *lambda,
-                     int use_lambda0, int32_t *iters, double *relres, int32_t *prob_status, void *stream) {
+}  // extern "C"
+
+// ssp_solve and the allocation-free solve share this body
+size_t ssp_host::solve_scratch_bytes(const ssp_batch *b) {
+    const size_t nv = (size_t)b->off_v[b->P];
+    const size_t elem = b->built && b->fp32 ? sizeof(float) : sizeof(double);
+    auto up = [](size_t n) { return (n + 255) / 256 * 256; };
+    return 256 + 2 * up(nv * sizeof(double)) + up(7 * nv * elem);
+}
+
+ssp_host::SolveScratch ssp_host::carve_solve_scratch(const ssp_batch *b, void *base) {
+    const size_t nv = (size_t)b->off_v[b->P];
+    auto up = [](size_t n) { return (n + 255) / 256 * 256; };
+    char *p = (char *)base;
+    SolveScratch sc;
+    sc.queue = (unsigned *)p;
+    sc.r64 = (double *)(p + 256);
+    sc.rh64 = (double *)(p + 256 + up(nv * sizeof(double)));
+    sc.work = p + 256 + 2 * up(nv * sizeof(double));
+    return sc;
+}
+
+ssp_status ssp_host::solve_impl(ssp_batch *b, double rel_tol, int32_t max_iter, const double *gamma,
+                                double *lambda, int use_lambda0, int32_t *iters, double *relres,
+                                int32_t *prob_status, void *stream, const SolveScratch *sc) {
     if (!b || !gamma || !lambda || !iters || !relres || !prob_status) return SSP_ERR_ARG;
     if (!(rel_tol >= 0.0) || use_lambda0 < 0 || use_lambda0 > 2) return SSP_ERR_ARG;
     if (!b->built) return SSP_ERR_STATE;
     DevGuard g(b->device);
     hipStream_t s = (hipStream_t)stream;
     ssp::SolveArgs a = solve_args(b, rel_tol, max_iter, gamma, lambda, use_lambda0, iters, relres, prob_status);
+    if (sc) {
+        a.work = sc->work;
+        a.r64 = sc->r64;
+        a.rh64 = sc->rh64;
+        a.queue = sc->queue;
+    }
     if (b->scaled) return launch_scaled(b, a, s);
     if (use_coop(b)) {
         // one long problem: spread its knots over the whole grid
@@ -790,6 +825,11 @@ ssp_status ssp_solve(ssp_batch *b, double rel_tol, int32_t max_iter, const doubl
         b->last_kernel = 1;
         // explicit stored stair blocks (also the fallback when a knot does not
         // fit the fused kernel's registers or LDS)
+        if (sc && b->pc != SSP_PC_BLOCK_JACOBI && !b->PM) {
+            g_last_error = "the explicit kernel's stair blocks are not allocated yet (a first ssp_solve or "
+                           "ssp_export allocates them)";
+            return SSP_ERR_STATE;
+        }
         if (b->pc != SSP_PC_BLOCK_JACOBI) {
             ssp_status rc = ensure_m(b, s);
             if (rc != SSP_OK) return rc;
@@ -799,6 +839,14 @@ ssp_status ssp_solve(ssp_batch *b, double rel_tol, int32_t max_iter, const doubl
         SSP_HIP(ssp::launch_pcg(a, b->P, b->fp32, b->threads, s));
     }
     return SSP_OK;
+}
+
+extern "C" {
+
+ssp_status ssp_solve(ssp_batch *b, double rel_tol, int32_t max_iter, const double *gamma, double *lambda,
+                     int use_lambda0, int32_t *iters, double *relres, int32_t *prob_status, void *stream) {
+    return solve_impl(b, rel_tol, max_iter, gamma, lambda, use_lambda0, iters, relres, prob_status, stream,
+                      nullptr);
 }
 
 ssp_status ssp_solve_outer(const ssp_batch *b, int32_t *outer, void *stream) {

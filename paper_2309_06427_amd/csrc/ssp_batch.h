@@ -43,6 +43,15 @@ hipError_t dalloc(T **p, size_t count) {
     return hipMalloc((void **)p, count * sizeof(T));
 }
 
+// Solve workspace of one call: the handle's own, or the library's fixed
+// device array (the allocation-free entry point).
+struct SolveScratch {
+    unsigned *queue = nullptr;  // persistent grid's work counter (1 word)
+    double *r64 = nullptr;      // FP64 residual, tot_v long
+    double *rh64 = nullptr;     // FP64 residual in the scaled basis, tot_v long
+    void *work = nullptr;       // 7 vectors of the storage precision, tot_v long each
+};
+
 }  // namespace ssp_host
 
 struct ssp_batch {
@@ -121,3 +130,21 @@ struct ssp_batch {
     std::vector<hipStream_t> gstreams;
     std::vector<hipEvent_t> gevents;  // one per group, plus the fork event at the end
 };
+
+namespace ssp_host {
+
+// Bytes of solve workspace the batch needs (FP64 sizes before a build).
+size_t solve_scratch_bytes(const ssp_batch *b);
+// The workspace pointers inside a region of solve_scratch_bytes(b) bytes
+// at base (256-byte aligned).
+SolveScratch carve_solve_scratch(const ssp_batch *b, void *base);
+// ssp_solve with the workspace of sc (nullptr: the handle's own).
+ssp_status solve_impl(ssp_batch *b, double rel_tol, int32_t max_iter, const double *gamma, double *lambda,
+                      int use_lambda0, int32_t *iters, double *relres, int32_t *prob_status, void *stream,
+                      const SolveScratch *sc);
+// Looks up the device address of the fixed workspace array on `device`
+// (the current device) once; later calls return the recorded result (the
+// address into *ptr when ptr is not null).
+ssp_status scratch_init(int device, void **ptr = nullptr);
+
+}  // namespace ssp_host

@@ -78,6 +78,14 @@ class BatchSolver:
                                     int(use_lambda0), _ptr(iters), _ptr(relres), _ptr(status),
                                     _stream(stream)), "ssp_solve")
 
+    def solve_noalloc(self, tol: float, max_iter: int, gamma, lam, use_lambda0: int, iters, relres, status,
+                      stream=None):
+        """solve() with the library's fixed per-device workspace: the call
+        allocates no device memory (the batch must fit that workspace)."""
+        check(_lib.load().ssp_solve_noalloc(self._h, float(tol), int(max_iter), _ptr(gamma), _ptr(lam),
+                                            int(use_lambda0), _ptr(iters), _ptr(relres), _ptr(status),
+                                            _stream(stream)), "ssp_solve_noalloc")
+
     def autotune(self, tol: float, gamma, lam, iters, relres, status, stream=None):
         check(_lib.load().ssp_autotune(self._h, float(tol), _ptr(gamma), _ptr(lam), _ptr(iters), _ptr(relres),
                                        _ptr(status), _stream(stream)), "ssp_autotune")
@@ -171,16 +179,17 @@ class DeviceBatch:
         self.solver.build(pc, precision, self.A, self.B, self.Q, self.R, self.status, stream)
 
     def solve(self, tol: float = 1e-6, max_iter: int = 0, lam0=None, fallback: bool = False,
-              warm_in_place: bool = False, stream=None):
+              warm_in_place: bool = False, stream=None, noalloc: bool = False):
         """Solve from zero, from ``lam0`` (copied in), or from what ``self.lam``
         already holds (``warm_in_place``, e.g. written by a warm-start network);
-        with ``fallback`` a start that does not reduce the residual is dropped."""
+        with ``fallback`` a start that does not reduce the residual is dropped;
+        ``noalloc`` runs the allocation-free entry point."""
         if lam0 is not None:
             self.lam.copy_(lam0)
         warm = lam0 is not None or warm_in_place
         use = (2 if fallback else 1) if warm else 0
-        self.solver.solve(tol, max_iter, self.gamma, self.lam, use, self.iters, self.relres,
-                          self.status, stream)
+        run = self.solver.solve_noalloc if noalloc else self.solver.solve
+        run(tol, max_iter, self.gamma, self.lam, use, self.iters, self.relres, self.status, stream)
         self.solver.solve_outer(self.outer, stream)
 
     def kkt_rhs(self, q, r, c, stream=None):
