@@ -164,7 +164,8 @@ def main() -> int:
                     help="learned: also run the step with the trained warm-start networks "
                          "(auto: when their weights are present)")
     ap.add_argument("--mapping", default="",
-                    help="fixed per-state-size mapping nx:threads:lds,... instead of autotuning")
+                    help="fixed mapping instead of autotuning: per state size nx:threads:lds,... for the "
+                         "fused solve, or scaled:threads:lds for the scaled solve")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="keep the default mapping instead of timing candidates per state size first")
     ap.add_argument("--no-graph", dest="graph", action="store_false",
@@ -253,6 +254,10 @@ def main() -> int:
         # a fixed per-state-size mapping, "nx:threads:lds,..." (e.g. from an earlier autotune)
         db.build(args.pc, precision)
         for item in args.mapping.split(","):
+            if item.startswith("scaled:"):
+                t_, l_ = (int(v) for v in item.split(":")[1:])
+                db.solver.set_scaled_mapping(t_, l_)
+                continue
             nx_, t_, l_ = (int(v) for v in item.split(":"))
             db.solver.set_group_mapping(nx_, t_, l_)
         mapping = db.solver.mapping()

@@ -318,7 +318,8 @@ __global__ void k_export(BuildArgs a, int which, const TM *hi, const float *lo, 
 }
 
 // D_k^-1 = W_k^T W_k (W_k = C_k^-1, D_k = C_k C_k^T) into the stored D_k^-1
-// slot, from W in FP64; one workgroup per knot, W_k in LDS.
+// slot, from the stored W (storage type, block stride bs); one workgroup per
+// knot, W_k in LDS in FP64.
 template <typename TM>
 __global__ void k_dinv_from_w(BuildArgs a) {
     extern __shared__ double sm[];
@@ -326,7 +327,8 @@ __global__ void k_dinv_from_w(BuildArgs a) {
     knot_of(a, p, k);
     const int nx = a.nx[p], nn = nx * nx, bs = block_stride(nx, sizeof(TM)), bp = packed_stride(nx, sizeof(TM));
     TM *blk = (TM *)a.B3 + a.off_b3[p] + (int64_t)k * (2 * bp + bs);
-    team_load(sm, a.Zw + a.off_nn[p] + (int64_t)k * nn, nn);
+    const TM *W = (const TM *)a.Zs + a.off_blk[p] + (int64_t)k * bs;
+    for (int e = threadIdx.x; e < nn; e += T) sm[e] = (double)W[e];
     __syncthreads();
     for (int e = threadIdx.x; e < nn; e += T) {
         const int r = e / nx, c = e - r * nx;

@@ -326,6 +326,15 @@ __device__ __forceinline__ void load_row(const double *__restrict__ src, int n, 
     });
 }
 
+// Load a full row of NX entries of the storage type into FP64 registers.
+template <typename TM, int NX>
+__device__ __forceinline__ void load_row_t(const TM *__restrict__ src, double (&r)[NX]) {
+    static_for<0, NX>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        r[j] = (double)src[j];
+    });
+}
+
 template <int NX>
 __device__ __forceinline__ void store_row(double *__restrict__ dst, int n, const double (&r)[NX]) {
     static_for<0, NX>([&](auto jc) {
@@ -447,13 +456,10 @@ __global__ __launch_bounds__(kThreads) void k_build_asm_nx(BuildArgs a, const in
     bool ok;
     if (a.Zs) {
         // scaled basis: W_k = C_k^-1 instead of D_k^-1, stored full (zeros
-        // above the diagonal) in the storage type and in FP64 for phase 3;
-        // D_k^-1 = W_k^T W_k is formed only on demand
+        // above the diagonal) in the storage type; D_k^-1 = W_k^T W_k is
+        // formed only on demand
         ok = lower_inverse_rows<NX>(d, i, ln.row, M);
-        if (ln.row) {
-            store_split_row<TM, NX>((TM *)a.Zs + ol + i * NX, (float *)nullptr, d, 1.0);
-            store_row<NX>(a.Zw + a.off_nn[p] + (int64_t)k * nn + i * NX, NX, d);
-        }
+        if (ln.row) store_split_row<TM, NX>((TM *)a.Zs + ol + i * NX, (float *)nullptr, d, 1.0);
     } else {
         ok = gj_inverse_blocked<NX, kGjBlock>(d, i, ln.row, NX, M);
         symmetrise<NX>(d, i, ln.row, M);
@@ -463,8 +469,9 @@ __global__ __launch_bounds__(kThreads) void k_build_asm_nx(BuildArgs a, const in
 }
 
 // Phase 3 of the scaled basis: Oh_k = W_k L_k W_{k-1}^T (k >= 1, Oh_0 = 0)
-// in FP64 from W (FP64 workspace) and L_k (storage hi + FP32 remainder, or
-// FP64), stored in the storage type.  Both products are row-times-transpose
+// in FP64 from the stored W and L_k (storage type: the block the solve
+// applies is rounded to that type anyway, and the transforms use the same
+// stored W), stored in the storage type.  Both products are row-times-transpose
 // dot products against LDS rows: X = L_k W_{k-1}^T with the rows of W_{k-1}
 // in LDS, then row i of W_k X = sum_l W_k[i][l] X[l][:] with X^T in LDS
 // (lane i stores its row of X as LDS column i) and row i of W_k in registers.
@@ -484,23 +491,12 @@ __global__ __launch_bounds__(kThreads) void k_build_ohat_nx(BuildArgs a, const i
     double x[NX], t[NX];
     static_for<0, NX>([&](auto jc) { t[decltype(jc)::value] = 0.0; });
     if (prev) {
-        load_row<NX>(a.Zw + a.off_nn[p] + (int64_t)(k - 1) * nn + i * NX, NX, x);  // row i of W_{k-1}
+        load_row_t<TM, NX>((const TM *)a.Zs + ol - bs + i * NX, x);  // row i of W_{k-1}
         wave_sync();
         lds_put_row<NX>(M + i * NP, x);
         wave_sync();
-        // row i of L_k in FP64
-        const TM *Lk = (const TM *)a.B3 + a.off_b3[p] + (int64_t)k * (2 * bp + bs) + bp + i * NX;
-        static_for<0, NX>([&](auto jc) {
-            constexpr int j = decltype(jc)::value;
-            x[j] = (double)Lk[j];
-        });
-        if (a.SLlo) {
-            const float *lo = a.SLlo + ol + i * NX;
-            static_for<0, NX>([&](auto jc) {
-                constexpr int j = decltype(jc)::value;
-                x[j] += (double)lo[j];
-            });
-        }
+        // row i of L_k
+        load_row_t<TM, NX>((const TM *)a.B3 + a.off_b3[p] + (int64_t)k * (2 * bp + bs) + bp + i * NX, x);
         row_times_t<NX>(x, M, NX, t);  // t = row i of X = L_k W_{k-1}^T
         wave_sync();
         static_for<0, NX>([&](auto jc) {  // X^T: LDS column i
@@ -508,7 +504,7 @@ __global__ __launch_bounds__(kThreads) void k_build_ohat_nx(BuildArgs a, const i
             M[j * NP + i] = t[j];
         });
         wave_sync();
-        load_row<NX>(a.Zw + a.off_nn[p] + (int64_t)k * nn + i * NX, NX, x);  // row i of W_k
+        load_row_t<TM, NX>((const TM *)a.Zs + ol + i * NX, x);  // row i of W_k
         static_for<0, NX>([&](auto jc) { t[decltype(jc)::value] = 0.0; });
         row_times_t<NX>(x, M, NX, t);  // row i of W_k X
     } else {

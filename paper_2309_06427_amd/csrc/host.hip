@@ -21,10 +21,10 @@ thread_local std::string ssp_host::g_last_error = "no error";
 namespace {
 
 void free_scaled(ssp_batch *b) {
-    for (void *p : {b->Zs, b->OH, (void *)b->Zw, (void *)b->rh64})
+    for (void *p : {b->Zs, b->OH, (void *)b->rh64})
         if (p) (void)hipFree(p);
     b->Zs = b->OH = nullptr;
-    b->Zw = b->rh64 = nullptr;
+    b->rh64 = nullptr;
     b->have_scaled = false;
     b->scaled = false;
 }
@@ -46,7 +46,7 @@ ssp_status alloc_scaled(ssp_batch *b) {
     const size_t nn = (size_t)(b->fp32 ? b->off_blk32 : b->off_blk64)[b->P];
     if (hipMalloc(&b->Zs, std::max<size_t>(nn, 1) * elem) != hipSuccess ||
         hipMalloc(&b->OH, std::max<size_t>(nn, 1) * elem) != hipSuccess ||
-        dalloc(&b->Zw, (size_t)b->off_nn[b->P]) != hipSuccess || dalloc(&b->rh64, (size_t)b->off_v[b->P]) != hipSuccess) {
+        dalloc(&b->rh64, (size_t)b->off_v[b->P]) != hipSuccess) {
         free_scaled(b);
         g_last_error = "hipMalloc of scaled-basis storage failed";
         return SSP_ERR_ALLOC;
@@ -197,7 +197,6 @@ ssp::BuildArgs build_args(const ssp_batch *b) {
     a.SLlo = b->fp32 ? b->SLlo : nullptr;
     a.PM = b->PM;
     a.Zs = a.OH = nullptr;
-    a.Zw = nullptr;
     a.pc = (int)b->pc;
     a.mx = std::max(b->nx_max, b->nu_max);
     return a;
@@ -207,7 +206,7 @@ ssp::BuildArgs build_args(const ssp_batch *b) {
 ssp_status ensure_dinv(ssp_batch *b, hipStream_t s) {
     if (b->dinv_valid) return SSP_OK;
     ssp::BuildArgs a = build_args(b);
-    a.Zw = b->Zw;
+    a.Zs = b->Zs;
     SSP_HIP(ssp::launch_dinv_from_w(a, b->knots, b->nx_max, b->fp32, s));
     b->dinv_valid = true;
     return SSP_OK;
@@ -727,7 +726,6 @@ ssp_status ssp_build(ssp_batch *b, ssp_precon pc, ssp_precision prec, const doub
     if (scaled) {
         a.Zs = b->Zs;
         a.OH = b->OH;
-        a.Zw = b->Zw;
     }
     for (int c = 0; c < ssp::kBuildClasses; ++c)
         SSP_HIP(ssp::launch_build_class(c, a, b->ditems + b->item_off[c], b->item_off[c + 1] - b->item_off[c], fp32,

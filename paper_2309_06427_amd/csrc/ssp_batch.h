@@ -95,7 +95,7 @@ struct ssp_batch {
     // storage type (full blocks, stride bs), Z_k in FP64 (build only), the
     // scaled residual and the persistent grid's queue counter
     void *Zs = nullptr, *OH = nullptr;
-    double *Zw = nullptr, *rh64 = nullptr;
+    double *rh64 = nullptr;
     unsigned *dqueue = nullptr;
     bool have_scaled = false;  // Zs/OH/Zw/rh64 allocated for the current storage precision
     bool scaled = false;       // the last build wrote the scaled basis: ssp_solve runs the scaled kernel

@@ -22,10 +22,8 @@ struct BuildArgs {
     void *PM;           // explicit Phi^-1[k][k-1] blocks (stride bs; null: not built)
     // scaled basis (null: not built): W_k = C_k^-1 with D_k = C_k C_k^T
     // (lower triangular) and Oh_k = W_k L_k W_{k-1}^T (stride bs, storage
-    // type), W_k in FP64 (layout of Q) for the neighbouring knot's Oh; the
-    // stored D_k^-1 is then not written
+    // type); the stored D_k^-1 is then not written
     void *Zs, *OH;
-    double *Zw;
     int32_t *status;
     int pc;  // 0 block-Jacobi, 1 additive stair, 2 symmetric stair, 3 scalar Jacobi, 4/5 Neumann degree 2/3
     int mx;  // max(nx, nu) over the batch

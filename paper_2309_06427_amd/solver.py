@@ -51,10 +51,13 @@ class BatchSolver:
         # Never call into HIP while the interpreter shuts down: the runtime's
         # own exit handlers may already have torn the device state down.
         # Callers close handles explicitly; an unclosed handle at exit is
-        # reclaimed with the process.
-        if sys.is_finalizing():
+        # reclaimed with the process.  A closed handle needs nothing, and
+        # module globals may already be gone at that point.
+        if not getattr(self, "_h", None):
             return
         try:
+            if sys.is_finalizing():
+                return
             self.close()
         except Exception:
             pass
