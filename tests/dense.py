@@ -93,3 +93,26 @@ def precond_spectrum(Phi_inv, S):
     """Eigenvalues of Phi^-1 S through the SPD similar matrix L^T S L, Phi^-1 = L L^T."""
     Lc = np.linalg.cholesky(Phi_inv)
     return np.linalg.eigvalsh(Lc.T @ S @ Lc)
+
+
+def kappa(D, L):
+    """2-norm condition number of the SPD block-tridiagonal S with diagonal
+    blocks D_k and sub-diagonal blocks L_k = S[k][k-1] (L_0 unused): dense
+    eigenvalues for small S, else the extreme eigenvalues of the sparse S by
+    Lanczos (the smallest by shift-invert about zero)."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as sla
+    N, nx = D.shape[0], D.shape[1]
+    if N * nx <= 600:
+        ev = np.linalg.eigvalsh(assemble(D, L))
+        return float(ev[-1] / ev[0])
+    blocks = [[None] * N for _ in range(N)]
+    for k in range(N):
+        blocks[k][k] = sp.csr_matrix(D[k])
+        if k:
+            blocks[k][k - 1] = sp.csr_matrix(L[k])
+            blocks[k - 1][k] = sp.csr_matrix(L[k].T)
+    S = sp.bmat(blocks, format="csc")
+    lmax = sla.eigsh(S, k=1, which="LA", return_eigenvectors=False, tol=1e-6)[0]
+    lmin = sla.eigsh(S, k=1, sigma=0.0, which="LM", return_eigenvectors=False, tol=1e-6)[0]
+    return float(lmax / lmin)
