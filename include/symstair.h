@@ -314,6 +314,12 @@ ssp_status ssp_mlp_loss_grad(ssp_mlp *m, ssp_batch *b, int32_t p0, int32_t p1, c
                              const double *lambda_star, double *loss, void *stream);
 /* One Adam step (Kingma & Ba, bias-corrected) with the last gradient. */
 ssp_status ssp_mlp_adam(ssp_mlp *m, float lr, float beta1, float beta2, float eps, void *stream);
+/* Optimiser state for checkpoint / resume: the Adam first and second moments
+ * (device float[num_params] each, either may be NULL on get) and the number
+ * of Adam steps taken (host).  set_state after set_params (which resets
+ * them) continues training exactly where get_state left it. */
+ssp_status ssp_mlp_get_state(const ssp_mlp *m, float *m1, float *m2, int64_t *steps, void *stream);
+ssp_status ssp_mlp_set_state(ssp_mlp *m, const float *m1, const float *m2, int64_t steps, void *stream);
 /* FP32 matrix-core GEMM the network uses, C = op(A) op(B) (row-major, op =
  * transpose when trans_* != 0); exposed for tests. */
 ssp_status ssp_gemm_f32(int32_t M, int32_t N, int32_t K, const float *A, int32_t lda, int32_t trans_a,

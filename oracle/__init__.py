@@ -71,6 +71,9 @@ def lib():
         L.ssp_oracle_solve_batch.argtypes = [i, ip, ip, ip, i64, i64, i64, i64, d, d, d, d, d,
                                              i, i, C.c_double, i, i, C.c_double, C.c_double,
                                              i, d, ip, ip, d, ip]
+        L.ssp_oracle_build_batch.argtypes = [i, ip, ip, ip, i64, i64, i64, d, d, d, d, i, ip]
+        L.ssp_oracle_set_threads.argtypes = [i]
+        L.ssp_oracle_get_threads.restype = i
         _lib = L
     return _lib
 
@@ -195,6 +198,30 @@ def direct(D, L, gamma):
     lam = np.zeros(N * nx)
     st = lib().ssp_oracle_direct(N, nx, _dp(D), _dp(L), _dp(gamma), _dp(lam))
     return st, lam
+
+
+def set_threads(n: int) -> None:
+    """OpenMP threads of the batch drivers (timing)."""
+    lib().ssp_oracle_set_threads(int(n))
+
+
+def get_threads() -> int:
+    return int(lib().ssp_oracle_get_threads())
+
+
+def build_batch(b, pc: str = "sym") -> np.ndarray:
+    """The build alone for every problem of a packed batch (timing); returns
+    the per-problem build status."""
+    P = b.P
+    ip = lambda a: np.ascontiguousarray(a, dtype=np.int32).ctypes.data_as(C.POINTER(C.c_int))
+    N32, nx32, nu32 = (np.ascontiguousarray(a, dtype=np.int32) for a in (b.N, b.nx, b.nu))
+    offs = [np.ascontiguousarray(o, dtype=np.int64) for o in (b.off_nn, b.off_nu, b.off_uu)]
+    i64 = lambda a: a.ctypes.data_as(C.POINTER(C.c_int64))
+    A, B, Q, R = map(_f64, (b.A, b.B, b.Q, b.R))
+    status = np.zeros(P, dtype=np.int32)
+    lib().ssp_oracle_build_batch(P, ip(N32), ip(nx32), ip(nu32), *(i64(o) for o in offs), _dp(A), _dp(B), _dp(Q),
+                                 _dp(R), PC[pc], ip(status))
+    return status
 
 
 def solve_batch(b, pc: str = "sym", precision: str = "fp64", tol: float = 1e-8,

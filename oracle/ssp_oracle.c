@@ -42,6 +42,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 /* status codes (per problem); kept numerically equal to the library's */
 #define OR_OK 0
@@ -674,6 +677,40 @@ int ssp_oracle_kkt_recover(int N, int nx, int nu, const double *A, const double 
 }
 
 /* --------------------------------------------------------------- batch --- */
+
+/* OpenMP threads of the batch drivers (n >= 1; used to time one core). */
+void ssp_oracle_set_threads(int n) {
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
+int ssp_oracle_get_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* The build alone for every problem of a packed batch (the first half of
+ * ssp_oracle_solve_batch, timed on its own); per-problem build status. */
+void ssp_oracle_build_batch(int P, const int *Ns, const int *nxs, const int *nus, const int64_t *off_nn,
+                            const int64_t *off_nu, const int64_t *off_uu, const double *A, const double *B,
+                            const double *Q, const double *R, int pc, int *status) {
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int p = 0; p < P; ++p) {
+        const int N = Ns[p], nx = nxs[p], nu = nus[p];
+        const size_t nb = (size_t)N * nx * nx;
+        double *D = malloc(sizeof(double) * nb), *L = malloc(sizeof(double) * nb);
+        double *Di = malloc(sizeof(double) * nb), *M = malloc(sizeof(double) * nb);
+        status[p] = ssp_oracle_build(N, nx, nu, A + off_nn[p], B + off_nu[p], Q + off_nn[p], R + off_uu[p], pc,
+                                     D, L, Di, M);
+        free(D); free(L); free(Di); free(M);
+    }
+}
 
 /* Build and solve every problem of a packed ragged batch, one problem per
  * OpenMP task.  Offsets are per problem (see the generator's layout):

@@ -47,6 +47,8 @@ SIGNATURES = {
     "ssp_mlp_fit_scaling": (C.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "ssp_mlp_predict": (C.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "ssp_mlp_loss_grad": (C.c_int, [_vp, _vp, _i32, _i32, _vp, _vp, _vp, _vp]),
+    "ssp_mlp_get_state": (C.c_int, [_vp, _vp, _vp, C.POINTER(C.c_int64), _vp]),
+    "ssp_mlp_set_state": (C.c_int, [_vp, _vp, _vp, C.c_int64, _vp]),
     "ssp_mlp_adam": (C.c_int, [_vp, _f, _f, _f, _f, _vp]),
     "ssp_gemm_f32": (C.c_int, [_i32, _i32, _i32, _vp, _i32, _i32, _vp, _i32, _i32, _vp, _i32, _vp]),
     "ssp_autotune": (C.c_int, [_vp, _d, _vp, _vp, _vp, _vp, _vp, _vp]),

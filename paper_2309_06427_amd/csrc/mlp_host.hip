@@ -310,6 +310,26 @@ ssp_status ssp_mlp_adam(ssp_mlp *m, float lr, float beta1, float beta2, float ep
     return SSP_OK;
 }
 
+ssp_status ssp_mlp_get_state(const ssp_mlp *m, float *m1, float *m2, int64_t *steps, void *stream) {
+    if (!m || !steps) return SSP_ERR_ARG;
+    DevGuard g(m->device);
+    hipStream_t s = (hipStream_t)stream;
+    if (m1) SSP_HIP(hipMemcpyAsync(m1, m->m, sizeof(float) * m->np, hipMemcpyDeviceToDevice, s));
+    if (m2) SSP_HIP(hipMemcpyAsync(m2, m->v, sizeof(float) * m->np, hipMemcpyDeviceToDevice, s));
+    *steps = m->t;
+    return SSP_OK;
+}
+
+ssp_status ssp_mlp_set_state(ssp_mlp *m, const float *m1, const float *m2, int64_t steps, void *stream) {
+    if (!m || !m1 || !m2 || steps < 0) return SSP_ERR_ARG;
+    DevGuard g(m->device);
+    hipStream_t s = (hipStream_t)stream;
+    SSP_HIP(hipMemcpyAsync(m->m, m1, sizeof(float) * m->np, hipMemcpyDeviceToDevice, s));
+    SSP_HIP(hipMemcpyAsync(m->v, m2, sizeof(float) * m->np, hipMemcpyDeviceToDevice, s));
+    m->t = steps;
+    return SSP_OK;
+}
+
 ssp_status ssp_gemm_f32(int32_t M, int32_t N, int32_t K, const float *A, int32_t lda, int32_t trans_a,
                         const float *B, int32_t ldb, int32_t trans_b, float *C, int32_t ldc, void *stream) {
     if (M < 0 || N < 0 || K < 0 || !A || !B || !C) return SSP_ERR_ARG;

@@ -43,9 +43,11 @@ class WarmStartNet:
 
     def __del__(self):
         # no HIP call while the interpreter shuts down (see BatchSolver.__del__)
-        if sys.is_finalizing():
+        if not getattr(self, "_h", None):
             return
         try:
+            if sys.is_finalizing():
+                return
             self.close()
         except Exception:
             pass
@@ -114,30 +116,71 @@ class WarmStartNet:
                                        _stream(stream)), "ssp_mlp_adam")
 
     def train(self, db, lam_star, epochs: int, problems_per_step: int = 16, lr: float = 1e-3,
-              lr_final: float = 1e-4, seed: int = 0, log=None) -> np.ndarray:
+              lr_final: float = 1e-4, seed: int = 0, log=None, start_epoch: int = 0,
+              end_epoch: int | None = None) -> np.ndarray:
         """Adam over contiguous problem ranges of ``db`` (all of this nx), in a
         shuffled order each epoch; the learning rate decays geometrically from
-        ``lr`` to ``lr_final``.  Returns the mean loss of each epoch."""
+        ``lr`` to ``lr_final`` over all ``epochs``.  Runs epochs
+        [start_epoch, end_epoch) of that schedule (a resumed run passes the
+        epoch its checkpoint was taken at) and returns their mean losses."""
         import torch
         P = db.batch.P
+        end_epoch = epochs if end_epoch is None else end_epoch
         ranges = [(p, min(P, p + problems_per_step)) for p in range(0, P, problems_per_step)]
         steps = epochs * len(ranges)
-        losses = torch.zeros(steps, dtype=torch.float64, device=self._dev)
+        run = end_epoch - start_epoch
+        losses = torch.zeros(max(run, 0) * len(ranges), dtype=torch.float64, device=self._dev)
         rng = np.random.default_rng(seed)
         decay = (lr_final / lr) ** (1.0 / max(steps - 1, 1))
         i = 0
         t0 = time.perf_counter()
-        for ep in range(epochs):
-            for j in rng.permutation(len(ranges)):
+        for ep in range(end_epoch):
+            order = rng.permutation(len(ranges))  # drawn for skipped epochs too
+            if ep < start_epoch:
+                continue
+            for j in order:
                 p0, p1 = ranges[j]
                 self.loss_grad(db, p0, p1, lam_star, losses[i:i + 1])
-                self.adam(lr * decay ** i)
+                self.adam(lr * decay ** (ep * len(ranges) + (i % len(ranges))))
                 i += 1
             if log is not None:
                 ep_loss = float(losses[i - len(ranges):i].mean())
                 log(f"[warmstart nx={self.nx}] epoch {ep + 1}/{epochs} loss {ep_loss:.5g} "
                     f"({time.perf_counter() - t0:.1f} s)")
-        return losses.view(epochs, len(ranges)).mean(dim=1).cpu().numpy()
+        return losses.view(max(run, 0), len(ranges)).mean(dim=1).cpu().numpy()
+
+    # ---------------------------------------------------------- checkpoint --
+    def get_state(self):
+        """(first moments, second moments, Adam steps taken) of the optimiser."""
+        import torch
+        m1 = torch.empty(self.n_params, dtype=torch.float32, device=self._dev)
+        m2 = torch.empty(self.n_params, dtype=torch.float32, device=self._dev)
+        t = C.c_int64()
+        check(_lib.load().ssp_mlp_get_state(self._h, _ptr(m1), _ptr(m2), C.byref(t), _stream(None)),
+              "ssp_mlp_get_state")
+        return m1.cpu().numpy(), m2.cpu().numpy(), int(t.value)
+
+    def set_state(self, m1, m2, steps: int):
+        import torch
+        a = torch.as_tensor(np.asarray(m1, dtype=np.float32), device=self._dev).contiguous()
+        b = torch.as_tensor(np.asarray(m2, dtype=np.float32), device=self._dev).contiguous()
+        check(_lib.load().ssp_mlp_set_state(self._h, _ptr(a), _ptr(b), int(steps), _stream(None)),
+              "ssp_mlp_set_state")
+        torch.cuda.current_stream().synchronize()
+
+    def checkpoint(self, path: str, epoch: int, **meta):
+        """Weights, standardisation and optimiser state after ``epoch`` epochs."""
+        m1, m2, t = self.get_state()
+        self.save(path, adam_m=m1, adam_v=m2, adam_steps=np.int64(t), epoch=np.int64(epoch), **meta)
+
+    @classmethod
+    def resume(cls, path: str, device: int = 0):
+        """(network, epoch) from a checkpoint: training continues with
+        ``train(..., start_epoch=epoch)`` exactly as if never interrupted."""
+        z = np.load(path, allow_pickle=False)
+        net = cls.load(path, device)
+        net.set_state(z["adam_m"], z["adam_v"], int(z["adam_steps"]))
+        return net, int(z["epoch"])
 
     # ---------------------------------------------------------------- files --
     def save(self, path: str, **meta):

@@ -205,3 +205,58 @@ def test_fallback_restarts_from_zero_like_the_oracle():
     assert np.array_equal(gw["iters"], gz["iters"])
     assert np.abs(gw["lam"] - gz["lam"]).max() <= 1e-12 * np.abs(gz["lam"]).max()
     assert np.all(np.abs(gw["iters"] - ref0["iters"]) <= 1)
+
+
+def test_checkpoint_resume_is_bit_exact(tmp_path):
+    """Training stopped after one epoch, checkpointed (weights, standardisation,
+    Adam moments and step count) and resumed in a new network handle for the
+    second epoch gives the uninterrupted two-epoch run bit for bit."""
+    from paper_2309_06427_amd.warmstart import WarmStartNet, training_pool
+    nx, H = 6, 32
+    db, lam_star = training_pool(nx, 24, seed=23)
+    kw = dict(epochs=2, problems_per_step=4, lr=2e-3, lr_final=2e-4, seed=5)
+    theta0 = inputs.mlp_init(nx, H, seed=2).astype(np.float32)
+
+    full = WarmStartNet(nx, H)
+    full.set_params(theta0)
+    full.fit_scaling(db, lam_star)
+    hist_full = full.train(db, lam_star, **kw)
+    th_full, st_full = full.get_params(), full.get_state()
+
+    part = WarmStartNet(nx, H)
+    part.set_params(theta0)
+    part.fit_scaling(db, lam_star)
+    hist_1 = part.train(db, lam_star, end_epoch=1, **kw)
+    path = str(tmp_path / "ckpt.npz")
+    part.checkpoint(path, epoch=1)
+    part.close()
+    resumed, ep = WarmStartNet.resume(path)
+    assert ep == 1
+    hist_2 = resumed.train(db, lam_star, start_epoch=ep, **kw)
+    th_res, st_res = resumed.get_params(), resumed.get_state()
+    assert np.array_equal(np.concatenate([hist_1, hist_2]), hist_full)
+    assert np.array_equal(th_res, th_full)
+    assert np.array_equal(st_res[0], st_full[0]) and np.array_equal(st_res[1], st_full[1])
+    assert st_res[2] == st_full[2] == 2 * 6
+    for n in (full, resumed):
+        n.close()
+    db.close()
+
+
+def test_training_labels_match_the_oracle():
+    """The training pool's labels (the library's FP64 PCG to 1e-10) against the
+    oracle's direct solution on 256 systems: within kappa_2(S) * 1e-10."""
+    from tests import dense
+    from paper_2309_06427_amd.warmstart import training_pool
+    nx = 14
+    db, lam_star = training_pool(nx, 256, seed=31)
+    lab = lam_star.cpu().numpy()
+    b = db.batch
+    for i in range(b.P):
+        p = b.problem(i)
+        st, D, L, _, _ = oracle.build(p["A"], p["B"], p["Q"], p["R"], "sym")
+        assert st == oracle.OK
+        st, ref = oracle.direct(D, L, p["gamma"])
+        err = np.linalg.norm(lab[b.off_v[i]:b.off_v[i + 1]] - ref) / np.linalg.norm(ref)
+        assert err <= dense.kappa(D, L) * 1e-10, (i, err)
+    db.close()
