@@ -352,6 +352,14 @@ ssp_status ssp_set_group_mapping(ssp_batch *b, int32_t nx, int32_t threads, int3
 ssp_status ssp_get_mapping(const ssp_batch *b, int32_t max_groups, int32_t *nx, int32_t *threads,
                            int32_t *lds_bytes, float *tuned_ms, int32_t *ngroups);
 
+/* Accumulation of the PCG inner products (r.u, w.u, r.r; Sec. II-B) in the
+ * scaled solve under FP32 storage: on = 0 (default) sums the FP32 products
+ * in FP32 (per-lane partial sums, then a fixed-order workgroup tree), on = 1
+ * sums the same FP32 products in FP64 and rounds the totals to FP32.  FP64
+ * storage always sums in FP64; the fused, cooperative and explicit solves
+ * sum in their storage type.  Takes effect at the next solve. */
+ssp_status ssp_set_reduction_fp64(ssp_batch *b, int32_t on);
+
 /* Mapping of the scaled solve (kernel 4): threads 128 or 256 and the LDS
  * budget per workgroup (0 = the largest pipeline step of every state size);
  * 0, 0 restores the defaults.  ssp_autotune tunes both when the last build

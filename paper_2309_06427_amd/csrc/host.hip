@@ -273,6 +273,7 @@ ssp::SolveArgs solve_args(const ssp_batch *b, double rel_tol, int32_t max_iter, 
     a.nprob = b->P;
     a.poly = poly_steps(b->pc);
     a.pc_c = b->pc == SSP_PC_STAIR_ADD ? 0.5 : 1.0;
+    a.acc64 = b->acc64;
     return a;
 }
 
@@ -1029,6 +1030,12 @@ ssp_status ssp_kkt_recover(ssp_batch *b, const double *A, const double *B, const
     return SSP_OK;
 }
 
+ssp_status ssp_set_reduction_fp64(ssp_batch *b, int32_t on) {
+    if (!b || (on != 0 && on != 1)) return SSP_ERR_ARG;
+    b->acc64 = on;
+    return SSP_OK;
+}
+
 ssp_status ssp_set_scaled_mapping(ssp_batch *b, int32_t threads, int32_t lds_bytes) {
     if (!b) return SSP_ERR_ARG;
     if (threads == 0 && lds_bytes == 0) {
@@ -1063,7 +1070,7 @@ ssp_status ssp_get_scaled_mapping(const ssp_batch *b, int32_t *threads, int32_t 
     if (grid) {
         DevGuard g(b->device);
         int cus = 0;
-        const int occ = ssp::pcg3_occupancy(b->fp32, t, l, &cus);
+        const int occ = ssp::pcg3_occupancy(b->fp32, t, l, &cus, b->fp32 && b->acc64);
         *grid = std::min(occ * cus, b->P);
     }
     return SSP_OK;

@@ -101,9 +101,12 @@ struct Vecs3 {
     TI *u, *w, *p, *s, *x, *r;
 };
 
+// Per-lane partial inner products of one pass: in the storage type, or (the
+// FP64-accumulation option) the same storage-type products summed in FP64.
 template <typename TI>
 struct Dots3 {
     TI gam, del, rho;
+    double g64 = 0.0, d64 = 0.0, r64 = 0.0;
 };
 
 // Register prefetch of one step: the step's Oh blocks (one contiguous chunk,
@@ -160,8 +163,23 @@ struct Prefetch3 {
     }
 };
 
+// Workgroup sums of a pass's partial inner products (fixed-order trees; in
+// FP64 under the FP64-accumulation option, then rounded to the storage type).
+template <typename TI, int BLOCK>
+__device__ __forceinline__ Dots3<TI> reduce_dots(Dots3<TI> dt, bool acc64, double *red64, TI *redT) {
+    if (acc64) {
+        block_sum2<BLOCK>(dt.g64, dt.d64, red64);
+        dt.r64 = block_sum<BLOCK>(dt.r64, red64 + 2 * (BLOCK / kWave));
+        return Dots3<TI>{uniform((TI)dt.g64), uniform((TI)dt.d64), uniform((TI)dt.r64)};
+    }
+    block_sum2<BLOCK>(dt.gam, dt.del, redT);
+    dt.rho = block_sum<BLOCK>(dt.rho, redT + 2 * (BLOCK / kWave));
+    return Dots3<TI>{uniform(dt.gam), uniform(dt.del), uniform(dt.rho)};
+}
+
 struct Geo3 {
     int N, C, R, m;  // knots, knots per step, ring slots, Horner steps
+    bool acc64;      // accumulate the inner products in FP64
 };
 
 // One pass over the knots (see the file comment).  init: the pass that starts
@@ -215,10 +233,17 @@ __device__ __forceinline__ Dots3<TI> scaled_pass(const Geo3 &g, bool init, bool 
             }
             v.r[row] = r;
             win[slot_of(sb, kme, R) * NXP + i] = r;
-            d.rho += r * r;
+            const TI rr = r * r;
+            if (g.acc64)
+                d.r64 += (double)rr;
+            else
+                d.rho += rr;
             if (m == 0) {  // block-Jacobi: u = r
                 v.u[row] = r;
-                d.gam += r * r;
+                if (g.acc64)
+                    d.g64 += (double)rr;
+                else
+                    d.gam += rr;
             }
         }
         __syncthreads();  // ring blocks and window 0 come from every wave
@@ -242,7 +267,10 @@ __device__ __forceinline__ Dots3<TI> scaled_pass(const Geo3 &g, bool init, bool 
                 const TI h = rk - cc * t;
                 hout[s * NXP + i] = h;
                 if (j == m) {
-                    d.gam += rk * h;
+                    if (g.acc64)
+                        d.g64 += (double)(rk * h);
+                    else
+                        d.gam += rk * h;
                     v.u[k * NX + i] = h;
                 }
             }
@@ -264,7 +292,10 @@ __device__ __forceinline__ Dots3<TI> scaled_pass(const Geo3 &g, bool init, bool 
                     const int sp = slot_of(sb, dk + 1, R);
                     w += lean_dot<NX, true>(ring + sp * BS, i, u + sp * NXP);
                 }
-                d.del += w * uk;
+                if (g.acc64)
+                    d.d64 += (double)(w * uk);
+                else
+                    d.del += w * uk;
                 v.w[k * NX + i] = w;
             }
         }
@@ -411,7 +442,7 @@ struct Outcome3 {
     double rnorm = 0.0;
 };
 
-template <typename TI, int BLOCK, int NX>
+template <typename TI, int BLOCK, int NX, bool ACC>
 __device__ __forceinline__ Outcome3 solve_scaled(const SolveArgs &a, const Prob3<TI> &q, unsigned char *smem_raw,
                                                  double *red64, TI *redT) {
     const int N = q.N, n = N * NX, tid = threadIdx.x;
@@ -419,6 +450,7 @@ __device__ __forceinline__ Outcome3 solve_scaled(const SolveArgs &a, const Prob3
     Geo3 g;
     g.N = N;
     g.m = a.poly;
+    g.acc64 = ACC;
     g.C = knots3<TI, BLOCK, NX>(a.lds_bytes, g.m);
     g.R = g.C + g.m + 2;
     const int Cres = residual3_knots<TI, NX>(a.lds_bytes);
@@ -489,9 +521,7 @@ __device__ __forceinline__ Outcome3 solve_scaled(const SolveArgs &a, const Prob3
         int it = 0, ist = kOk;
         Dots3<TI> dt = scaled_pass<TI, BLOCK, NX>(gc, true, false, TI(0), TI(0), cc, 1.0 / hn, q.rh64, q.OH, q.v,
                                                   (TI *)smem_raw);
-        block_sum2<BLOCK>(dt.gam, dt.del, redT);
-        dt.rho = block_sum<BLOCK>(dt.rho, redT + 2 * (BLOCK / kWave));
-        dt = Dots3<TI>{uniform(dt.gam), uniform(dt.del), uniform(dt.rho)};
+        dt = reduce_dots<TI, BLOCK>(dt, gc.acc64, red64, redT);
         const TI bnorm = sqrt(dt.rho);
         const TI tauT = (TI)tau;
         TI gam_prev = TI(0), alpha = TI(0), beta = TI(0);
@@ -522,9 +552,7 @@ __device__ __forceinline__ Outcome3 solve_scaled(const SolveArgs &a, const Prob3
             gam_prev = dt.gam;
             dt = scaled_pass<TI, BLOCK, NX>(gc, false, it == 0, alpha, beta, cc, 0.0, q.rh64, q.OH, q.v,
                                             (TI *)smem_raw);
-            block_sum2<BLOCK>(dt.gam, dt.del, redT);
-            dt.rho = block_sum<BLOCK>(dt.rho, redT + 2 * (BLOCK / kWave));
-            dt = Dots3<TI>{uniform(dt.gam), uniform(dt.del), uniform(dt.rho)};
+            dt = reduce_dots<TI, BLOCK>(dt, gc.acc64, red64, redT);
             ++it;
         }
         o.total += it;
@@ -544,7 +572,7 @@ __device__ __forceinline__ Outcome3 solve_scaled(const SolveArgs &a, const Prob3
     return o;
 }
 
-template <typename TI, int BLOCK, int NX>
+template <typename TI, int BLOCK, int NX, bool ACC>
 __device__ __forceinline__ void solve_one3(const SolveArgs &a, int p, Prob3<TI> &q, unsigned char *smem_raw,
                                            double *red64, TI *redT) {
     const int tid = threadIdx.x;
@@ -580,7 +608,7 @@ __device__ __forceinline__ void solve_one3(const SolveArgs &a, int p, Prob3<TI> 
     } else if (gg == 0.0) {
         for (int row = tid; row < n; row += BLOCK) q.lam[row] = 0.0;
     } else {
-        o = solve_scaled<TI, BLOCK, NX>(a, q, smem_raw, red64, redT);
+        o = solve_scaled<TI, BLOCK, NX, ACC>(a, q, smem_raw, red64, redT);
     }
     if (tid == 0) {
         a.iters[p] = o.total;
@@ -595,7 +623,7 @@ __device__ __forceinline__ void solve_one3(const SolveArgs &a, int p, Prob3<TI> 
 // the caller's workgroup barrier (no early return: a divergent-looking exit
 // next to the queue's single-thread fetch lets the compiler thread it back
 // to the loop head without that fetch).
-template <typename TI, int BLOCK, int NX>
+template <typename TI, int BLOCK, int NX, bool ACC>
 __device__ __forceinline__ void run_problem3(const SolveArgs &a, int p, int st_in, unsigned char *smem_raw,
                                              double *red64, TI *redT) {
     const int tid = threadIdx.x;
@@ -616,7 +644,7 @@ __device__ __forceinline__ void run_problem3(const SolveArgs &a, int p, int st_i
             a.relres[p] = NAN;
         }
     } else {
-        solve_one3<TI, BLOCK, NX>(a, p, q, smem_raw, red64, redT);
+        solve_one3<TI, BLOCK, NX, ACC>(a, p, q, smem_raw, red64, redT);
     }
 }
 
@@ -629,10 +657,11 @@ __device__ __forceinline__ void run_problem3(const SolveArgs &a, int p, int st_i
 // into scalar registers (readfirstlane), so every branch on them is uniform
 // for the compiler too: each workgroup barrier is then reached the same
 // number of times by every wave.
-template <typename TI, int BLOCK>
+// ACC: sum the inner products in FP64 (the option; FP32 storage only)
+template <typename TI, int BLOCK, bool ACC>
 __global__ __launch_bounds__(BLOCK, 3) void k_pcg3(SolveArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    __shared__ double red64[2 * (BLOCK / kWave)];
+    __shared__ double red64[3 * (BLOCK / kWave)];
     __shared__ TI redT[3 * (BLOCK / kWave)];
     __shared__ int s_next;
     if (threadIdx.x == 0) s_next = (int)atomicAdd(a.queue, 1u);
@@ -643,10 +672,10 @@ __global__ __launch_bounds__(BLOCK, 3) void k_pcg3(SolveArgs a) {
         const int nx = __builtin_amdgcn_readfirstlane(a.nx[p]);
         const int st_in = __builtin_amdgcn_readfirstlane(a.status[p]);
         switch (nx) {
-            case 6: run_problem3<TI, BLOCK, 6>(a, p, st_in, smem_raw, red64, redT); break;
-            case 14: run_problem3<TI, BLOCK, 14>(a, p, st_in, smem_raw, red64, redT); break;
-            case 26: run_problem3<TI, BLOCK, 26>(a, p, st_in, smem_raw, red64, redT); break;
-            case 36: run_problem3<TI, BLOCK, 36>(a, p, st_in, smem_raw, red64, redT); break;
+            case 6: run_problem3<TI, BLOCK, 6, ACC>(a, p, st_in, smem_raw, red64, redT); break;
+            case 14: run_problem3<TI, BLOCK, 14, ACC>(a, p, st_in, smem_raw, red64, redT); break;
+            case 26: run_problem3<TI, BLOCK, 26, ACC>(a, p, st_in, smem_raw, red64, redT); break;
+            case 36: run_problem3<TI, BLOCK, 36, ACC>(a, p, st_in, smem_raw, red64, redT); break;
             default:  // the host sends only compiled state sizes here
                 if (threadIdx.x == 0) {
                     a.status[p] = kNonFinite;
@@ -697,14 +726,15 @@ int lds3_rt(int nx, int threads, int m) {
     return 0;
 }
 
-template <typename TI, int BLOCK>
+template <typename TI, int BLOCK, bool ACC>
 const void *pcg3_fn() {
-    return (const void *)k_pcg3<TI, BLOCK>;
+    return (const void *)k_pcg3<TI, BLOCK, ACC>;
 }
 
-const void *pcg3_kernel(bool fp32, int threads) {
-    if (fp32) return threads == 128 ? pcg3_fn<float, 128>() : pcg3_fn<float, 256>();
-    return threads == 128 ? pcg3_fn<double, 128>() : pcg3_fn<double, 256>();
+const void *pcg3_kernel(bool fp32, int threads, bool acc) {
+    if (fp32 && acc) return threads == 128 ? pcg3_fn<float, 128, true>() : pcg3_fn<float, 256, true>();
+    if (fp32) return threads == 128 ? pcg3_fn<float, 128, false>() : pcg3_fn<float, 256, false>();
+    return threads == 128 ? pcg3_fn<double, 128, false>() : pcg3_fn<double, 256, false>();
 }
 
 hipError_t allow_lds(const void *f) {
@@ -741,11 +771,11 @@ int pcg3_lds(int nx, bool fp32, int threads, int m) {
     return l;
 }
 
-int pcg3_occupancy(bool fp32, int threads, int lds_bytes, int *cus) {
+int pcg3_occupancy(bool fp32, int threads, int lds_bytes, int *cus, bool acc) {
     int dev = 0, n = 0;
     if (cus) *cus = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
-    const void *f = pcg3_kernel(fp32, threads);
+    const void *f = pcg3_kernel(fp32, threads, acc);
     if (allow_lds(f) != hipSuccess) return 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, threads, (size_t)lds_bytes) != hipSuccess) return 0;
     if (cus) {
@@ -759,9 +789,10 @@ int pcg3_occupancy(bool fp32, int threads, int lds_bytes, int *cus) {
 hipError_t launch_pcg3(const SolveArgs &a, bool fp32, int threads, int grid, hipStream_t s) {
     if (a.nprob == 0) return hipSuccess;
     if (threads != 128 && threads != 256) return hipErrorInvalidValue;
-    const void *f = pcg3_kernel(fp32, threads);
-    static bool allowed[4] = {false, false, false, false};
-    const int key = (fp32 ? 2 : 0) + (threads == 256 ? 1 : 0);
+    const bool acc = fp32 && a.acc64 != 0;
+    const void *f = pcg3_kernel(fp32, threads, acc);
+    static bool allowed[8] = {false, false, false, false, false, false, false, false};
+    const int key = (acc ? 4 : 0) + (fp32 ? 2 : 0) + (threads == 256 ? 1 : 0);
     if (!allowed[key]) {
         hipError_t e = allow_lds(f);
         if (e != hipSuccess) return e;
@@ -778,7 +809,7 @@ hipError_t launch_pcg3(const SolveArgs &a, bool fp32, int threads, int grid, hip
             if (cache_key[c] == ckey) hit = c;
         if (hit < 0) {
             int cus = 0;
-            const int occ = pcg3_occupancy(fp32, threads, a.lds_bytes, &cus);
+            const int occ = pcg3_occupancy(fp32, threads, a.lds_bytes, &cus, acc);
             if (occ < 1 || cus < 1) return hipErrorInvalidConfiguration;
             static int next = 0;
             hit = next;
@@ -789,16 +820,21 @@ hipError_t launch_pcg3(const SolveArgs &a, bool fp32, int threads, int grid, hip
         grid = cache_grid[hit];
     }
     if (grid > a.nprob) grid = a.nprob;
-    if (fp32) {
+    if (fp32 && acc) {
         if (threads == 128)
-            hipLaunchKernelGGL((k_pcg3<float, 128>), dim3(grid), dim3(128), a.lds_bytes, s, a);
+            hipLaunchKernelGGL((k_pcg3<float, 128, true>), dim3(grid), dim3(128), a.lds_bytes, s, a);
         else
-            hipLaunchKernelGGL((k_pcg3<float, 256>), dim3(grid), dim3(256), a.lds_bytes, s, a);
+            hipLaunchKernelGGL((k_pcg3<float, 256, true>), dim3(grid), dim3(256), a.lds_bytes, s, a);
+    } else if (fp32) {
+        if (threads == 128)
+            hipLaunchKernelGGL((k_pcg3<float, 128, false>), dim3(grid), dim3(128), a.lds_bytes, s, a);
+        else
+            hipLaunchKernelGGL((k_pcg3<float, 256, false>), dim3(grid), dim3(256), a.lds_bytes, s, a);
     } else {
         if (threads == 128)
-            hipLaunchKernelGGL((k_pcg3<double, 128>), dim3(grid), dim3(128), a.lds_bytes, s, a);
+            hipLaunchKernelGGL((k_pcg3<double, 128, false>), dim3(grid), dim3(128), a.lds_bytes, s, a);
         else
-            hipLaunchKernelGGL((k_pcg3<double, 256>), dim3(grid), dim3(256), a.lds_bytes, s, a);
+            hipLaunchKernelGGL((k_pcg3<double, 256, false>), dim3(grid), dim3(256), a.lds_bytes, s, a);
     }
     return hipGetLastError();
 }

@@ -60,6 +60,7 @@ struct SolveArgs {
     int nprob;           // problems in the queue
     int poly;            // Horner steps m of the preconditioner polynomial in Oh (0: block-Jacobi)
     double pc_c;         // coefficient of each Horner step (1; 1/2 for the additive stair)
+    int acc64;           // scaled solve: sum the FP32 inner products in FP64
 };
 
 // Generic assembly (any nx <= 64), one 64-lane workgroup per knot of
@@ -149,6 +150,6 @@ int pcg3_steps_for(int nx, bool fp32, int threads, int lds_bytes, int m);
 // Knots per step of the scaled solve's FP64 residual for a budget (< 1: none).
 int pcg3_residual_steps(int nx, bool fp32, int lds_bytes);
 // Workgroups of k_pcg3 resident per CU with this LDS budget, and CUs.
-int pcg3_occupancy(bool fp32, int threads, int lds_bytes, int *cus);
+int pcg3_occupancy(bool fp32, int threads, int lds_bytes, int *cus, bool acc = false);
 
 }  // namespace ssp

@@ -110,6 +110,10 @@ class BatchSolver:
                                 C.byref(n)), "ssp_get_mapping")
         return [(int(nx[i]), int(th[i]), int(lds[i]), float(ms[i])) for i in range(k)]
 
+    def set_reduction_fp64(self, on: bool):
+        """Scaled solve under FP32 storage: sum the inner products in FP64."""
+        check(_lib.load().ssp_set_reduction_fp64(self._h, int(bool(on))), "ssp_set_reduction_fp64")
+
     def set_scaled_mapping(self, threads: int, lds_bytes: int = 0):
         check(_lib.load().ssp_set_scaled_mapping(self._h, int(threads), int(lds_bytes)), "ssp_set_scaled_mapping")
 

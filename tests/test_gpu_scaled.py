@@ -224,3 +224,36 @@ def test_scalar_jacobi_runs_the_classic_kernel_and_matches_oracle():
     assert np.abs(out["lam"] - ref["lam"]).max() <= 1e-7 * np.abs(ref["lam"]).max()
     out32 = run(b, "jacobi", "fp32_refine64", 1e-6)
     assert ((out32["status"] & ~16) == 0).all() and out32["relres"].max() <= 1e-6
+
+
+def test_fp64_accumulation_option_reports_both_errors():
+    """Inner products summed in FP32 (default) and in FP64 (the option): both
+    reach tol with errors within kappa_2(S) tol on ill-conditioned problems;
+    the option changes the iterates (it takes effect) and turning it off
+    again restores the default results bit for bit.  Prints both errors."""
+    from paper_2309_06427_amd import solver
+    b = inputs.make("batch1024_n128_nx26_cond1e6", P=16)
+    exact, kap = [], []
+    for i in range(b.P):
+        p = b.problem(i)
+        _, D, L, _, _ = oracle.build(p["A"], p["B"], p["Q"], p["R"], "sym")
+        exact.append(oracle.direct(D, L, p["gamma"])[1])
+        kap.append(dense.kappa(D, L))
+    res = {}
+    with solver.DeviceBatch(b) as db:
+        db.build("sym", "fp32_refine64")
+        for name, on in (("fp32_sums", False), ("fp64_sums", True), ("fp32_again", False)):
+            db.solver.set_reduction_fp64(on)
+            db.solve(1e-6)
+            out = db.results()
+            assert db.solver.solve_kernel()[0] == 4
+            err = np.array([np.linalg.norm(seg(b, out["lam"], i) - exact[i]) / np.linalg.norm(exact[i])
+                            for i in range(b.P)])
+            res[name] = (out, err)
+            print(f"{name}: iters {out['iters'].mean():.2f} outer {out['outer'].mean():.2f} "
+                  f"max relres {out['relres'].max():.2e} median err {np.median(err):.2e} max err {err.max():.2e}")
+            assert ((out["status"] & ~16) == 0).all() and out["relres"].max() <= 1e-6
+            assert np.all(err <= np.array(kap) * 1e-6)
+    assert not np.array_equal(res["fp32_sums"][0]["lam"], res["fp64_sums"][0]["lam"])
+    for k in ("lam", "iters", "relres", "status"):
+        assert np.array_equal(res["fp32_sums"][0][k], res["fp32_again"][0][k])
