@@ -27,11 +27,12 @@ HBM_PEAK_GBS = 8000.0
 # WRITE_SIZE (KiB per dispatch), each scaled by what the counter reads for a
 # plain copy of known size (2.0 and 1.0), keyed by the workload/settings and by
 # a hash of the kernel's sources: a changed kernel reports null.
-SOLVE_SOURCES = ("pcg2.hip", "ssp_device.h", "ssp_sweep.h", "ssp_host.h", "host.hip")
+SOLVE_SOURCES = ("pcg3.hip", "ssp_fused.h", "ssp_device.h", "ssp_host.h")  # the scaled solve's device code
 MEASURED_TRAFFIC = {
-    # (workload, pc, precision, kernel): (sources sha256[:16], bytes of one solve, all its dispatches)
+    # (workload, pc, precision, kernel): (sources sha256[:16], HBM bytes of one solve): rocprofv3 FETCH_SIZE x 2.0
+    # + WRITE_SIZE x 1.0 (KiB, the factors a plain 1 GiB copy reads), k_pcg3 at 256 threads / 48 336 B
     ("batch4096_ragged", "sym", "fp32_refine64", 0):
-        ("4271748e2a8a1ed3", (21505446.3125 * 2.0 + 5561210.09375 * 1.0) * 1024),
+        ("d23c06ca6bfbce3d", (13761502.75 * 2.0 + 5545838.75 * 1.0) * 1024),
 }
 
 
