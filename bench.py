@@ -27,7 +27,8 @@ HBM_PEAK_GBS = 8000.0
 # WRITE_SIZE (KiB per dispatch), each scaled by what the counter reads for a
 # plain copy of known size (2.0 and 1.0), keyed by the workload/settings and by
 # a hash of the kernel's sources: a changed kernel reports null.
-SOLVE_SOURCES = ("pcg3.hip", "ssp_fused.h", "ssp_device.h", "ssp_host.h")  # the scaled solve's device code
+# the scaled solve's device code and the host code that sets its launch and stopping parameters
+SOLVE_SOURCES = ("pcg3.hip", "ssp_fused.h", "ssp_device.h", "ssp_host.h", "host.hip")
 MEASURED_TRAFFIC = {
     # (workload, pc, precision, kernel): (sources sha256[:16], HBM bytes of one solve): rocprofv3 FETCH_SIZE x 2.0
     # + WRITE_SIZE x 1.0 (KiB, the factors a plain 1 GiB copy reads), k_pcg3 at 256 threads / 48 336 B

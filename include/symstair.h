@@ -167,7 +167,8 @@ ssp_status ssp_build_from_blocks(ssp_batch *b, ssp_precon pc, ssp_precision prec
  *             earlier solve's status, is ignored), out = solve status.
  *   max_iter: cap on the inner iterations per problem (<= 0: 10 * N * nx).
  * FP32_REFINE64 runs at most 5 refinement steps; the inner relative
- * tolerance of step j is clamp(0.5 * rel_tol * ||gamma|| / ||r_j||, 1e-6, 1).
+ * tolerance of step j is clamp(0.5 * rel_tol * ||gamma|| / ||r_j||, t, 1) with
+ * t = 1e-6, and t = min(1e-6, rel_tol / 2) in the scaled solve (kernel 4).
  * There a float breakdown only ends the inner solve; under a stair
  * preconditioner it also replaces it by block-Jacobi for the rest of the
  * solve (SSP_P_PC_FALLBACK, with a fresh budget of 5 refinement steps), and

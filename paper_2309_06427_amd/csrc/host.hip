@@ -289,7 +289,10 @@ ssp_status launch_scaled(ssp_batch *b, ssp::SolveArgs a, hipStream_t s) {
     a.refine = b->prec == SSP_FP32 ? 0 : 1;
     a.max_outer = a.refine ? 5 : 1;
     a.theta = 0.5;
-    a.tau_min = b->prec == SSP_FP64 ? 1e-15 : 1e-6;
+    // the float operator I + Oh is as well conditioned as block-Jacobi
+    // preconditioned S, so the first inner solve may aim at theta tol itself
+    // (no floor above it): one outer step then suffices for most problems
+    a.tau_min = b->prec == SSP_FP64 ? 1e-15 : std::min(1e-6, a.theta * a.tol);
     SSP_HIP(ssp::launch_fill_i32((int32_t *)a.queue, 0, 1, s));
     SSP_HIP(ssp::launch_pcg3(a, b->fp32, t, 0, s));
     b->last_kernel = 4;

@@ -68,7 +68,8 @@ def test_whole_batch_converges_in_the_bench_configuration(full):
 def test_sampled_problems_match_the_oracle(full):
     b, out, _, _ = full
     ids = sample(b)
-    ref = oracle.solve_batch(inputs.pack([b.problem(i) for i in ids]), "sym", "fp32_refine64", tol=TOL)
+    ref = oracle.solve_batch(inputs.pack([b.problem(i) for i in ids]), "sym", "fp32_refine64", tol=TOL,
+                             tau_min=min(1e-6, 0.5 * TOL))
     for j, i in enumerate(ids):
         p = b.problem(i)
         lam = out["lam"][b.off_v[i]:b.off_v[i + 1]]

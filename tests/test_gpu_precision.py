@@ -80,7 +80,7 @@ def test_fallbacks_on_the_ill_conditioned_batch():
         db.solve(1e-6)
         out = db.results()
         kern = db.solver.solve_kernel()[0]
-    ref = oracle.solve_batch(b, "sym", "fp32_refine64", tol=1e-6)
+    ref = oracle.solve_batch(b, "sym", "fp32_refine64", tol=1e-6, tau_min=5e-7)
     gpu_fb, ref_fb = int(((out["status"] & 16) != 0).sum()), int(((ref["status"] & 16) != 0).sum())
     print(f"kernel {kern}: block-Jacobi fallbacks GPU {gpu_fb} / oracle {ref_fb} of {b.P}; "
           f"iterations GPU {out['iters'].mean():.1f} oracle {ref['iters'].mean():.1f}")

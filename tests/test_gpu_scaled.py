@@ -30,6 +30,12 @@ def _need_gpu():
         pytest.skip("no GPU")
 
 
+def scaled_tau(tol):
+    """The scaled solve's floor on the inner tolerance under refinement: the
+    first inner solve aims at theta tol (theta = 1/2), never above 1e-6."""
+    return min(1e-6, 0.5 * tol)
+
+
 def seg(b, v, i):
     return v[b.off_v[i]:b.off_v[i + 1]]
 
@@ -67,7 +73,7 @@ def test_scaled_solve_matches_oracle(pc, prec, tol):
     out = run(b, pc, prec, tol, kernel=4)
     assert out["kernel"] == 4
     assert ((out["status"] & ~16) == 0).all(), out["status"]
-    ref = oracle.solve_batch(b, pc, prec, tol=tol)
+    ref = oracle.solve_batch(b, pc, prec, tol=tol, tau_min=scaled_tau(tol))
     assert ((ref["status"] & ~16) == 0).all()
     for i in range(b.P):
         p = b.problem(i)
@@ -183,7 +189,7 @@ def test_scaled_statuses_and_warm_start():
     rng = np.random.default_rng(3)
     lam0 = 1e3 * rng.standard_normal(b.gamma.shape[0])
     lam0[:b.off_v[1]] = 0.0
-    ref = oracle.solve_batch(b, "sym", "fp32_refine64", 1e-6, lam0=lam0, fallback=True)
+    ref = oracle.solve_batch(b, "sym", "fp32_refine64", 1e-6, lam0=lam0, fallback=True, tau_min=scaled_tau(1e-6))
     with solver.DeviceBatch(b) as db:
         db.build("sym", "fp32_refine64")
         db.solve(1e-6, lam0=torch.from_numpy(lam0).cuda(), fallback=True)
