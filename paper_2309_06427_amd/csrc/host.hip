@@ -293,8 +293,31 @@ ssp_status launch_scaled(ssp_batch *b, ssp::SolveArgs a, hipStream_t s) {
     // preconditioned S, so the first inner solve may aim at theta tol itself
     // (no floor above it): one outer step then suffices for most problems
     a.tau_min = b->prec == SSP_FP64 ? 1e-15 : std::min(1e-6, a.theta * a.tol);
-    SSP_HIP(ssp::launch_fill_i32((int32_t *)a.queue, 0, 1, s));
-    SSP_HIP(ssp::launch_pcg3(a, b->fp32, t, 0, s));
+    // one persistent grid per state size (largest total work first), each
+    // with its own queue counter, on internal streams forked from and joined
+    // back into s: a grid whose queue is empty retires and the next size's
+    // workgroups take its place
+    const int ng = (int)b->groups.size();
+    SSP_HIP(ssp::launch_fill_i32((int32_t *)a.queue, 0, ng, s));
+    const bool fork = ng > 1;
+    if (fork) {
+        SSP_HIP(hipEventRecord(b->gevents[ng], s));
+        for (int i = 0; i < ng; ++i) SSP_HIP(hipStreamWaitEvent(b->gstreams[i], b->gevents[ng], 0));
+    }
+    for (int i = 0; i < ng; ++i) {
+        const auto &g = b->groups[i];
+        ssp::SolveArgs ga = a;
+        ga.order = b->dgorder + g.offset;
+        ga.nprob = g.count;
+        ga.queue = a.queue + i;
+        SSP_HIP(ssp::launch_pcg3(ga, b->fp32, t, g.nx, 0, fork ? b->gstreams[i] : s));
+    }
+    if (fork) {
+        for (int i = 0; i < ng; ++i) {
+            SSP_HIP(hipEventRecord(b->gevents[i], b->gstreams[i]));
+            SSP_HIP(hipStreamWaitEvent(s, b->gevents[i], 0));
+        }
+    }
     b->last_kernel = 4;
     return SSP_OK;
 }
@@ -611,7 +634,7 @@ ssp_status ssp_batch_create(int32_t nprob, const int32_t *N, const int32_t *nx, 
         const size_t nn = b->off_nn[nprob], uu = b->off_uu[nprob], nv = b->off_v[nprob];
         if (dalloc(&b->Qinv, nn) != hipSuccess || dalloc(&b->Rinv, uu) != hipSuccess ||
             dalloc(&b->r64, nv) != hipSuccess || dalloc(&b->douter, (size_t)nprob) != hipSuccess ||
-            dalloc(&b->dqueue, 1) != hipSuccess)
+            dalloc(&b->dqueue, std::max<size_t>(b->groups.size(), 1)) != hipSuccess)
             rc = SSP_ERR_ALLOC;
     }
     if (rc != SSP_OK) {
@@ -1073,7 +1096,7 @@ ssp_status ssp_get_scaled_mapping(const ssp_batch *b, int32_t *threads, int32_t 
     if (grid) {
         DevGuard g(b->device);
         int cus = 0;
-        const int occ = ssp::pcg3_occupancy(b->fp32, t, l, &cus, b->fp32 && b->acc64);
+        const int occ = ssp::pcg3_occupancy(b->fp32, t, l, &cus, b->fp32 && b->acc64, b->groups[0].nx);
         *grid = std::min(occ * cus, b->P);
     }
     return SSP_OK;

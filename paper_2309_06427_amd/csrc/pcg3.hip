@@ -657,8 +657,11 @@ __device__ __forceinline__ void run_problem3(const SolveArgs &a, int p, int st_i
 // into scalar registers (readfirstlane), so every branch on them is uniform
 // for the compiler too: each workgroup barrier is then reached the same
 // number of times by every wave.
-// ACC: sum the inner products in FP64 (the option; FP32 storage only)
-template <typename TI, int BLOCK, bool ACC>
+// One persistent grid for the problems of one compiled state size NX (a
+// kernel instance per size keeps each size's register allocation to
+// itself).  ACC: sum the inner products in FP64 (the option; FP32 storage
+// only).
+template <typename TI, int BLOCK, int NX, bool ACC>
 __global__ __launch_bounds__(BLOCK, 3) void k_pcg3(SolveArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ double red64[3 * (BLOCK / kWave)];
@@ -671,19 +674,13 @@ __global__ __launch_bounds__(BLOCK, 3) void k_pcg3(SolveArgs a) {
         const int p = __builtin_amdgcn_readfirstlane(a.order[qi]);
         const int nx = __builtin_amdgcn_readfirstlane(a.nx[p]);
         const int st_in = __builtin_amdgcn_readfirstlane(a.status[p]);
-        switch (nx) {
-            case 6: run_problem3<TI, BLOCK, 6, ACC>(a, p, st_in, smem_raw, red64, redT); break;
-            case 14: run_problem3<TI, BLOCK, 14, ACC>(a, p, st_in, smem_raw, red64, redT); break;
-            case 26: run_problem3<TI, BLOCK, 26, ACC>(a, p, st_in, smem_raw, red64, redT); break;
-            case 36: run_problem3<TI, BLOCK, 36, ACC>(a, p, st_in, smem_raw, red64, redT); break;
-            default:  // the host sends only compiled state sizes here
-                if (threadIdx.x == 0) {
-                    a.status[p] = kNonFinite;
-                    a.relres[p] = NAN;
-                    a.iters[p] = 0;
-                    a.outer[p] = 0;
-                }
-                break;
+        if (nx == NX) {
+            run_problem3<TI, BLOCK, NX, ACC>(a, p, st_in, smem_raw, red64, redT);
+        } else if (threadIdx.x == 0) {  // the host queues only problems of this size
+            a.status[p] = kNonFinite;
+            a.relres[p] = NAN;
+            a.iters[p] = 0;
+            a.outer[p] = 0;
         }
         __syncthreads();  // the problem is done: s_next, the LDS and the reduction scratch are free
         if (threadIdx.x == 0) s_next = (int)atomicAdd(a.queue, 1u);
@@ -727,14 +724,20 @@ int lds3_rt(int nx, int threads, int m) {
 }
 
 template <typename TI, int BLOCK, bool ACC>
-const void *pcg3_fn() {
-    return (const void *)k_pcg3<TI, BLOCK, ACC>;
+const void *pcg3_fn(int nx) {
+    switch (nx) {
+        case 6: return (const void *)k_pcg3<TI, BLOCK, 6, ACC>;
+        case 14: return (const void *)k_pcg3<TI, BLOCK, 14, ACC>;
+        case 26: return (const void *)k_pcg3<TI, BLOCK, 26, ACC>;
+        case 36: return (const void *)k_pcg3<TI, BLOCK, 36, ACC>;
+    }
+    return nullptr;
 }
 
-const void *pcg3_kernel(bool fp32, int threads, bool acc) {
-    if (fp32 && acc) return threads == 128 ? pcg3_fn<float, 128, true>() : pcg3_fn<float, 256, true>();
-    if (fp32) return threads == 128 ? pcg3_fn<float, 128, false>() : pcg3_fn<float, 256, false>();
-    return threads == 128 ? pcg3_fn<double, 128, false>() : pcg3_fn<double, 256, false>();
+const void *pcg3_kernel(bool fp32, int threads, bool acc, int nx) {
+    if (fp32 && acc) return threads == 128 ? pcg3_fn<float, 128, true>(nx) : pcg3_fn<float, 256, true>(nx);
+    if (fp32) return threads == 128 ? pcg3_fn<float, 128, false>(nx) : pcg3_fn<float, 256, false>(nx);
+    return threads == 128 ? pcg3_fn<double, 128, false>(nx) : pcg3_fn<double, 256, false>(nx);
 }
 
 hipError_t allow_lds(const void *f) {
@@ -771,11 +774,12 @@ int pcg3_lds(int nx, bool fp32, int threads, int m) {
     return l;
 }
 
-int pcg3_occupancy(bool fp32, int threads, int lds_bytes, int *cus, bool acc) {
+int pcg3_occupancy(bool fp32, int threads, int lds_bytes, int *cus, bool acc, int nx) {
     int dev = 0, n = 0;
     if (cus) *cus = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
-    const void *f = pcg3_kernel(fp32, threads, acc);
+    const void *f = pcg3_kernel(fp32, threads, acc, nx);
+    if (!f) return 0;
     if (allow_lds(f) != hipSuccess) return 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, threads, (size_t)lds_bytes) != hipSuccess) return 0;
     if (cus) {
@@ -786,57 +790,39 @@ int pcg3_occupancy(bool fp32, int threads, int lds_bytes, int *cus, bool acc) {
     return n;
 }
 
-hipError_t launch_pcg3(const SolveArgs &a, bool fp32, int threads, int grid, hipStream_t s) {
+hipError_t launch_pcg3(const SolveArgs &a, bool fp32, int threads, int nx, int grid, hipStream_t s) {
     if (a.nprob == 0) return hipSuccess;
     if (threads != 128 && threads != 256) return hipErrorInvalidValue;
     const bool acc = fp32 && a.acc64 != 0;
-    const void *f = pcg3_kernel(fp32, threads, acc);
-    static bool allowed[8] = {false, false, false, false, false, false, false, false};
-    const int key = (acc ? 4 : 0) + (fp32 ? 2 : 0) + (threads == 256 ? 1 : 0);
-    if (!allowed[key]) {
+    const void *f = pcg3_kernel(fp32, threads, acc, nx);
+    if (!f) return hipErrorInvalidValue;
+    // per kernel instance: the LDS opt-in once, and the resident workgroups
+    // for an LDS budget queried once per process (no runtime query inside a
+    // graph capture after the first eager solve)
+    struct Entry {
+        const void *f;
+        int lds, grid;
+    };
+    static Entry cache[64];
+    static int used = 0, next = 0;
+    int hit = -1;
+    for (int c = 0; c < used; ++c)
+        if (cache[c].f == f && cache[c].lds == a.lds_bytes) hit = c;
+    if (hit < 0) {
         hipError_t e = allow_lds(f);
         if (e != hipSuccess) return e;
-        allowed[key] = true;
+        int cus = 0;
+        const int occ = pcg3_occupancy(fp32, threads, a.lds_bytes, &cus, acc, nx);
+        if (occ < 1 || cus < 1) return hipErrorInvalidConfiguration;
+        hit = used < 64 ? used++ : (next++ % 64);
+        cache[hit] = Entry{f, a.lds_bytes, occ * cus};
     }
-    if (grid <= 0) {
-        // resident workgroups for this (precision, threads, LDS budget),
-        // queried once per process: no runtime query inside a graph capture
-        // after the first eager solve
-        static int cache_key[8] = {0, 0, 0, 0, 0, 0, 0, 0}, cache_grid[8];
-        const int ckey = (a.lds_bytes << 2) | key | (1 << 30);
-        int hit = -1;
-        for (int c = 0; c < 8; ++c)
-            if (cache_key[c] == ckey) hit = c;
-        if (hit < 0) {
-            int cus = 0;
-            const int occ = pcg3_occupancy(fp32, threads, a.lds_bytes, &cus, acc);
-            if (occ < 1 || cus < 1) return hipErrorInvalidConfiguration;
-            static int next = 0;
-            hit = next;
-            next = (next + 1) % 8;
-            cache_key[hit] = ckey;
-            cache_grid[hit] = occ * cus;
-        }
-        grid = cache_grid[hit];
-    }
+    if (grid <= 0) grid = cache[hit].grid;
     if (grid > a.nprob) grid = a.nprob;
-    if (fp32 && acc) {
-        if (threads == 128)
-            hipLaunchKernelGGL((k_pcg3<float, 128, true>), dim3(grid), dim3(128), a.lds_bytes, s, a);
-        else
-            hipLaunchKernelGGL((k_pcg3<float, 256, true>), dim3(grid), dim3(256), a.lds_bytes, s, a);
-    } else if (fp32) {
-        if (threads == 128)
-            hipLaunchKernelGGL((k_pcg3<float, 128, false>), dim3(grid), dim3(128), a.lds_bytes, s, a);
-        else
-            hipLaunchKernelGGL((k_pcg3<float, 256, false>), dim3(grid), dim3(256), a.lds_bytes, s, a);
-    } else {
-        if (threads == 128)
-            hipLaunchKernelGGL((k_pcg3<double, 128, false>), dim3(grid), dim3(128), a.lds_bytes, s, a);
-        else
-            hipLaunchKernelGGL((k_pcg3<double, 256, false>), dim3(grid), dim3(256), a.lds_bytes, s, a);
-    }
-    return hipGetLastError();
+    SolveArgs arg = a;
+    void *args[] = {(void *)&arg};
+    hipError_t e = hipLaunchKernel(f, dim3(grid), dim3(threads), args, (size_t)a.lds_bytes, s);
+    return e != hipSuccess ? e : hipGetLastError();
 }
 
 }  // namespace ssp

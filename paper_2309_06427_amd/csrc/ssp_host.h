@@ -138,10 +138,11 @@ int pcg2_steps_for(int nx, bool fp32, int threads, int lds_bytes);
 // Workgroup sizes the fused kernel is compiled for (128, 256).
 bool pcg2_threads_ok(int threads);
 
-// Scaled solve: one persistent grid over every problem (state sizes
-// kBuildSizes only), problems taken from a device queue in `order`.
-// `grid`: workgroups to launch (<= 0: as many as fit on the device at once).
-hipError_t launch_pcg3(const SolveArgs &a, bool fp32, int threads, int grid, hipStream_t s);
+// Scaled solve of the problems order[0 .. nprob) (all of state size nx, one
+// of kBuildSizes): one persistent grid of the kernel instance compiled for
+// nx, problems taken from the device queue counter a.queue.  `grid`:
+// workgroups to launch (<= 0: as many as fit on the device at once).
+hipError_t launch_pcg3(const SolveArgs &a, bool fp32, int threads, int nx, int grid, hipStream_t s);
 // LDS bytes for the largest pipeline step of state size nx at `threads`
 // with m Horner steps (0 if it cannot run), and the knots per step a budget
 // gives (< 1: cannot run).
@@ -149,7 +150,8 @@ int pcg3_lds(int nx, bool fp32, int threads, int m);
 int pcg3_steps_for(int nx, bool fp32, int threads, int lds_bytes, int m);
 // Knots per step of the scaled solve's FP64 residual for a budget (< 1: none).
 int pcg3_residual_steps(int nx, bool fp32, int lds_bytes);
-// Workgroups of k_pcg3 resident per CU with this LDS budget, and CUs.
-int pcg3_occupancy(bool fp32, int threads, int lds_bytes, int *cus, bool acc = false);
+// Workgroups of k_pcg3 for state size nx resident per CU with this LDS
+// budget, and CUs.
+int pcg3_occupancy(bool fp32, int threads, int lds_bytes, int *cus, bool acc, int nx);
 
 }  // namespace ssp

@@ -4,6 +4,8 @@ stream, every computation runs in the HIP library.
 from __future__ import annotations
 
 import ctypes as C
+import json
+import os
 import sys
 
 import numpy as np
@@ -184,6 +186,7 @@ class DeviceBatch:
 
     def build(self, pc: str = "sym", precision: str = "fp32_refine64", stream=None):
         self.solver.build(pc, precision, self.A, self.B, self.Q, self.R, self.status, stream)
+        self._built = (pc, precision)
 
     def solve(self, tol: float = 1e-6, max_iter: int = 0, lam0=None, fallback: bool = False,
               warm_in_place: bool = False, stream=None, noalloc: bool = False):
@@ -212,11 +215,70 @@ class DeviceBatch:
         self.solver.kkt_recover(self.A, self.B, q, r, self.lam, dx, du, stream)
         return dx, du
 
-    def autotune(self, tol: float = 1e-6, stream=None) -> list:
-        """Pick the fused kernel's mapping per state size on this batch (after a build)."""
+    def autotune(self, tol: float = 1e-6, stream=None, cache: str | None = None) -> list:
+        """Pick the solve's mapping on this batch (after a build): the scaled
+        solve's threads and LDS budget, or the fused kernel's per state size.
+        With ``cache`` (a JSON file path), a batch with the same device,
+        precision, preconditioner, state sizes and size buckets reuses the
+        mapping stored there instead of timing candidates, and a new choice is
+        stored.  Leaves a solve's results in the outputs either way."""
+        key = self.tune_key() if cache else None
+        if key is not None and self._apply_cached(cache, key):
+            self.solve(tol, stream=stream)
+            return self.solver.mapping()
         self.solver.autotune(tol, self.gamma, self.lam, self.iters, self.relres, self.status, stream)
         self.solver.solve_outer(self.outer, stream)
+        if key is not None:
+            self._store_cached(cache, key)
         return self.solver.mapping()
+
+    def tune_key(self) -> str:
+        """Cache key of the autotuner's choice: device architecture, precision,
+        preconditioner, the set of state sizes, and the batch's problem count
+        and longest horizon rounded up to powers of two."""
+        import torch
+        pc, prec = getattr(self, "_built", ("?", "?"))
+        arch = getattr(torch.cuda.get_device_properties(self.gamma.device), "gcnArchName", "gpu")
+        pow2 = lambda n: 1 << max(int(n) - 1, 0).bit_length()
+        nxs = ",".join(str(int(v)) for v in np.unique(self.batch.nx))
+        return f"{arch}|{prec}|{pc}|nx={nxs}|P<={pow2(self.batch.P)}|N<={pow2(int(np.max(self.batch.N)))}"
+
+    def _apply_cached(self, path: str, key: str) -> bool:
+        try:
+            with open(path) as f:
+                entry = json.load(f).get(key)
+        except (OSError, ValueError):
+            return False
+        if not entry:
+            return False
+        try:
+            if entry["kind"] == "scaled":
+                self.solver.set_scaled_mapping(entry["threads"], entry["lds"])
+            else:
+                for nx, t, l in entry["groups"]:
+                    self.solver.set_group_mapping(nx, t, l)
+        except RuntimeError:
+            return False  # not usable for this batch: tune again
+        return True
+
+    def _store_cached(self, path: str, key: str) -> None:
+        kern = self.solver.solve_kernel()[0]
+        if kern == 4:
+            t, l = self.solver.scaled_mapping()[:2]
+            entry = {"kind": "scaled", "threads": t, "lds": l}
+        else:
+            entry = {"kind": "groups", "groups": [[nx, t, l] for nx, t, l, _ in self.solver.mapping()]}
+        try:
+            with open(path) as f:
+                data = json.load(f)
+        except (OSError, ValueError):
+            data = {}
+        data[key] = entry
+        os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
+        tmp = f"{path}.{os.getpid()}.tmp"
+        with open(tmp, "w") as f:
+            json.dump(data, f, indent=1, sort_keys=True)
+        os.replace(tmp, path)
 
     def results(self) -> dict:
         import torch

@@ -263,3 +263,30 @@ def test_fp64_accumulation_option_reports_both_errors():
     assert not np.array_equal(res["fp32_sums"][0]["lam"], res["fp64_sums"][0]["lam"])
     for k in ("lam", "iters", "relres", "status"):
         assert np.array_equal(res["fp32_sums"][0][k], res["fp32_again"][0][k])
+
+
+def test_autotune_cache_reuses_the_choice(tmp_path):
+    """The first autotune times candidates and stores its choice under the
+    batch's key; a second batch of the same kind (new handle, same state
+    sizes and size buckets) takes the stored mapping without timing, and its
+    solve is valid."""
+    import json
+    from paper_2309_06427_amd import solver
+    path = str(tmp_path / "tune.json")
+    b1 = inputs.batch(40, seed=81, N_range=(20, 100), nx_choices=(6, 14, 26))
+    b2 = inputs.batch(40, seed=82, N_range=(20, 100), nx_choices=(6, 14, 26))
+    with solver.DeviceBatch(b1) as d1, solver.DeviceBatch(b2) as d2:
+        d1.build("sym", "fp32_refine64")
+        d1.autotune(1e-6, cache=path)
+        t1, l1, _, ms1 = d1.solver.scaled_mapping()
+        assert ms1 > 0  # timed here
+        data = json.load(open(path))
+        assert list(data) == [d1.tune_key()] and data[d1.tune_key()] == {"kind": "scaled", "threads": t1, "lds": l1}
+        d2.build("sym", "fp32_refine64")
+        assert d2.tune_key() == d1.tune_key()
+        d2.autotune(1e-6, cache=path)
+        t2, l2, _, ms2 = d2.solver.scaled_mapping()
+        assert (t2, l2) == (t1, l1) and ms2 == 0.0  # taken from the cache, not timed
+        out = d2.results()
+        assert ((out["status"] & ~16) == 0).all() and out["relres"].max() <= 1e-6
+        assert json.load(open(path)) == data
