@@ -146,19 +146,19 @@ struct Prefetch3 {
         }
     }
 
-    // chunk -> ring slots sb, sb + 1, ... (mod R); surplus lanes of the
-    // partial slot write the 16-byte spot `dummy`
+    // chunk -> ring slots sb, sb + 1, ... (mod R); surplus vectors (a
+    // partial slot, or whole slots of a short step) go to the 16-byte spot
+    // `dummy`.  Every register is stored on every path, so the next issue
+    // finds no load still pending on them and need not wait for memory.
     __device__ __forceinline__ void store(TM *ring, int kc, int sb, int R, TM *dummy) const {
         const int nvec = kc * BS / V;
         const int wrap = R * BS, base = sb * BS;
         static_for<0, kPF>([&](auto mc) {
             constexpr int m = decltype(mc)::value;
-            if (m * BLOCK < nvec) {
-                const int q = threadIdx.x + m * BLOCK;
-                int off = base + q * V;
-                if (off >= wrap) off -= wrap;
-                *(VT *)(q < nvec ? ring + off : dummy) = reg[m];
-            }
+            const int q = threadIdx.x + m * BLOCK;
+            int off = base + q * V;
+            if (off >= wrap) off -= wrap;
+            *(VT *)(q < nvec ? ring + off : dummy) = reg[m];
         });
     }
 };
