@@ -31,9 +31,11 @@ HBM_PEAK_GBS = 8000.0
 SOLVE_SOURCES = ("pcg3.hip", "ssp_fused.h", "ssp_device.h", "ssp_host.h", "host.hip")
 MEASURED_TRAFFIC = {
     # (workload, pc, precision, kernel): (sources sha256[:16], HBM bytes of one solve): rocprofv3 FETCH_SIZE x 2.0
-    # + WRITE_SIZE x 1.0 (KiB, the factors a plain 1 GiB copy reads), k_pcg3 at 256 threads / 48 336 B
+    # + WRITE_SIZE x 1.0 (KiB, the factors a plain 1 GiB copy reads), summed over the three k_pcg3 instances (nx 6,
+    # 14, 26) of one solve at 256 threads / 48 336 B
     ("batch4096_ragged", "sym", "fp32_refine64", 0):
-        ("d23c06ca6bfbce3d", (13761502.75 * 2.0 + 5545838.75 * 1.0) * 1024),
+        ("dc4d4fa0befd4c2a", ((8419609.06 + 2956410.12 + 574623.0) * 2.0
+                              + (2916238.34 + 1658391.94 + 709916.97) * 1.0) * 1024),
 }
 
 
@@ -474,7 +476,9 @@ def main() -> int:
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
             **({"note": "latency-bound: blocks stay in LDS, one grid-wide sum per PCG iteration"}
-               if kern == 3 else {}),
+               if kern == 3 else
+               {"note": "one persistent instance per state size, run concurrently; achieved and traffic cover "
+                        "all of them over the solve phase"} if kern == 4 else {}),
         },
         "cpu_baseline": cpu,
     }

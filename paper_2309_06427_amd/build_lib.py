@@ -14,7 +14,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(PKG, "csrc")
 OBJ = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libsymstair.so")
-SOURCES = ["build.hip", "build2.hip", "pcg.hip", "pcg2.hip", "pcg3.hip", "coop.hip", "kkt.hip", "noalloc.hip", "mlp.hip", "host.hip", "mlp_host.hip",
+SOURCES = ["build.hip", "build2.hip", "build3.hip", "pcg.hip", "pcg2.hip", "pcg3.hip", "coop.hip", "kkt.hip", "noalloc.hip", "mlp.hip", "host.hip", "mlp_host.hip",
            "util.hip"]
 ARCH = os.environ.get("SSP_OFFLOAD_ARCH", "gfx950")
 

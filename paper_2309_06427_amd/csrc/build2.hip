@@ -546,13 +546,28 @@ hipError_t launch_build_ohat(int cls, const BuildArgs &a, const int2 *items, int
         case 1: return launch_ohat_nx<14>(a, items, nitems, fp32, s);
         case 2: return launch_ohat_nx<26>(a, items, nitems, fp32, s);
         case 3: return launch_ohat_nx<36>(a, items, nitems, fp32, s);
+        case 4: return launch_dpp_ohat<6>(a, items, nitems, fp32, s);
+        case 5: return launch_dpp_ohat<14>(a, items, nitems, fp32, s);
+        case 6: return launch_dpp_ohat<26>(a, items, nitems, fp32, s);
     }
     return hipErrorInvalidValue;
 }
 
-const int kBuildSizes[kBuildClasses] = {6, 14, 26, 36};
+// classes 0-3: the LDS kernels above (any nu <= nx); 4-6: the DPP-broadcast
+// kernels, for nu = nx / 2.  At nx = 6 a knot fills 6 lanes of a 16-lane DPP
+// row, and the LDS kernels (ten knots per wave) are faster, so class 4 is
+// compiled but not chosen.
+const int kBuildSizes[kBuildClasses] = {6, 14, 26, 36, 6, 14, 26};
 
-int build_knots_per_item(int nx) { return (kThreads / 64) * (64 / nx); }
+int build_class_of(int nx, int nu) {
+    for (int c = 5; c < kBuildClasses; ++c)
+        if (nx == kBuildSizes[c] && 2 * nu == nx) return c;
+    for (int c = 0; c < 4; ++c)
+        if (nx == kBuildSizes[c] && nu <= nx) return c;
+    return -1;
+}
+
+int build_knots_per_item(int cls) { return cls >= 4 ? dpp_knots_per_item() : (kThreads / 64) * (64 / kBuildSizes[cls]); }
 
 hipError_t launch_build_class(int cls, const BuildArgs &a, const int2 *items, int nitems, bool fp32, hipStream_t s) {
     switch (cls) {
@@ -560,6 +575,9 @@ hipError_t launch_build_class(int cls, const BuildArgs &a, const int2 *items, in
         case 1: return launch_nx<14>(a, items, nitems, fp32, s);
         case 2: return launch_nx<26>(a, items, nitems, fp32, s);
         case 3: return launch_nx<36>(a, items, nitems, fp32, s);
+        case 4: return launch_dpp_class<6>(a, items, nitems, fp32, s);
+        case 5: return launch_dpp_class<14>(a, items, nitems, fp32, s);
+        case 6: return launch_dpp_class<26>(a, items, nitems, fp32, s);
     }
     return hipErrorInvalidValue;
 }

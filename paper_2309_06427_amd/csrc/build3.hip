@@ -1,0 +1,600 @@
+// Assembly of S and the scaled basis for the compiled state sizes up to 32,
+// with every broadcast operand folded into the FP64 multiply-add.
+//
+// Mapping: one knot per 16-lane row of a wavefront (4 knots per wave, 8 per
+// 128-thread workgroup).  A matrix is held R = 1 (nx <= 16) or R = 2 rows
+// per lane: lane p < P = ceil(nx / R) of the knot's row holds matrix rows p
+// and p + P in its slots 0 and 1.  Row l of such a matrix sits in lane l % P,
+// slot l / P; the FP64 multiply-add with DPP row_newbcast:(l % P) reads that
+// lane's register for every lane of the row (v_fmac_f64_dpp).  Products and
+// elimination steps therefore take no LDS traffic and no extra instruction
+// per operand: an LDS broadcast read feeds one FP64 multiply-add per 8 bytes
+// and runs at half the FP64 rate, the folded broadcast at the full rate.
+//
+// The phases and their arithmetic are those of the LDS kernels of the same
+// assembly (Sec. II-A blocks, Eq. (jacobi), the scaled basis): Q_k^-1 and
+// R_k^-1 by Gauss-Jordan without pivoting (a non-positive pivot flags the
+// matrix as not positive definite), L_k = -A_{k-1} Q_{k-1}^-1,
+// D_k = Q_k^-1 + A_{k-1} Q_{k-1}^-1 A_{k-1}^T + B_{k-1} R_{k-1}^-1 B_{k-1}^T,
+// then W_k = C_k^-1 (D_k = C_k C_k^T) and Oh_k = W_k L_k W_{k-1}^T, or D_k^-1.
+// Sums run in a different order.  Two differences of form: the Gauss-Jordan
+// pivot row is scaled by its pivot's inverse once at the end instead of at its
+// step (the row stays a fixed multiple of the usual one in between), and D_k
+// is made symmetric by copying its upper triangle onto the lower one (the
+// upper triangle is what is stored).
+//
+// A DPP read of a VGPR needs two wait states after a VALU write to it, which
+// the compiler cannot see inside the asm: every block of multiply-adds starts
+// with s_nop 1 and reads no register that an earlier instruction of the block
+// writes.  The blocks are not volatile, so the compiler schedules the operand
+// loads ahead of them; results that only a masked store uses are pinned in
+// wave-uniform code first (keep()), so no block runs with lanes masked off.
+#include "ssp_device.h"
+#include "ssp_host.h"
+#include "ssp_sweep.h"
+
+namespace ssp {
+
+namespace {
+
+constexpr int kThreadsD = 128;            // two waves
+constexpr int kKnotsD = kThreadsD / 16;   // one knot per 16-lane row
+
+template <int NX>
+struct RowGeo {
+    static constexpr int R = NX > 16 ? 2 : 1;      // matrix rows per lane
+    static constexpr int P = (NX + R - 1) / R;     // lanes per knot
+};
+
+template <int L>
+__device__ __forceinline__ double bcast(double v) {
+    return __builtin_amdgcn_mov_dpp(v, 0x150 + L, 0xf, 0xf, true);  // row_newbcast:L
+}
+
+#define SSP_FMAC(d, s, x, l) "v_fmac_f64_dpp %" #d ", %" #s ", %" #x " row_newbcast:%" #l " row_mask:0xf bank_mask:0xf\n\t"
+
+// a_t += bcast_L(s_t) * x, one broadcast lane
+template <int L>
+__device__ __forceinline__ void fmac_l8(double &a0, double &a1, double &a2, double &a3, double &a4, double &a5,
+                                        double &a6, double &a7, double s0, double s1, double s2, double s3, double s4,
+                                        double s5, double s6, double s7, double x) {
+    asm("s_nop 1\n\t" SSP_FMAC(0, 8, 16, 17) SSP_FMAC(1, 9, 16, 17) SSP_FMAC(2, 10, 16, 17)
+                     SSP_FMAC(3, 11, 16, 17) SSP_FMAC(4, 12, 16, 17) SSP_FMAC(5, 13, 16, 17) SSP_FMAC(6, 14, 16, 17)
+                         SSP_FMAC(7, 15, 16, 17)
+                 : "+v"(a0), "+v"(a1), "+v"(a2), "+v"(a3), "+v"(a4), "+v"(a5), "+v"(a6), "+v"(a7)
+                 : "v"(s0), "v"(s1), "v"(s2), "v"(s3), "v"(s4), "v"(s5), "v"(s6), "v"(s7), "v"(x), "n"(L));
+}
+template <int L>
+__device__ __forceinline__ void fmac_l4(double &a0, double &a1, double &a2, double &a3, double s0, double s1, double s2,
+                                        double s3, double x) {
+    asm("s_nop 1\n\t" SSP_FMAC(0, 4, 8, 9) SSP_FMAC(1, 5, 8, 9) SSP_FMAC(2, 6, 8, 9) SSP_FMAC(3, 7, 8, 9)
+                 : "+v"(a0), "+v"(a1), "+v"(a2), "+v"(a3)
+                 : "v"(s0), "v"(s1), "v"(s2), "v"(s3), "v"(x), "n"(L));
+}
+template <int L>
+__device__ __forceinline__ void fmac_l2(double &a0, double &a1, double s0, double s1, double x) {
+    asm("s_nop 1\n\t" SSP_FMAC(0, 2, 4, 5) SSP_FMAC(1, 3, 4, 5)
+                 : "+v"(a0), "+v"(a1)
+                 : "v"(s0), "v"(s1), "v"(x), "n"(L));
+}
+template <int L>
+__device__ __forceinline__ void fmac_l1(double &a0, double s0, double x) {
+    asm("s_nop 1\n\t" SSP_FMAC(0, 1, 2, 3) : "+v"(a0) : "v"(s0), "v"(x), "n"(L));
+}
+
+// a_t += bcast_{L_t}(s_t) * x, one broadcast lane per multiply-add
+template <int L0, int L1, int L2, int L3, int L4, int L5, int L6, int L7>
+__device__ __forceinline__ void fmac_j8(double &a0, double &a1, double &a2, double &a3, double &a4, double &a5,
+                                        double &a6, double &a7, double s0, double s1, double s2, double s3, double s4,
+                                        double s5, double s6, double s7, double x) {
+    asm("s_nop 1\n\t" SSP_FMAC(0, 8, 16, 17) SSP_FMAC(1, 9, 16, 18) SSP_FMAC(2, 10, 16, 19)
+                     SSP_FMAC(3, 11, 16, 20) SSP_FMAC(4, 12, 16, 21) SSP_FMAC(5, 13, 16, 22) SSP_FMAC(6, 14, 16, 23)
+                         SSP_FMAC(7, 15, 16, 24)
+                 : "+v"(a0), "+v"(a1), "+v"(a2), "+v"(a3), "+v"(a4), "+v"(a5), "+v"(a6), "+v"(a7)
+                 : "v"(s0), "v"(s1), "v"(s2), "v"(s3), "v"(s4), "v"(s5), "v"(s6), "v"(s7), "v"(x), "n"(L0),
+                   "n"(L1), "n"(L2), "n"(L3), "n"(L4), "n"(L5), "n"(L6), "n"(L7));
+}
+template <int L0, int L1, int L2, int L3>
+__device__ __forceinline__ void fmac_j4(double &a0, double &a1, double &a2, double &a3, double s0, double s1, double s2,
+                                        double s3, double x) {
+    asm("s_nop 1\n\t" SSP_FMAC(0, 4, 8, 9) SSP_FMAC(1, 5, 8, 10) SSP_FMAC(2, 6, 8, 11) SSP_FMAC(3, 7, 8, 12)
+                 : "+v"(a0), "+v"(a1), "+v"(a2), "+v"(a3)
+                 : "v"(s0), "v"(s1), "v"(s2), "v"(s3), "v"(x), "n"(L0), "n"(L1), "n"(L2), "n"(L3));
+}
+template <int L0, int L1>
+__device__ __forceinline__ void fmac_j2(double &a0, double &a1, double s0, double s1, double x) {
+    asm("s_nop 1\n\t" SSP_FMAC(0, 2, 4, 5) SSP_FMAC(1, 3, 4, 6)
+                 : "+v"(a0), "+v"(a1)
+                 : "v"(s0), "v"(s1), "v"(x), "n"(L0), "n"(L1));
+}
+
+#undef SSP_FMAC
+
+__device__ __forceinline__ void keep1(double v) { asm volatile("" ::"v"(v)); }
+
+// Make every value of a[][] be computed here (in wave-uniform code).
+template <int R, int N>
+__device__ __forceinline__ void keep(const double (&a)[R][N]) {
+    static_for<0, R>([&](auto s_) {
+        static_for<0, N>([&](auto jc) { keep1(a[decltype(s_)::value][decltype(jc)::value]); });
+    });
+}
+
+// acc[j] += bcast_L(src[j]) * x for J0 <= j < J1 (src: the same row slot in
+// every lane, read from lane L)
+template <int L, int J0, int J1, int N>
+__device__ __forceinline__ void row_l(double (&acc)[N], const double (&src)[N], double x) {
+    constexpr int c = J1 - J0;
+    if constexpr (c >= 8) {
+        fmac_l8<L>(acc[J0], acc[J0 + 1], acc[J0 + 2], acc[J0 + 3], acc[J0 + 4], acc[J0 + 5], acc[J0 + 6], acc[J0 + 7],
+                   src[J0], src[J0 + 1], src[J0 + 2], src[J0 + 3], src[J0 + 4], src[J0 + 5], src[J0 + 6],
+                   src[J0 + 7], x);
+        row_l<L, J0 + 8, J1>(acc, src, x);
+    } else if constexpr (c >= 4) {
+        fmac_l4<L>(acc[J0], acc[J0 + 1], acc[J0 + 2], acc[J0 + 3], src[J0], src[J0 + 1], src[J0 + 2], src[J0 + 3], x);
+        row_l<L, J0 + 4, J1>(acc, src, x);
+    } else if constexpr (c >= 2) {
+        fmac_l2<L>(acc[J0], acc[J0 + 1], src[J0], src[J0 + 1], x);
+        row_l<L, J0 + 2, J1>(acc, src, x);
+    } else if constexpr (c == 1) {
+        fmac_l1<L>(acc[J0], src[J0], x);
+    }
+}
+
+// acc[j] += bcast_{j % P}(m[j / P][E]) * x for J0 <= j < J1: element E of
+// row j of a matrix held R rows per lane (the transposed product)
+template <int P, int E, int J0, int J1, int R, int N, int M>
+__device__ __forceinline__ void row_t(double (&acc)[N], const double (&m)[R][M], double x) {
+    constexpr int c = J1 - J0;
+    if constexpr (c >= 8) {
+        fmac_j8<J0 % P, (J0 + 1) % P, (J0 + 2) % P, (J0 + 3) % P, (J0 + 4) % P, (J0 + 5) % P, (J0 + 6) % P,
+                (J0 + 7) % P>(acc[J0], acc[J0 + 1], acc[J0 + 2], acc[J0 + 3], acc[J0 + 4], acc[J0 + 5], acc[J0 + 6],
+                              acc[J0 + 7], m[J0 / P][E], m[(J0 + 1) / P][E], m[(J0 + 2) / P][E],
+                              m[(J0 + 3) / P][E], m[(J0 + 4) / P][E], m[(J0 + 5) / P][E], m[(J0 + 6) / P][E],
+                              m[(J0 + 7) / P][E], x);
+        row_t<P, E, J0 + 8, J1>(acc, m, x);
+    } else if constexpr (c >= 4) {
+        fmac_j4<J0 % P, (J0 + 1) % P, (J0 + 2) % P, (J0 + 3) % P>(acc[J0], acc[J0 + 1], acc[J0 + 2], acc[J0 + 3],
+                                                                  m[J0 / P][E], m[(J0 + 1) / P][E],
+                                                                  m[(J0 + 2) / P][E], m[(J0 + 3) / P][E], x);
+        row_t<P, E, J0 + 4, J1>(acc, m, x);
+    } else if constexpr (c >= 2) {
+        fmac_j2<J0 % P, (J0 + 1) % P>(acc[J0], acc[J0 + 1], m[J0 / P][E], m[(J0 + 1) / P][E], x);
+        row_t<P, E, J0 + 2, J1>(acc, m, x);
+    } else if constexpr (c == 1) {
+        fmac_l1<J0 % P>(acc[J0], m[J0 / P][E], x);
+    }
+}
+
+// Gauss-Jordan inverse, without pivoting, of the n x n SPD matrix (n <= NC)
+// held RS rows per lane in a[][] (rows >= n: identity rows).  At step k every
+// other row subtracts a_ik / a_kk times the broadcast pivot row and takes
+// -a_ik / a_kk in column k; the pivot row keeps its values and takes 1 in
+// column k, and is scaled by 1 / a_kk after the last step.  Returns false if
+// a pivot is not positive.
+template <int P, int RS, int NC>
+__device__ __forceinline__ bool gj_dpp(double (&a)[RS][NC], int p, int n) {
+    bool ok = true;
+    double sc[RS];
+    static_for<0, RS>([&](auto sc_) { sc[decltype(sc_)::value] = 1.0; });
+    static_for<0, NC>([&](auto kc) {
+        constexpr int k = decltype(kc)::value, Lk = k % P, Sk = k / P;
+        if (k < n) {
+            const double piv = bcast<Lk>(a[Sk][k]);
+            if (!(piv > 0.0)) ok = false;
+            const double inv = 1.0 / piv;
+            double ng[RS];
+            bool me[RS];
+            static_for<0, RS>([&](auto s_) {
+                constexpr int s = decltype(s_)::value;
+                me[s] = s == Sk && p == Lk;
+                ng[s] = me[s] ? 0.0 : -a[s][k] * inv;
+                if (me[s]) sc[s] = inv;
+            });
+            // the other slots first, then the pivot's slot (whose pivot row stays as it is)
+            static_for<0, RS>([&](auto s_) {
+                constexpr int s = decltype(s_)::value;
+                if constexpr (s != Sk) {
+                    row_l<Lk, 0, k>(a[s], a[Sk], ng[s]);
+                    row_l<Lk, k + 1, NC>(a[s], a[Sk], ng[s]);
+                }
+            });
+            row_l<Lk, 0, k>(a[Sk], a[Sk], ng[Sk]);
+            row_l<Lk, k + 1, NC>(a[Sk], a[Sk], ng[Sk]);
+            static_for<0, RS>([&](auto s_) {
+                constexpr int s = decltype(s_)::value;
+                a[s][k] = me[s] ? 1.0 : ng[s];
+            });
+        }
+    });
+    static_for<0, RS>([&](auto s_) {
+        constexpr int s = decltype(s_)::value;
+        static_for<0, NC>([&](auto jc) { a[s][decltype(jc)::value] *= sc[s]; });
+    });
+    return ok;
+}
+
+// W = C^-1 for the Cholesky factor C of the SPD matrix held R rows per lane
+// in a[][] (A = C C^T), in place: forward elimination of [A | I] without
+// pivoting, rows below the pivot subtracting f = a_ij / u_jj times the
+// broadcast pivot row and taking -f in column j, leaves E = L^-1 on the left
+// and U's pivots u_ii on the diagonal; W = diag(u)^-1/2 E.  Returns false if a
+// pivot is not positive.
+template <int P, int R, int NX>
+__device__ __forceinline__ bool lower_inverse_dpp(double (&a)[R][NX], int p) {
+    bool ok = true;
+    static_for<0, NX>([&](auto jc) {
+        constexpr int j = decltype(jc)::value, Lj = j % P, Sj = j / P;
+        const double piv = bcast<Lj>(a[Sj][j]);
+        if (!(piv > 0.0)) ok = false;
+        const double inv = 1.0 / piv;
+        double ng[R];
+        bool below[R];
+        static_for<0, R>([&](auto s_) {
+            constexpr int s = decltype(s_)::value;
+            below[s] = p + s * P > j;
+            ng[s] = below[s] ? -a[s][j] * inv : 0.0;
+        });
+        static_for<0, R>([&](auto s_) {
+            constexpr int s = decltype(s_)::value;
+            if constexpr (s != Sj) {
+                row_l<Lj, 0, j>(a[s], a[Sj], ng[s]);
+                row_l<Lj, j + 1, NX>(a[s], a[Sj], ng[s]);
+            }
+        });
+        row_l<Lj, 0, j>(a[Sj], a[Sj], ng[Sj]);
+        row_l<Lj, j + 1, NX>(a[Sj], a[Sj], ng[Sj]);
+        static_for<0, R>([&](auto s_) {
+            constexpr int s = decltype(s_)::value;
+            if (below[s]) a[s][j] = ng[s];
+        });
+    });
+    static_for<0, R>([&](auto s_) {
+        constexpr int s = decltype(s_)::value;
+        const int i = p + s * P;
+        double u = 1.0;
+        static_for<0, NX>([&](auto jc) {
+            constexpr int j = decltype(jc)::value;
+            if (j == i) u = a[s][j];
+        });
+        const double sc = 1.0 / sqrt(u);
+        static_for<0, NX>([&](auto jc) {
+            constexpr int j = decltype(jc)::value;
+            a[s][j] = j < i ? a[s][j] * sc : (j == i ? sc : 0.0);
+        });
+    });
+    return ok;
+}
+
+// per-lane place: knot slot g in the workgroup, lane p of the knot
+template <int NX>
+struct Dl {
+    int g, p, knot;
+    bool act;  // lane p < P of a knot < N
+    __device__ int row(int s) const { return p + s * RowGeo<NX>::P; }
+    __device__ bool has(int s) const { return act && row(s) < NX; }
+};
+
+template <int NX>
+__device__ __forceinline__ Dl<NX> dl_of(int k0, int N) {
+    Dl<NX> d;
+    d.g = threadIdx.x >> 4;
+    d.p = threadIdx.x & 15;
+    d.knot = k0 + d.g;
+    d.act = d.p < RowGeo<NX>::P && d.knot < N;
+    return d;
+}
+
+// rows of an n-column row-major FP64 block into slots (row r of the block at
+// src + r * n; rows clamped to the block, columns >= n zero)
+template <int NX, int RS, int NC>
+__device__ __forceinline__ void load_slots(const double *__restrict__ src, int n, int nrows, int p,
+                                           double (&a)[RS][NC]) {
+    static_for<0, RS>([&](auto s_) {
+        constexpr int s = decltype(s_)::value;
+        const int r = min(p + s * RowGeo<NX>::P, nrows - 1);
+        static_for<0, NC>([&](auto jc) {
+            constexpr int j = decltype(jc)::value;
+            a[s][j] = j < n ? src[(int64_t)r * n + j] : 0.0;
+        });
+    });
+}
+
+template <typename TM, int NX>
+__device__ __forceinline__ void load_slots_t(const TM *__restrict__ src, int p, double (&a)[RowGeo<NX>::R][NX]) {
+    static_for<0, RowGeo<NX>::R>([&](auto s_) {
+        constexpr int s = decltype(s_)::value;
+        const int r = min(p + s * RowGeo<NX>::P, NX - 1);
+        static_for<0, NX>([&](auto jc) {
+            constexpr int j = decltype(jc)::value;
+            a[s][j] = (double)src[r * NX + j];
+        });
+    });
+}
+
+// rows that are not this lane's real rows become identity rows
+template <int NX, int RS, int NC>
+__device__ __forceinline__ void identity_outside(double (&a)[RS][NC], int p, bool live, int n) {
+    static_for<0, RS>([&](auto s_) {
+        constexpr int s = decltype(s_)::value;
+        const int r = p + s * RowGeo<NX>::P;
+        const bool real = live && r < n;
+        static_for<0, NC>([&](auto jc) {
+            constexpr int j = decltype(jc)::value;
+            a[s][j] = real ? a[s][j] : (j == r ? 1.0 : 0.0);
+        });
+    });
+}
+
+template <int NX, int RS, int NC>
+__device__ __forceinline__ void store_slots(double *__restrict__ dst, int n, const Dl<NX> &d, const double (&a)[RS][NC]) {
+    static_for<0, RS>([&](auto s_) {
+        constexpr int s = decltype(s_)::value;
+        const int r = d.row(s);
+        if (d.act && r < n)
+            static_for<0, NC>([&](auto jc) {
+                constexpr int j = decltype(jc)::value;
+                if (j < n) dst[(int64_t)r * n + j] = a[s][j];
+            });
+    });
+}
+
+// Copy the upper triangle of the matrix held in a[][] onto its lower triangle
+// through the knot's LDS buffer (P rows of NX doubles), one slot at a time:
+// upper entries are never changed, so every copy reads original values.
+template <int NX>
+__device__ __forceinline__ void lower_from_upper(double (&a)[RowGeo<NX>::R][NX], int p, double *buf) {
+    constexpr int R = RowGeo<NX>::R, P = RowGeo<NX>::P;
+    static_for<0, R>([&](auto t_) {
+        constexpr int t = decltype(t_)::value;  // source slot: rows q + t P
+        wave_sync();
+        if (p < P) static_for<0, NX>([&](auto jc) { buf[p * NX + decltype(jc)::value] = a[t][decltype(jc)::value]; });
+        wave_sync();
+        static_for<0, R>([&](auto s_) {
+            constexpr int s = decltype(s_)::value;
+            const int i = min(p + s * P, NX - 1);
+            static_for<0, P>([&](auto qc) {
+                constexpr int j = decltype(qc)::value + t * P;  // row j of the source slot
+                if constexpr (j < NX) {
+                    const double v = buf[decltype(qc)::value * NX + i];  // entry (j, i)
+                    if (j < i) a[s][j] = v;
+                }
+            });
+        });
+    });
+    wave_sync();
+}
+
+template <typename TM, int NX>
+__device__ __forceinline__ void store_split_slots(TM *__restrict__ hi, float *__restrict__ lo, const Dl<NX> &d,
+                                                  const double (&a)[RowGeo<NX>::R][NX], double scale) {
+    static_for<0, RowGeo<NX>::R>([&](auto s_) {
+        constexpr int s = decltype(s_)::value;
+        const int r = d.row(s);
+        if (d.has(s))
+            static_for<0, NX>([&](auto jc) {
+                constexpr int j = decltype(jc)::value;
+                const double v = scale * a[s][j];
+                const TM h = (TM)v;
+                hi[r * NX + j] = h;
+                if (lo) lo[r * NX + j] = (float)(v - (double)h);
+            });
+    });
+}
+
+template <typename TM, int NX>
+__device__ __forceinline__ void store_split_packed_slots(TM *__restrict__ hi, float *__restrict__ lo, const Dl<NX> &d,
+                                                         const double (&a)[RowGeo<NX>::R][NX]) {
+    static_for<0, RowGeo<NX>::R>([&](auto s_) {
+        constexpr int s = decltype(s_)::value;
+        const int r = d.row(s);
+        if (d.has(s)) {
+            const int base = packed_row(r, NX);
+            static_for<0, NX>([&](auto jc) {
+                constexpr int j = decltype(jc)::value;
+                if (j >= r) {
+                    const double v = a[s][j];
+                    const TM h = (TM)v;
+                    hi[base + j] = h;
+                    if (lo) lo[base + j] = (float)(v - (double)h);
+                }
+            });
+        }
+    });
+}
+
+}  // namespace
+
+// Q_k^-1 for every knot and R_k^-1 for k < N-1, into the FP64 workspaces
+// (nu = NX / 2).
+template <int NX>
+__global__ __launch_bounds__(kThreadsD) void k_bdpp_inv(BuildArgs a, const int2 *items) {
+    constexpr int R = RowGeo<NX>::R, P = RowGeo<NX>::P, NU = NX / 2, RU = (NU + P - 1) / P;
+    const int2 it = items[blockIdx.x];
+    const int pr = it.x, N = a.N[pr];
+    const Dl<NX> d = dl_of<NX>(it.y, N);
+    const int kc = min(d.knot, N - 1);
+    const int64_t oq = a.off_nn[pr] + (int64_t)kc * NX * NX;
+    double q[R][NX];
+    load_slots<NX>(a.Q + oq, NX, NX, d.p, q);
+    identity_outside<NX>(q, d.p, d.act, NX);
+    bool ok = gj_dpp<P, R, NX>(q, d.p, NX);
+    store_slots<NX>(a.Qinv + oq, NX, d, q);
+    const int64_t orr = a.off_uu[pr] + (int64_t)kc * NU * NU;
+    const bool live = d.act && d.knot < N - 1;
+    double r[RU][NU];
+    load_slots<NX>(a.R + orr, NU, NU, d.p, r);
+    identity_outside<NX>(r, d.p, live, NU);
+    const bool okr = gj_dpp<P, RU, NU>(r, d.p, NU);
+    if (live) ok = ok && okr;
+    if (live) store_slots<NX>(a.Rinv + orr, NU, d, r);
+    if (d.act && !ok) atomicOr(a.status + pr, kNotSpd);
+}
+
+// D_k, L_k (storage type, FP32 remainder under FP32 storage) and then W_k
+// (SCALED: the scaled basis) or D_k^-1 (nu = NX / 2).
+// (at least two waves per SIMD: the operand loads are hoisted only as far as
+// 256 registers allow)
+template <typename TM, int NX, bool SCALED>
+__global__ __launch_bounds__(kThreadsD) __attribute__((amdgpu_waves_per_eu(2))) void k_bdpp_asm(BuildArgs a, const int2 *items) {
+    constexpr int R = RowGeo<NX>::R, P = RowGeo<NX>::P, NN = NX * NX, NU = NX / 2, nu = NU;
+    __shared__ __align__(16) double sm[kKnotsD * RowGeo<NX>::P * NX];
+    const int2 it = items[blockIdx.x];
+    const int pr = it.x, N = a.N[pr];
+    const Dl<NX> d = dl_of<NX>(it.y, N);
+    double *buf = sm + d.g * RowGeo<NX>::P * NX;
+    const int k = d.knot, kc = min(k, N - 1), km = max(kc - 1, 0);
+    const bool prev = d.act && k > 0;
+    const int bs = block_stride(NX, sizeof(TM)), bp = packed_stride(NX, sizeof(TM));
+    TM *blk = (TM *)a.B3 + a.off_b3[pr] + (int64_t)kc * (2 * bp + bs);  // D_k (packed), L_k, D_k^-1 (packed)
+    const int64_t ol = a.off_blk[pr] + (int64_t)kc * bs;
+    const int64_t od = a.off_pk[pr] + (int64_t)kc * bp;
+    int rw[R];
+    static_for<0, R>([&](auto s_) { rw[decltype(s_)::value] = min(d.row(decltype(s_)::value), NX - 1); });
+
+    // t = A_{k-1} Q_{k-1}^-1 (rows of Q^-1 broadcast)
+    double m[R][NX], t[R][NX];
+    load_slots<NX>(a.Qinv + a.off_nn[pr] + (int64_t)km * NN, NX, NX, d.p, m);
+    static_for<0, R>([&](auto s_) { static_for<0, NX>([&](auto jc) { t[decltype(s_)::value][decltype(jc)::value] = 0.0; }); });
+    const double *Ar = a.A + a.off_nn[pr] + (int64_t)km * NN;
+    static_for<0, NX>([&](auto lc) {
+        constexpr int l = decltype(lc)::value;
+        static_for<0, R>([&](auto s_) {
+            constexpr int s = decltype(s_)::value;
+            const double av = Ar[rw[s] * NX + l], x = prev ? av : 0.0;  // address valid for every lane
+            row_l<l % P, 0, NX>(t[s], m[l / P], x);
+        });
+    });
+    store_split_slots<TM, NX>(blk + bp, a.SLlo ? a.SLlo + ol : nullptr, d, t, -1.0);  // L_k = -t
+
+    // D_k = Q_k^-1 + A t^T (rows of t broadcast)
+    double dk[R][NX];
+    load_slots<NX>(a.Qinv + a.off_nn[pr] + (int64_t)kc * NN, NX, NX, d.p, dk);
+    static_for<0, NX>([&](auto lc) {
+        constexpr int l = decltype(lc)::value;
+        static_for<0, R>([&](auto s_) {
+            constexpr int s = decltype(s_)::value;
+            const double av = Ar[rw[s] * NX + l], x = prev ? av : 0.0;  // address valid for every lane
+            row_t<P, l, 0, NX>(dk[s], t, x);
+        });
+    });
+    // D_k += B u^T with u = B_{k-1} R_{k-1}^-1
+    {
+        constexpr int RU = (NU + P - 1) / P;
+        double ri[RU][NU], u[R][NU];
+        load_slots<NX>(a.Rinv + a.off_uu[pr] + (int64_t)km * nu * nu, nu, nu, d.p, ri);
+        static_for<0, R>([&](auto s_) { static_for<0, NU>([&](auto jc) { u[decltype(s_)::value][decltype(jc)::value] = 0.0; }); });
+        const double *Br = a.B + a.off_nu[pr] + (int64_t)km * NX * nu;
+        static_for<0, NU>([&](auto lc) {
+            constexpr int l = decltype(lc)::value;
+            static_for<0, R>([&](auto s_) {
+                    constexpr int s = decltype(s_)::value;
+                    const double bv = Br[rw[s] * nu + l], x = prev ? bv : 0.0;
+                    row_l<l % P, 0, NU>(u[s], ri[l / P], x);
+                });
+        });
+        static_for<0, NU>([&](auto lc) {
+            constexpr int l = decltype(lc)::value;
+            static_for<0, R>([&](auto s_) {
+                    constexpr int s = decltype(s_)::value;
+                    const double bv = Br[rw[s] * nu + l], x = prev ? bv : 0.0;
+                    row_t<P, l, 0, NX>(dk[s], u, x);
+                });
+        });
+    }
+    lower_from_upper<NX>(dk, d.p, buf);
+    store_split_packed_slots<TM, NX>(blk, a.SDlo ? a.SDlo + od : nullptr, d, dk);
+    bool ok;
+    if constexpr (SCALED) {
+        // scaled basis: W_k = C_k^-1, stored full (zeros above the diagonal)
+        ok = lower_inverse_dpp<P, R, NX>(dk, d.p);
+        store_split_slots<TM, NX>((TM *)a.Zs + ol, (float *)nullptr, d, dk, 1.0);
+    } else {
+        ok = gj_dpp<P, R, NX>(dk, d.p, NX);
+        lower_from_upper<NX>(dk, d.p, buf);
+        store_split_packed_slots<TM, NX>(blk + bp + bs, (float *)nullptr, d, dk);
+    }
+    if (d.act && !ok) atomicOr(a.status + pr, kNotSpd);
+}
+
+// Oh_k = W_k L_k W_{k-1}^T (k >= 1, Oh_0 = 0) in FP64 from the stored W and
+// L_k (storage type): X = L_k W_{k-1}^T with the rows of W_{k-1} broadcast,
+// then W_k X with the rows of X broadcast.
+template <typename TM, int NX>
+__global__ __launch_bounds__(kThreadsD) void k_bdpp_ohat(BuildArgs a, const int2 *items) {
+    constexpr int R = RowGeo<NX>::R, P = RowGeo<NX>::P;
+    const int2 it = items[blockIdx.x];
+    const int pr = it.x, N = a.N[pr];
+    const Dl<NX> d = dl_of<NX>(it.y, N);
+    const int k = d.knot, kc = min(k, N - 1), km = max(kc - 1, 0);
+    const bool prev = d.act && k > 0;
+    const int bs = block_stride(NX, sizeof(TM)), bp = packed_stride(NX, sizeof(TM));
+    const TM *Z = (const TM *)a.Zs + a.off_blk[pr];
+    const TM *Lk = (const TM *)a.B3 + a.off_b3[pr] + (int64_t)kc * (2 * bp + bs) + bp;
+    int rw[R];
+    static_for<0, R>([&](auto s_) { rw[decltype(s_)::value] = min(d.row(decltype(s_)::value), NX - 1); });
+    double w[R][NX], x[R][NX];
+    load_slots_t<TM, NX>(Z + (int64_t)km * bs, d.p, w);
+    static_for<0, R>([&](auto s_) { static_for<0, NX>([&](auto jc) { x[decltype(s_)::value][decltype(jc)::value] = 0.0; }); });
+    static_for<0, NX>([&](auto lc) {
+        constexpr int l = decltype(lc)::value;
+        static_for<0, R>([&](auto s_) {
+            constexpr int s = decltype(s_)::value;
+            const double lv = (double)Lk[rw[s] * NX + l], v = prev ? lv : 0.0;
+            row_t<P, l, 0, NX>(x[s], w, v);
+        });
+    });
+    const TM *Wk = Z + (int64_t)kc * bs;
+    double o[R][NX];
+    static_for<0, R>([&](auto s_) { static_for<0, NX>([&](auto jc) { o[decltype(s_)::value][decltype(jc)::value] = 0.0; }); });
+    static_for<0, NX>([&](auto lc) {
+        constexpr int l = decltype(lc)::value;
+        static_for<0, R>([&](auto s_) {
+            constexpr int s = decltype(s_)::value;
+            const double v = (double)Wk[rw[s] * NX + l];
+            row_l<l % P, 0, NX>(o[s], x[l / P], v);
+        });
+    });
+    keep(o);
+    store_split_slots<TM, NX>((TM *)a.OH + a.off_blk[pr] + (int64_t)kc * bs, (float *)nullptr, d, o, 1.0);
+}
+
+template <int NX>
+hipError_t launch_dpp_class(const BuildArgs &a, const int2 *items, int nitems, bool fp32, hipStream_t s) {
+    if (nitems == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bdpp_inv<NX>, dim3(nitems), dim3(kThreadsD), 0, s, a, items);
+    hipError_t e = hipGetLastError();
+    if (e) return e;
+    const bool sc = a.Zs != nullptr;
+    const dim3 g(nitems), t(kThreadsD);
+    if (fp32 && sc)
+        hipLaunchKernelGGL((k_bdpp_asm<float, NX, true>), g, t, 0, s, a, items);
+    else if (fp32)
+        hipLaunchKernelGGL((k_bdpp_asm<float, NX, false>), g, t, 0, s, a, items);
+    else if (sc)
+        hipLaunchKernelGGL((k_bdpp_asm<double, NX, true>), g, t, 0, s, a, items);
+    else
+        hipLaunchKernelGGL((k_bdpp_asm<double, NX, false>), g, t, 0, s, a, items);
+    return hipGetLastError();
+}
+
+template <int NX>
+hipError_t launch_dpp_ohat(const BuildArgs &a, const int2 *items, int nitems, bool fp32, hipStream_t s) {
+    if (nitems == 0) return hipSuccess;
+    if (fp32)
+        hipLaunchKernelGGL((k_bdpp_ohat<float, NX>), dim3(nitems), dim3(kThreadsD), 0, s, a, items);
+    else
+        hipLaunchKernelGGL((k_bdpp_ohat<double, NX>), dim3(nitems), dim3(kThreadsD), 0, s, a, items);
+    return hipGetLastError();
+}
+
+int dpp_knots_per_item() { return kKnotsD; }
+
+template hipError_t launch_dpp_class<6>(const BuildArgs &, const int2 *, int, bool, hipStream_t);
+template hipError_t launch_dpp_class<14>(const BuildArgs &, const int2 *, int, bool, hipStream_t);
+template hipError_t launch_dpp_class<26>(const BuildArgs &, const int2 *, int, bool, hipStream_t);
+template hipError_t launch_dpp_ohat<6>(const BuildArgs &, const int2 *, int, bool, hipStream_t);
+template hipError_t launch_dpp_ohat<14>(const BuildArgs &, const int2 *, int, bool, hipStream_t);
+template hipError_t launch_dpp_ohat<26>(const BuildArgs &, const int2 *, int, bool, hipStream_t);
+
+}  // namespace ssp

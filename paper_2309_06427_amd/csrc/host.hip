@@ -71,11 +71,8 @@ int poly_steps(ssp_precon pc) {
 // every problem has a compiled state size (the register-resident assembly,
 // which also builds the scaled basis, and the scaled solve exist for those)
 bool scaled_possible(const ssp_batch *b) {
-    for (int p = 0; p < b->P; ++p) {
-        bool cls = false;
-        for (int c = 0; c < ssp::kBuildClasses; ++c) cls = cls || (b->nx[p] == ssp::kBuildSizes[c] && b->nu[p] <= b->nx[p]);
-        if (!cls) return false;
-    }
+    for (int p = 0; p < b->P; ++p)
+        if (ssp::build_class_of(b->nx[p], b->nu[p]) < 0) return false;
     return true;
 }
 
@@ -553,16 +550,14 @@ ssp_status ssp_batch_create(int32_t nprob, const int32_t *N, const int32_t *nx, 
     std::vector<int32_t> generic;
     for (int c = 0; c < ssp::kBuildClasses; ++c) {
         b->item_off[c] = (int)items.size();
-        const int X = ssp::kBuildSizes[c], per = ssp::build_knots_per_item(X);
+        const int per = ssp::build_knots_per_item(c);
         for (int32_t p : order)
-            if (nx[p] == X && nu[p] <= X)
+            if (ssp::build_class_of(nx[p], nu[p]) == c)
                 for (int k0 = 0; k0 < N[p]; k0 += per) items.push_back(make_int2(p, k0));
     }
     b->item_off[ssp::kBuildClasses] = (int)items.size();
     for (int p = 0; p < nprob; ++p) {
-        bool cls = false;
-        for (int c = 0; c < ssp::kBuildClasses; ++c) cls = cls || (nx[p] == ssp::kBuildSizes[c] && nu[p] <= nx[p]);
-        if (cls) continue;
+        if (ssp::build_class_of(nx[p], nu[p]) >= 0) continue;
         for (int64_t g = b->koff[p]; g < b->koff[p + 1]; ++g) generic.push_back((int32_t)g);
         b->gen_nx_max = std::max(b->gen_nx_max, (int)nx[p]);
         b->gen_nu_max = std::max(b->gen_nu_max, (int)nu[p]);

@@ -66,15 +66,24 @@ struct SolveArgs {
 // Generic assembly (any nx <= 64), one 64-lane workgroup per knot of
 // a.knot_list[0 .. knots).
 hipError_t launch_build(const BuildArgs &a, int64_t knots, int nx_max, int nu_max, bool fp32, hipStream_t s);
-// Register-resident assembly for the state sizes kBuildSizes (nu <= nx):
-// work item (problem, first knot) covers build_knots_per_item(nx) knots.
-constexpr int kBuildClasses = 4;
+// Register-resident assembly for the state sizes kBuildSizes: class
+// build_class_of(nx, nu) (-1: the generic kernels); a work item (problem,
+// first knot) of class c covers build_knots_per_item(c) knots.
+constexpr int kBuildClasses = 7;
 extern const int kBuildSizes[kBuildClasses];
-int build_knots_per_item(int nx);
+int build_class_of(int nx, int nu);
+int build_knots_per_item(int cls);
 hipError_t launch_build_class(int cls, const BuildArgs &a, const int2 *items, int nitems, bool fp32, hipStream_t s);
-// Scaled basis for one compiled state size, after launch_build_class wrote
-// Z_k (a.Zs, a.Zw): Oh_k = Z_k^T L_k Z_{k-1} for the same work items.
+// Scaled basis for one class, after launch_build_class wrote W_k (a.Zs) and
+// L_k: Oh_k = W_k L_k W_{k-1}^T for the same work items.
 hipError_t launch_build_ohat(int cls, const BuildArgs &a, const int2 *items, int nitems, bool fp32, hipStream_t s);
+// The same two steps with DPP-broadcast kernels (state sizes up to 32, one
+// knot per 16-lane row, dpp_knots_per_item() knots per work item).
+int dpp_knots_per_item();
+template <int NX>
+hipError_t launch_dpp_class(const BuildArgs &a, const int2 *items, int nitems, bool fp32, hipStream_t s);
+template <int NX>
+hipError_t launch_dpp_ohat(const BuildArgs &a, const int2 *items, int nitems, bool fp32, hipStream_t s);
 // D_k^-1 = W_k^T W_k into the stored D_k^-1 slots after a scaled build
 // (from the FP64 W of a.Zw), for the consumers of D^-1 (export, explicit
 // stair blocks).
