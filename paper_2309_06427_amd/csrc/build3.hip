@@ -37,7 +37,7 @@ namespace ssp {
 
 namespace {
 
-constexpr int kThreadsD = 128;            // two waves
+constexpr int kThreadsD = 64;             // one wave
 constexpr int kKnotsD = kThreadsD / 16;   // one knot per 16-lane row
 
 template <int NX>
@@ -120,6 +120,38 @@ __device__ __forceinline__ void keep(const double (&a)[R][N]) {
     });
 }
 
+// An empty asm that makes v depend on w: reads addressed through v stay below
+// the computation of w.
+__device__ __forceinline__ void tie(int &v, double w) { asm("" : "+v"(v) : "v"(w)); }
+
+// Runs step(l, x) for l = 0 .. NL-1 with x[s] = blk[ro[s] + l] (0 where
+// !live), the LDS reads of step l + 1 issued at the start of step l: the row
+// offsets are tied to step l - 1's result dep(s), so the compiler cannot
+// hoist the reads of all steps to the top (and spill what they occupy).
+template <int NL, int R, typename T, typename Step, typename Dep>
+__device__ __forceinline__ void lds_steps(const T *blk, int (&ro)[R], bool live, Step &&step, Dep &&dep) {
+    double xn[R];
+    static_for<0, R>([&](auto s_) { xn[decltype(s_)::value] = (double)blk[ro[decltype(s_)::value]]; });
+    static_for<0, NL>([&](auto lc) {
+        constexpr int l = decltype(lc)::value;
+        double xc[R];
+        static_for<0, R>([&](auto s_) {
+            constexpr int s = decltype(s_)::value;
+            xc[s] = live ? xn[s] : 0.0;
+        });
+        if constexpr (l + 1 < NL)
+            static_for<0, R>([&](auto s_) {
+                constexpr int s = decltype(s_)::value;
+                xn[s] = (double)blk[ro[s] + l + 1];
+            });
+        step(lc, xc);
+        static_for<0, R>([&](auto s_) {
+            constexpr int s = decltype(s_)::value;
+            tie(ro[s], dep(s_));
+        });
+    });
+}
+
 // acc[j] += bcast_L(src[j]) * x for J0 <= j < J1 (src: the same row slot in
 // every lane, read from lane L)
 template <int L, int J0, int J1, int N>
@@ -184,12 +216,15 @@ __device__ __forceinline__ bool gj_dpp(double (&a)[RS][NC], int p, int n) {
             if (!(piv > 0.0)) ok = false;
             const double inv = 1.0 / piv;
             double ng[RS];
-            bool me[RS];
             static_for<0, RS>([&](auto s_) {
                 constexpr int s = decltype(s_)::value;
-                me[s] = s == Sk && p == Lk;
-                ng[s] = me[s] ? 0.0 : -a[s][k] * inv;
-                if (me[s]) sc[s] = inv;
+                if constexpr (s == Sk) {
+                    const bool me = p == Lk;  // this lane holds the pivot row
+                    ng[s] = me ? 0.0 : -a[s][k] * inv;
+                    sc[s] = me ? inv : sc[s];
+                } else {
+                    ng[s] = -a[s][k] * inv;
+                }
             });
             // the other slots first, then the pivot's slot (whose pivot row stays as it is)
             static_for<0, RS>([&](auto s_) {
@@ -203,7 +238,10 @@ __device__ __forceinline__ bool gj_dpp(double (&a)[RS][NC], int p, int n) {
             row_l<Lk, k + 1, NC>(a[Sk], a[Sk], ng[Sk]);
             static_for<0, RS>([&](auto s_) {
                 constexpr int s = decltype(s_)::value;
-                a[s][k] = me[s] ? 1.0 : ng[s];
+                if constexpr (s == Sk)
+                    a[s][k] = p == Lk ? 1.0 : ng[s];
+                else
+                    a[s][k] = ng[s];
             });
         }
     });
@@ -285,21 +323,97 @@ __device__ __forceinline__ Dl<NX> dl_of(int k0, int N) {
     return d;
 }
 
-// rows of an n-column row-major FP64 block into slots (row r of the block at
-// src + r * n; rows clamped to the block, columns >= n zero)
-template <int NX, int RS, int NC>
-__device__ __forceinline__ void load_slots(const double *__restrict__ src, int n, int nrows, int p,
-                                           double (&a)[RS][NC]) {
-    static_for<0, RS>([&](auto s_) {
-        constexpr int s = decltype(s_)::value;
-        const int r = min(p + s * RowGeo<NX>::P, nrows - 1);
-        static_for<0, NC>([&](auto jc) {
-            constexpr int j = decltype(jc)::value;
-            a[s][j] = j < n ? src[(int64_t)r * n + j] : 0.0;
-        });
+// Global memory is only touched by these wave-wide copies of contiguous
+// ranges (consecutive lanes, consecutive elements); lanes read and write
+// their matrix rows in LDS.  A lane that loads or stores its own rows in
+// global memory touches a separate cache line per lane and instruction, and
+// the memory pipeline, not the arithmetic, then bounds the assembly.
+// The lane index, opaque to the compiler: a copy's element addresses are
+// formed where the copy runs instead of once for all copies (and held in
+// registers through every phase between them).
+__device__ __forceinline__ int lane_here() {
+    int l = threadIdx.x;
+    asm volatile("" : "+v"(l));
+    return l;
+}
+
+// Into LDS: n <= MAXN contiguous elements, every load of the range in flight
+// before the first write (source indices clamped to the range, so no load is
+// masked; lanes past the range write their copy to a spare slot).  The
+// copy's loads are issued where it is called, so only one staged range
+// occupies registers at a time.
+template <int MAXN, typename TD, typename TS>
+__device__ __forceinline__ void stage_in(TD *dst, const TS *__restrict__ src, int n, TD *spare) {
+    constexpr int B = (MAXN + kThreadsD - 1) / kThreadsD;
+    asm volatile("" ::: "memory");  // the loads of this copy stay here (not hoisted into earlier phases)
+    const int ln = lane_here();
+    TS v[B];
+    static_for<0, B>([&](auto ic) { v[decltype(ic)::value] = src[min(decltype(ic)::value * kThreadsD + ln, n - 1)]; });
+    static_for<0, B>([&](auto ic) {
+        const int e = decltype(ic)::value * kThreadsD + ln;
+        *(e < n ? dst + e : spare) = (TD)v[decltype(ic)::value];
     });
 }
 
+// Two ranges at once, the second made of blocks of NB elements sst apart at
+// the source (dense in LDS): one wait for both.
+template <int MAXA, int MAXB, int NB, typename T>
+__device__ __forceinline__ void stage_in2(T *da, const T *__restrict__ sa, int na, T *db, const T *__restrict__ sb,
+                                          int nb, int64_t sst, T *spare) {
+    constexpr int BA = (MAXA + kThreadsD - 1) / kThreadsD, BB = (MAXB + kThreadsD - 1) / kThreadsD;
+    asm volatile("" ::: "memory");
+    const int ln = lane_here();
+    T va[BA], vb[BB];
+    static_for<0, BA>([&](auto ic) { va[decltype(ic)::value] = sa[min(decltype(ic)::value * kThreadsD + ln, na - 1)]; });
+    static_for<0, BB>([&](auto ic) {
+        const int e = min(decltype(ic)::value * kThreadsD + ln, nb - 1);
+        vb[decltype(ic)::value] = sb[(e / NB) * sst + e % NB];
+    });
+    static_for<0, BA>([&](auto ic) {
+        const int e = decltype(ic)::value * kThreadsD + ln;
+        *(e < na ? da + e : spare) = va[decltype(ic)::value];
+    });
+    static_for<0, BB>([&](auto ic) {
+        const int e = decltype(ic)::value * kThreadsD + ln;
+        *(e < nb ? db + e : spare) = vb[decltype(ic)::value];
+    });
+}
+
+// Out of LDS: n <= MAXN contiguous elements, eight per lane at a time; only a
+// partial last chunk tests each element.
+template <int MAXN, typename TD, typename TS>
+__device__ __forceinline__ void copy_out(TD *__restrict__ dst, const TS *src, int n) {
+    constexpr int B = 8, CH = B * kThreadsD;
+    const int ln = lane_here();
+    static_for<0, (MAXN + CH - 1) / CH>([&](auto cc) {
+        constexpr int base = decltype(cc)::value * CH;
+        if (base + CH <= n) {
+            static_for<0, B>([&](auto ic) {
+                const int e = base + decltype(ic)::value * kThreadsD + ln;
+                dst[e] = (TD)src[e];
+            });
+        } else if (base < n) {
+            static_for<0, B>([&](auto ic) {
+                const int e = base + decltype(ic)::value * kThreadsD + ln;
+                if (e < n) dst[e] = (TD)src[e];
+            });
+        }
+    });
+}
+
+// rows p + s P of an LDS block of nrows x ld doubles into slots (rows clamped
+// to the block)
+template <int NX, int RS, int NC>
+__device__ __forceinline__ void lds_rows(const double *blk, int ld, int nrows, int p, double (&a)[RS][NC]) {
+    static_for<0, RS>([&](auto s_) {
+        constexpr int s = decltype(s_)::value;
+        const int r = min(p + s * RowGeo<NX>::P, nrows - 1);
+        static_for<0, NC>([&](auto jc) { a[s][decltype(jc)::value] = blk[r * ld + decltype(jc)::value]; });
+    });
+}
+
+// rows p + s P of a row-major NX x NX block in global memory into slots
+// (rows clamped), converted to FP64
 template <typename TM, int NX>
 __device__ __forceinline__ void load_slots_t(const TM *__restrict__ src, int p, double (&a)[RowGeo<NX>::R][NX]) {
     static_for<0, RowGeo<NX>::R>([&](auto s_) {
@@ -326,15 +440,72 @@ __device__ __forceinline__ void identity_outside(double (&a)[RS][NC], int p, boo
     });
 }
 
-template <int NX, int RS, int NC>
-__device__ __forceinline__ void store_slots(double *__restrict__ dst, int n, const Dl<NX> &d, const double (&a)[RS][NC]) {
+// this lane's real rows (r < n) into an LDS block of n x n elements
+template <int NX, typename T, int RS, int NC>
+__device__ __forceinline__ void rows_to_lds(T *blk, int n, bool live, int p, const double (&a)[RS][NC], double scale) {
     static_for<0, RS>([&](auto s_) {
         constexpr int s = decltype(s_)::value;
-        const int r = d.row(s);
-        if (d.act && r < n)
-            static_for<0, NC>([&](auto jc) {
+        const int r = p + s * RowGeo<NX>::P;
+        if (live && r < n)
+            static_for<0, NC>([&](auto jc) { blk[r * n + decltype(jc)::value] = (T)(scale * a[s][decltype(jc)::value]); });
+    });
+}
+
+// The same with the FP32 remainder v - (TM)v into a second block.
+template <int NX, typename TM>
+__device__ __forceinline__ void split_rows_to_lds(TM *hi, float *lo, bool live, int p,
+                                                  const double (&a)[RowGeo<NX>::R][NX], double scale) {
+    static_for<0, RowGeo<NX>::R>([&](auto s_) {
+        constexpr int s = decltype(s_)::value;
+        const int r = p + s * RowGeo<NX>::P;
+        if (live && r < NX)
+            static_for<0, NX>([&](auto jc) {
                 constexpr int j = decltype(jc)::value;
-                if (j < n) dst[(int64_t)r * n + j] = a[s][j];
+                const double v = scale * a[s][j];
+                const TM h = (TM)v;
+                hi[r * NX + j] = h;
+                if (lo) lo[r * NX + j] = (float)(v - (double)h);
+            });
+    });
+}
+
+// upper triangle (j >= r) of this lane's rows into packed LDS blocks
+template <int NX, typename TM>
+__device__ __forceinline__ void split_packed_to_lds(TM *hi, float *lo, bool live, int p,
+                                                    const double (&a)[RowGeo<NX>::R][NX]) {
+    static_for<0, RowGeo<NX>::R>([&](auto s_) {
+        constexpr int s = decltype(s_)::value;
+        const int r = p + s * RowGeo<NX>::P;
+        if (live && r < NX) {
+            const int base = packed_row(r, NX);
+            static_for<0, NX>([&](auto jc) {
+                constexpr int j = decltype(jc)::value;
+                if (j >= r) {
+                    const double v = a[s][j];
+                    const TM h = (TM)v;
+                    hi[base + j] = h;
+                    if (lo) lo[base + j] = (float)(v - (double)h);
+                }
+            });
+        }
+    });
+}
+
+// this lane's real rows (scale applied) into a row-major NX x NX block in
+// global memory, with the FP32 remainder under FP32 storage
+template <typename TM, int NX>
+__device__ __forceinline__ void store_split_slots(TM *__restrict__ hi, float *__restrict__ lo, const Dl<NX> &d,
+                                                  const double (&a)[RowGeo<NX>::R][NX], double scale) {
+    static_for<0, RowGeo<NX>::R>([&](auto s_) {
+        constexpr int s = decltype(s_)::value;
+        const int r = d.row(s);
+        if (d.has(s))
+            static_for<0, NX>([&](auto jc) {
+                constexpr int j = decltype(jc)::value;
+                const double v = scale * a[s][j];
+                const TM h = (TM)v;
+                hi[r * NX + j] = h;
+                if (lo) lo[r * NX + j] = (float)(v - (double)h);
             });
     });
 }
@@ -365,161 +536,184 @@ __device__ __forceinline__ void lower_from_upper(double (&a)[RowGeo<NX>::R][NX],
     wave_sync();
 }
 
-template <typename TM, int NX>
-__device__ __forceinline__ void store_split_slots(TM *__restrict__ hi, float *__restrict__ lo, const Dl<NX> &d,
-                                                  const double (&a)[RowGeo<NX>::R][NX], double scale) {
-    static_for<0, RowGeo<NX>::R>([&](auto s_) {
-        constexpr int s = decltype(s_)::value;
-        const int r = d.row(s);
-        if (d.has(s))
-            static_for<0, NX>([&](auto jc) {
-                constexpr int j = decltype(jc)::value;
-                const double v = scale * a[s][j];
-                const TM h = (TM)v;
-                hi[r * NX + j] = h;
-                if (lo) lo[r * NX + j] = (float)(v - (double)h);
-            });
-    });
-}
-
-template <typename TM, int NX>
-__device__ __forceinline__ void store_split_packed_slots(TM *__restrict__ hi, float *__restrict__ lo, const Dl<NX> &d,
-                                                         const double (&a)[RowGeo<NX>::R][NX]) {
-    static_for<0, RowGeo<NX>::R>([&](auto s_) {
-        constexpr int s = decltype(s_)::value;
-        const int r = d.row(s);
-        if (d.has(s)) {
-            const int base = packed_row(r, NX);
-            static_for<0, NX>([&](auto jc) {
-                constexpr int j = decltype(jc)::value;
-                if (j >= r) {
-                    const double v = a[s][j];
-                    const TM h = (TM)v;
-                    hi[base + j] = h;
-                    if (lo) lo[base + j] = (float)(v - (double)h);
-                }
-            });
-        }
-    });
-}
-
 }  // namespace
 
 // Q_k^-1 for every knot and R_k^-1 for k < N-1, into the FP64 workspaces
-// (nu = NX / 2).
+// (nu = NX / 2).  One wave, knots k0 .. k0 + 3.
 template <int NX>
 __global__ __launch_bounds__(kThreadsD) void k_bdpp_inv(BuildArgs a, const int2 *items) {
-    constexpr int R = RowGeo<NX>::R, P = RowGeo<NX>::P, NU = NX / 2, RU = (NU + P - 1) / P;
+    constexpr int R = RowGeo<NX>::R, P = RowGeo<NX>::P, NN = NX * NX, NU = NX / 2, UU = NU * NU;
+    constexpr int RU = (NU + P - 1) / P;
+    __shared__ __align__(16) double sm[kKnotsD * NN + 2];
+    double *spare = sm + kKnotsD * NN;  // sink of staged copies past their range
     const int2 it = items[blockIdx.x];
-    const int pr = it.x, N = a.N[pr];
-    const Dl<NX> d = dl_of<NX>(it.y, N);
-    const int kc = min(d.knot, N - 1);
-    const int64_t oq = a.off_nn[pr] + (int64_t)kc * NX * NX;
+    const int pr = it.x, N = a.N[pr], k0 = it.y, nk = min(kKnotsD, N - k0);
+    const Dl<NX> d = dl_of<NX>(k0, N);
+    const int gc = min(d.g, nk - 1);  // staged knot of this row (clamped)
+    const int64_t oq = a.off_nn[pr] + (int64_t)k0 * NN, orr = a.off_uu[pr] + (int64_t)k0 * UU;
+
+    stage_in<kKnotsD * NN>(sm, a.Q + oq, nk * NN, spare);
+    wave_sync();
     double q[R][NX];
-    load_slots<NX>(a.Q + oq, NX, NX, d.p, q);
+    lds_rows<NX>(sm + gc * NN, NX, NX, d.p, q);
     identity_outside<NX>(q, d.p, d.act, NX);
     bool ok = gj_dpp<P, R, NX>(q, d.p, NX);
-    store_slots<NX>(a.Qinv + oq, NX, d, q);
-    const int64_t orr = a.off_uu[pr] + (int64_t)kc * NU * NU;
+    wave_sync();
+    rows_to_lds<NX>(sm + d.g * NN, NX, d.act, d.p, q, 1.0);
+    wave_sync();
+    copy_out<kKnotsD * NN>(a.Qinv + oq, sm, nk * NN);
+    wave_sync();
+
     const bool live = d.act && d.knot < N - 1;
+    const int nr = min(kKnotsD, N - 1 - k0);  // knots with an R_k^-1
+    stage_in<kKnotsD * UU>(sm, a.R + orr, nk * UU, spare);
+    wave_sync();
     double r[RU][NU];
-    load_slots<NX>(a.R + orr, NU, NU, d.p, r);
+    lds_rows<NX>(sm + gc * UU, NU, NU, d.p, r);
     identity_outside<NX>(r, d.p, live, NU);
     const bool okr = gj_dpp<P, RU, NU>(r, d.p, NU);
     if (live) ok = ok && okr;
-    if (live) store_slots<NX>(a.Rinv + orr, NU, d, r);
+    wave_sync();
+    rows_to_lds<NX>(sm + d.g * UU, NU, live, d.p, r, 1.0);
+    wave_sync();
+    if (nr > 0) copy_out<kKnotsD * UU>(a.Rinv + orr, sm, nr * UU);
     if (d.act && !ok) atomicOr(a.status + pr, kNotSpd);
 }
 
 // D_k, L_k (storage type, FP32 remainder under FP32 storage) and then W_k
-// (SCALED: the scaled basis) or D_k^-1 (nu = NX / 2).
-// (at least two waves per SIMD: the operand loads are hoisted only as far as
-// 256 registers allow)
+// (SCALED: the scaled basis) or D_k^-1 (nu = NX / 2).  One wave, knots
+// k0 .. k0 + 3; at least two waves per SIMD (the compiler keeps the kernel
+// within 256 registers).
 template <typename TM, int NX, bool SCALED>
-__global__ __launch_bounds__(kThreadsD) __attribute__((amdgpu_waves_per_eu(2))) void k_bdpp_asm(BuildArgs a, const int2 *items) {
-    constexpr int R = RowGeo<NX>::R, P = RowGeo<NX>::P, NN = NX * NX, NU = NX / 2, nu = NU;
-    __shared__ __align__(16) double sm[kKnotsD * RowGeo<NX>::P * NX];
+__global__ __launch_bounds__(kThreadsD) __attribute__((amdgpu_waves_per_eu(2))) void k_bdpp_asm(BuildArgs a,
+                                                                                              const int2 *items) {
+    constexpr int R = RowGeo<NX>::R, P = RowGeo<NX>::P, NN = NX * NX, NU = NX / 2, UU = NU * NU, XU = NX * NU;
+    constexpr int RU = (NU + P - 1) / P, PK = NX * (NX + 1) / 2;
+    __shared__ __align__(16) double sm[kKnotsD * NN + 2];
+    double *spare = sm + kKnotsD * NN;  // sink of staged copies past their range
     const int2 it = items[blockIdx.x];
-    const int pr = it.x, N = a.N[pr];
-    const Dl<NX> d = dl_of<NX>(it.y, N);
-    double *buf = sm + d.g * RowGeo<NX>::P * NX;
+    const int pr = it.x, N = a.N[pr], k0 = it.y, nk = min(kKnotsD, N - k0);
+    const Dl<NX> d = dl_of<NX>(k0, N);
     const int k = d.knot, kc = min(k, N - 1), km = max(kc - 1, 0);
     const bool prev = d.act && k > 0;
-    const int bs = block_stride(NX, sizeof(TM)), bp = packed_stride(NX, sizeof(TM));
-    TM *blk = (TM *)a.B3 + a.off_b3[pr] + (int64_t)kc * (2 * bp + bs);  // D_k (packed), L_k, D_k^-1 (packed)
-    const int64_t ol = a.off_blk[pr] + (int64_t)kc * bs;
-    const int64_t od = a.off_pk[pr] + (int64_t)kc * bp;
+    // blocks k-1 of the knots k0 .. k0+nk-1 (knot 0 reads block 0 with a zero multiplier)
+    const int ks = max(k0 - 1, 0), ke = max(k0 + nk - 1, ks + 1), gm = km - ks, gc = kc - k0;
+    const int bs = block_stride(NX, sizeof(TM)), bp = packed_stride(NX, sizeof(TM)), kst = 2 * bp + bs;
+    TM *b3 = (TM *)a.B3 + a.off_b3[pr] + (int64_t)k0 * kst;  // per knot: D_k (packed), L_k, D_k^-1 (packed)
     int rw[R];
     static_for<0, R>([&](auto s_) { rw[decltype(s_)::value] = min(d.row(decltype(s_)::value), NX - 1); });
 
     // t = A_{k-1} Q_{k-1}^-1 (rows of Q^-1 broadcast)
     double m[R][NX], t[R][NX];
-    load_slots<NX>(a.Qinv + a.off_nn[pr] + (int64_t)km * NN, NX, NX, d.p, m);
+    stage_in<kKnotsD * NN>(sm, a.Qinv + a.off_nn[pr] + (int64_t)ks * NN, (ke - ks) * NN, spare);
+    wave_sync();
+    lds_rows<NX>(sm + gm * NN, NX, NX, d.p, m);
+    wave_sync();
+    stage_in<kKnotsD * NN>(sm, a.A + a.off_nn[pr] + (int64_t)ks * NN, (ke - ks) * NN, spare);
+    wave_sync();
+    int ro[R];  // this lane's rows in the staged block
+    static_for<0, R>([&](auto s_) { ro[decltype(s_)::value] = gm * NN + rw[decltype(s_)::value] * NX; });
     static_for<0, R>([&](auto s_) { static_for<0, NX>([&](auto jc) { t[decltype(s_)::value][decltype(jc)::value] = 0.0; }); });
-    const double *Ar = a.A + a.off_nn[pr] + (int64_t)km * NN;
-    static_for<0, NX>([&](auto lc) {
+    lds_steps<NX>(sm, ro, prev, [&](auto lc, const double (&x)[R]) {
         constexpr int l = decltype(lc)::value;
-        static_for<0, R>([&](auto s_) {
-            constexpr int s = decltype(s_)::value;
-            const double av = Ar[rw[s] * NX + l], x = prev ? av : 0.0;  // address valid for every lane
-            row_l<l % P, 0, NX>(t[s], m[l / P], x);
-        });
-    });
-    store_split_slots<TM, NX>(blk + bp, a.SLlo ? a.SLlo + ol : nullptr, d, t, -1.0);  // L_k = -t
-
-    // D_k = Q_k^-1 + A t^T (rows of t broadcast)
+        static_for<0, R>([&](auto s_) { row_l<l % P, 0, NX>(t[decltype(s_)::value], m[l / P], x[decltype(s_)::value]); });
+    }, [&](auto s_) { return t[decltype(s_)::value][NX - 1]; });
+    // D_k = A t^T (rows of t broadcast), + B u^T, + Q_k^-1 below
     double dk[R][NX];
-    load_slots<NX>(a.Qinv + a.off_nn[pr] + (int64_t)kc * NN, NX, NX, d.p, dk);
-    static_for<0, NX>([&](auto lc) {
+    static_for<0, R>([&](auto s_) { static_for<0, NX>([&](auto jc) { dk[decltype(s_)::value][decltype(jc)::value] = 0.0; }); });
+    lds_steps<NX>(sm, ro, prev, [&](auto lc, const double (&x)[R]) {
         constexpr int l = decltype(lc)::value;
-        static_for<0, R>([&](auto s_) {
-            constexpr int s = decltype(s_)::value;
-            const double av = Ar[rw[s] * NX + l], x = prev ? av : 0.0;  // address valid for every lane
-            row_t<P, l, 0, NX>(dk[s], t, x);
-        });
-    });
+        static_for<0, R>([&](auto s_) { row_t<P, l, 0, NX>(dk[decltype(s_)::value], t, x[decltype(s_)::value]); });
+    }, [&](auto s_) { return dk[decltype(s_)::value][NX - 1]; });
+    // L_k = -t
+    {
+        wave_sync();
+        TM *hi = (TM *)sm;
+        float *lo = sizeof(TM) == 4 && a.SLlo ? (float *)(hi + kKnotsD * NN) : nullptr;
+        split_rows_to_lds<NX, TM>(hi + d.g * NN, lo ? lo + d.g * NN : nullptr, d.act, d.p, t, -1.0);
+        wave_sync();
+        for (int g = 0; g < nk; ++g) {
+            copy_out<NN>(b3 + (int64_t)g * kst + bp, hi + g * NN, NN);
+            if (lo) copy_out<NN>(a.SLlo + a.off_blk[pr] + (int64_t)(k0 + g) * bs, lo + g * NN, NN);
+        }
+        wave_sync();
+    }
     // D_k += B u^T with u = B_{k-1} R_{k-1}^-1
     {
-        constexpr int RU = (NU + P - 1) / P;
+        double *Rb = sm, *Bb = sm + kKnotsD * UU;
+        stage_in<kKnotsD * UU>(Rb, a.Rinv + a.off_uu[pr] + (int64_t)ks * UU, (ke - ks) * UU, spare);
+        stage_in<kKnotsD * XU>(Bb, a.B + a.off_nu[pr] + (int64_t)ks * XU, (ke - ks) * XU, spare);
+        wave_sync();
         double ri[RU][NU], u[R][NU];
-        load_slots<NX>(a.Rinv + a.off_uu[pr] + (int64_t)km * nu * nu, nu, nu, d.p, ri);
+        lds_rows<NX>(Rb + gm * UU, NU, NU, d.p, ri);
+        // R_{N-1}^-1 is never formed: a one-knot problem's knot 0 (zero
+        // multiplier) must not read it
+        const bool rok = km < N - 1;
+        static_for<0, RU>([&](auto s_) {
+            static_for<0, NU>([&](auto jc) {
+                double &v = ri[decltype(s_)::value][decltype(jc)::value];
+                v = rok ? v : 0.0;
+            });
+        });
         static_for<0, R>([&](auto s_) { static_for<0, NU>([&](auto jc) { u[decltype(s_)::value][decltype(jc)::value] = 0.0; }); });
-        const double *Br = a.B + a.off_nu[pr] + (int64_t)km * NX * nu;
-        static_for<0, NU>([&](auto lc) {
+        int rb[R];
+        static_for<0, R>([&](auto s_) { rb[decltype(s_)::value] = gm * XU + rw[decltype(s_)::value] * NU; });
+        lds_steps<NU>(Bb, rb, prev, [&](auto lc, const double (&x)[R]) {
             constexpr int l = decltype(lc)::value;
-            static_for<0, R>([&](auto s_) {
-                    constexpr int s = decltype(s_)::value;
-                    const double bv = Br[rw[s] * nu + l], x = prev ? bv : 0.0;
-                    row_l<l % P, 0, NU>(u[s], ri[l / P], x);
-                });
-        });
-        static_for<0, NU>([&](auto lc) {
+            static_for<0, R>([&](auto s_) { row_l<l % P, 0, NU>(u[decltype(s_)::value], ri[l / P], x[decltype(s_)::value]); });
+        }, [&](auto s_) { return u[decltype(s_)::value][NU - 1]; });
+        lds_steps<NU>(Bb, rb, prev, [&](auto lc, const double (&x)[R]) {
             constexpr int l = decltype(lc)::value;
-            static_for<0, R>([&](auto s_) {
-                    constexpr int s = decltype(s_)::value;
-                    const double bv = Br[rw[s] * nu + l], x = prev ? bv : 0.0;
-                    row_t<P, l, 0, NX>(dk[s], u, x);
-                });
-        });
+            static_for<0, R>([&](auto s_) { row_t<P, l, 0, NX>(dk[decltype(s_)::value], u, x[decltype(s_)::value]); });
+        }, [&](auto s_) { return dk[decltype(s_)::value][NX - 1]; });
+        wave_sync();
     }
-    lower_from_upper<NX>(dk, d.p, buf);
-    store_split_packed_slots<TM, NX>(blk, a.SDlo ? a.SDlo + od : nullptr, d, dk);
+    // D_k += Q_k^-1
+    stage_in<kKnotsD * NN>(sm, a.Qinv + a.off_nn[pr] + (int64_t)k0 * NN, nk * NN, spare);
+    wave_sync();
+    static_for<0, R>([&](auto s_) {
+        constexpr int s = decltype(s_)::value;
+        static_for<0, NX>([&](auto jc) {
+            constexpr int j = decltype(jc)::value;
+            dk[s][j] += sm[gc * NN + rw[s] * NX + j];
+        });
+    });
+    lower_from_upper<NX>(dk, d.p, sm + d.g * P * NX);
+    // D_k (packed upper triangle)
+    {
+        TM *hi = (TM *)sm;
+        float *lo = sizeof(TM) == 4 && a.SDlo ? (float *)(hi + kKnotsD * PK) : nullptr;
+        split_packed_to_lds<NX, TM>(hi + d.g * PK, lo ? lo + d.g * PK : nullptr, d.act, d.p, dk);
+        wave_sync();
+        for (int g = 0; g < nk; ++g) {
+            copy_out<PK>(b3 + (int64_t)g * kst, hi + g * PK, PK);
+            if (lo) copy_out<PK>(a.SDlo + a.off_pk[pr] + (int64_t)(k0 + g) * bp, lo + g * PK, PK);
+        }
+        wave_sync();
+    }
     bool ok;
     if constexpr (SCALED) {
         // scaled basis: W_k = C_k^-1, stored full (zeros above the diagonal)
         ok = lower_inverse_dpp<P, R, NX>(dk, d.p);
-        store_split_slots<TM, NX>((TM *)a.Zs + ol, (float *)nullptr, d, dk, 1.0);
+        TM *w = (TM *)sm;
+        split_rows_to_lds<NX, TM>(w + d.g * NN, nullptr, d.act, d.p, dk, 1.0);
+        wave_sync();
+        for (int g = 0; g < nk; ++g) copy_out<NN>((TM *)a.Zs + a.off_blk[pr] + (int64_t)(k0 + g) * bs, w + g * NN, NN);
     } else {
         ok = gj_dpp<P, R, NX>(dk, d.p, NX);
-        lower_from_upper<NX>(dk, d.p, buf);
-        store_split_packed_slots<TM, NX>(blk + bp + bs, (float *)nullptr, d, dk);
+        TM *di = (TM *)sm;
+        split_packed_to_lds<NX, TM>(di + d.g * PK, nullptr, d.act, d.p, dk);
+        wave_sync();
+        for (int g = 0; g < nk; ++g) copy_out<PK>(b3 + (int64_t)g * kst + bp + bs, di + g * PK, PK);
     }
     if (d.act && !ok) atomicOr(a.status + pr, kNotSpd);
 }
 
 // Oh_k = W_k L_k W_{k-1}^T (k >= 1, Oh_0 = 0) in FP64 from the stored W and
 // L_k (storage type): X = L_k W_{k-1}^T with the rows of W_{k-1} broadcast,
-// then W_k X with the rows of X broadcast.
+// then W_k X with the rows of X broadcast.  Each lane reads its own rows from
+// global memory: few loads per knot, all issued at the start, which here
+// beats staging the blocks through LDS.
 template <typename TM, int NX>
 __global__ __launch_bounds__(kThreadsD) void k_bdpp_ohat(BuildArgs a, const int2 *items) {
     constexpr int R = RowGeo<NX>::R, P = RowGeo<NX>::P;
