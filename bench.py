@@ -34,8 +34,8 @@ MEASURED_TRAFFIC = {
     # + WRITE_SIZE x 1.0 (KiB, the factors a plain 1 GiB copy reads), summed over the three k_pcg3 instances (nx 6,
     # 14, 26) of one solve at 256 threads / 48 336 B
     ("batch4096_ragged", "sym", "fp32_refine64", 0):
-        ("dc4d4fa0befd4c2a", ((8419609.06 + 2956410.12 + 574623.0) * 2.0
-                              + (2916238.34 + 1658391.94 + 709916.97) * 1.0) * 1024),
+        ("60fcb408fc2f8283", ((8423793.8125 + 2959781.6875 + 564687.1875) * 2.0
+                              + (2921136.96875 + 1659202.65625 + 713284.90625) * 1.0) * 1024),
 }
 
 
