@@ -1,8 +1,8 @@
 // Assembly of S and the scaled basis for the compiled state sizes up to 32,
 // with every broadcast operand folded into the FP64 multiply-add.
 //
-// Mapping: one knot per 16-lane row of a wavefront (4 knots per wave, 8 per
-// 128-thread workgroup).  A matrix is held R = 1 (nx <= 16) or R = 2 rows
+// Mapping: one knot per 16-lane row of a wavefront, one wave (4 knots) per
+// workgroup and work item.  A matrix is held R = 1 (nx <= 16) or R = 2 rows
 // per lane: lane p < P = ceil(nx / R) of the knot's row holds matrix rows p
 // and p + P in its slots 0 and 1.  Row l of such a matrix sits in lane l % P,
 // slot l / P; the FP64 multiply-add with DPP row_newbcast:(l % P) reads that
@@ -22,6 +22,13 @@
 // step (the row stays a fixed multiple of the usual one in between), and D_k
 // is made symmetric by copying its upper triangle onto the lower one (the
 // upper triangle is what is stored).
+//
+// Memory: the inverse and assembly kernels move blocks between HBM and LDS
+// only in wave-wide copies of contiguous ranges, and lanes read their rows
+// from LDS (a lane that loads or stores its own rows touches a separate cache
+// line per lane and instruction, which bounded an earlier version in the
+// memory pipeline); the Oh kernel, with few loads per knot, reads its rows
+// directly.
 //
 // A DPP read of a VGPR needs two wait states after a VALU write to it, which
 // the compiler cannot see inside the asm: every block of multiply-adds starts

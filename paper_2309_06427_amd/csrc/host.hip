@@ -749,14 +749,31 @@ ssp_status ssp_build(ssp_batch *b, ssp_precon pc, ssp_precision prec, const doub
         a.Zs = b->Zs;
         a.OH = b->OH;
     }
-    for (int c = 0; c < ssp::kBuildClasses; ++c)
-        SSP_HIP(ssp::launch_build_class(c, a, b->ditems + b->item_off[c], b->item_off[c + 1] - b->item_off[c], fp32,
-                                        s));
+    // The classes are independent (disjoint problems): each class's chain (inverse, assembly, Oh) runs on the
+    // internal stream of its state size, forked from and joined back into the caller's stream, so the small
+    // classes' launches overlap the large ones' instead of queueing behind them.
+    const int ng = (int)b->groups.size();
+    const bool fork = ng > 1 && (int)b->gstreams.size() == ng;
+    if (fork) {
+        SSP_HIP(hipEventRecord(b->gevents[ng], s));
+        for (int i = 0; i < ng; ++i) SSP_HIP(hipStreamWaitEvent(b->gstreams[i], b->gevents[ng], 0));
+    }
+    for (int c = 0; c < ssp::kBuildClasses; ++c) {
+        const int n = b->item_off[c + 1] - b->item_off[c];
+        if (n == 0) continue;
+        hipStream_t cs = s;
+        if (fork)
+            for (int i = 0; i < ng; ++i)
+                if (b->groups[i].nx == ssp::kBuildSizes[c]) cs = b->gstreams[i];
+        SSP_HIP(ssp::launch_build_class(c, a, b->ditems + b->item_off[c], n, fp32, cs));
+        if (scaled) SSP_HIP(ssp::launch_build_ohat(c, a, b->ditems + b->item_off[c], n, fp32, cs));
+    }
     SSP_HIP(ssp::launch_build(a, b->n_generic, b->gen_nx_max, b->gen_nu_max, fp32, s));
-    if (scaled)
-        for (int c = 0; c < ssp::kBuildClasses; ++c)
-            SSP_HIP(ssp::launch_build_ohat(c, a, b->ditems + b->item_off[c], b->item_off[c + 1] - b->item_off[c],
-                                           fp32, s));
+    if (fork)
+        for (int i = 0; i < ng; ++i) {
+            SSP_HIP(hipEventRecord(b->gevents[i], b->gstreams[i]));
+            SSP_HIP(hipStreamWaitEvent(s, b->gevents[i], 0));
+        }
     if (pc == SSP_PC_SCALAR_JACOBI) SSP_HIP(ssp::launch_jacobi_diag(a, b->knots, fp32, s));
     b->built = true;
     return SSP_OK;
