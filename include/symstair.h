@@ -126,7 +126,11 @@ ssp_status ssp_layout(const ssp_batch *b, int64_t *off_nn, int64_t *off_nu, int6
  * one nx x nx block per knot (D_k^-1 = W_k^T W_k is formed when ssp_export
  * asks for it).  The
  * polynomial preconditioners SSP_PC_NEUMANN2/3 exist only there, and need
- * every problem's nx in {6, 14, 26, 36} with nu <= nx (else SSP_ERR_ARG). */
+ * every problem's nx in {6, 14, 26, 36} with nu <= nx (else SSP_ERR_ARG).
+ * With several state sizes in the batch the build's launches run on the
+ * handle's internal streams, forked from `stream` and joined back into it:
+ * the call is ordered on `stream` like a single launch (and can be captured
+ * into a graph with it). */
 ssp_status ssp_build(ssp_batch *b, ssp_precon pc, ssp_precision prec, const double *A,
                      const double *B, const double *Q, const double *R, int32_t *prob_status,
                      void *stream);
@@ -173,7 +177,9 @@ ssp_status ssp_build_from_blocks(ssp_batch *b, ssp_precon pc, ssp_precision prec
  * preconditioner it also replaces it by block-Jacobi for the rest of the
  * solve (SSP_P_PC_FALLBACK, with a fresh budget of 5 refinement steps), and
  * under block-Jacobi SSP_P_BREAKDOWN is reported if the next FP64 residual
- * is not smaller. */
+ * is not smaller.  With several state sizes in the batch the solve runs one
+ * launch per state size on the handle's internal streams, forked from
+ * `stream` and joined back into it (ordered on `stream` like one launch). */
 ssp_status ssp_solve(ssp_batch *b, double rel_tol, int32_t max_iter, const double *gamma,
                      double *lambda, int use_lambda0, int32_t *iters, double *relres,
                      int32_t *prob_status, void *stream);
@@ -367,15 +373,17 @@ ssp_status ssp_set_reduction_fp64(ssp_batch *b, int32_t on);
  * chose the scaled solve.  SSP_ERR_ARG if some state size of the batch gets
  * no pipeline step from the budget. */
 ssp_status ssp_set_scaled_mapping(ssp_batch *b, int32_t threads, int32_t lds_bytes);
-/* The scaled solve's mapping: threads, LDS bytes, workgroups of the
- * persistent grid on this device (min(resident workgroups, nprob)) and the
- * autotuner's best time in ms (0 if not tuned); any pointer may be NULL. */
+/* The scaled solve's mapping: threads, LDS bytes, workgroups of each
+ * persistent grid on this device (min(resident workgroups, nprob); one grid
+ * runs per state size of the batch) and the autotuner's best time in ms (0 if
+ * not tuned); any pointer may be NULL. */
 ssp_status ssp_get_scaled_mapping(const ssp_batch *b, int32_t *threads, int32_t *lds_bytes, int32_t *grid,
                                   float *tuned_ms);
 
 /* The kernel the last ssp_solve (or ssp_autotune) of this batch enqueued:
  * 1 explicit two-sweep, 2 fused (one workgroup per problem), 3 cooperative
- * (one problem over the whole grid), 4 scaled (persistent grid); 0 before
+ * (one problem over the whole grid), 4 scaled (a persistent grid per state
+ * size); 0 before
  * any solve.  *W and *G (may be
  * NULL) receive the cooperative plan: own knots per workgroup and
  * workgroups (0 for the other kernels). */
