@@ -362,30 +362,6 @@ __device__ __forceinline__ void stage_in(TD *dst, const TS *__restrict__ src, in
     });
 }
 
-// Two ranges at once, the second made of blocks of NB elements sst apart at
-// the source (dense in LDS): one wait for both.
-template <int MAXA, int MAXB, int NB, typename T>
-__device__ __forceinline__ void stage_in2(T *da, const T *__restrict__ sa, int na, T *db, const T *__restrict__ sb,
-                                          int nb, int64_t sst, T *spare) {
-    constexpr int BA = (MAXA + kThreadsD - 1) / kThreadsD, BB = (MAXB + kThreadsD - 1) / kThreadsD;
-    asm volatile("" ::: "memory");
-    const int ln = lane_here();
-    T va[BA], vb[BB];
-    static_for<0, BA>([&](auto ic) { va[decltype(ic)::value] = sa[min(decltype(ic)::value * kThreadsD + ln, na - 1)]; });
-    static_for<0, BB>([&](auto ic) {
-        const int e = min(decltype(ic)::value * kThreadsD + ln, nb - 1);
-        vb[decltype(ic)::value] = sb[(e / NB) * sst + e % NB];
-    });
-    static_for<0, BA>([&](auto ic) {
-        const int e = decltype(ic)::value * kThreadsD + ln;
-        *(e < na ? da + e : spare) = va[decltype(ic)::value];
-    });
-    static_for<0, BB>([&](auto ic) {
-        const int e = decltype(ic)::value * kThreadsD + ln;
-        *(e < nb ? db + e : spare) = vb[decltype(ic)::value];
-    });
-}
-
 // Out of LDS: n <= MAXN contiguous elements, eight per lane at a time; only a
 // partial last chunk tests each element.
 template <int MAXN, typename TD, typename TS>
