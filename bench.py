@@ -34,8 +34,8 @@ MEASURED_TRAFFIC = {
     # + WRITE_SIZE x 1.0 (KiB, the factors a plain 1 GiB copy reads), summed over the three k_pcg3 instances (nx 6,
     # 14, 26) of one solve at 256 threads / 48 336 B
     ("batch4096_ragged", "sym", "fp32_refine64", 0):
-        ("60fcb408fc2f8283", ((8423793.8125 + 2959781.6875 + 564687.1875) * 2.0
-                              + (2921136.96875 + 1659202.65625 + 713284.90625) * 1.0) * 1024),
+        ("2246ba680425411d", ((8416569.1875 + 2961907.0 + 570620.9375) * 2.0
+                              + (2917602.96875 + 1656755.53125 + 710684.875) * 1.0) * 1024),
 }
 
 
