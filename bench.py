@@ -118,6 +118,21 @@ def scaled_bytes(b, iters, outer, precision: str):
     return blk, vec
 
 
+def kkt_bytes(b):
+    """Bytes the two KKT calls must move per problem, all FP64: each knot
+    block they read once (Q_k^-1 on N knots; A_k, B_k and R_k^-1 on the
+    N - 1 knots that have a successor) and each vector element once.
+    Right-hand side: q, c in, r of N - 1 knots in, gamma out.  Recovery:
+    q, lambda in, r of N - 1 knots in, dx and du out."""
+    N = b.N.astype(np.float64)
+    nx = b.nx.astype(np.float64)
+    nu = b.nu.astype(np.float64)
+    blocks = 8.0 * (N * nx * nx + (N - 1) * (nx * nx + nx * nu + nu * nu))
+    rhs = blocks + 8.0 * (3 * N * nx + (N - 1) * nu)
+    rec = blocks + 8.0 * (3 * N * nx + (N - 1) * nu + N * nu)
+    return rhs, rec
+
+
 def load_nets(b, warm: str) -> list:
     """Trained warm-start networks for the state sizes in the batch."""
     from paper_2309_06427_amd.train_warmstart import weights_path
@@ -186,7 +201,8 @@ def main() -> int:
                          "3 cooperative")
     ap.add_argument("--cpu-sample", type=int, default=512)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-compare", action="store_true")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the per-preconditioner runs and the KKT step timing")
     ap.add_argument("--warm", default="auto", choices=["auto", "zero", "learned"],
                     help="learned: also run the step with the trained warm-start networks "
                          "(auto: when their weights are present); the analytic start runs unless zero")
@@ -390,17 +406,65 @@ def main() -> int:
     achieved = bytes_solve / solve_avg_s / 1e9
     value = b.P * args.steps / head_wall
 
+    def timed(fn, reps):
+        """Mean HIP-event time of fn() on the stream, ms, after one untimed call."""
+        fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
     compare = None
     if not args.no_compare:
+        # every preconditioner on the same batch and precision: build and
+        # solve timed apart, the solve's algorithmic bytes for the kernel it ran
         compare = {}
         for pc in ("jacobi", "bj", "add", "sym", "poly3"):
-            db.build(pc, precision)
-            db.solve(tol)
+            build_ms = timed(lambda: db.build(pc, precision), 3)
+            solve_ms = timed(lambda: db.solve(tol), 3)
             r = db.results()
+            pk = db.solver.solve_kernel()[0]
+            by = float(algorithmic_bytes(b, r["iters"], r["outer"], pc, precision, pk).sum())
             compare[pc] = {"iters_mean": round(float(r["iters"].mean()), 3),
                            "outer_mean": round(float(r["outer"].mean()), 3),
                            "max_relres": float(r["relres"].max()),
-                           "pc_fallbacks": int(((r["status"] & 16) != 0).sum())}
+                           "pc_fallbacks": int(((r["status"] & 16) != 0).sum()),
+                           "kernel": {1: "explicit", 2: "fused", 3: "cooperative", 4: "scaled"}[pk],
+                           "build_ms": round(build_ms, 4),
+                           "solve_ms": round(solve_ms, 4),
+                           "solves_per_s": round(b.P / ((build_ms + solve_ms) / 1e3), 2),
+                           "solve_algorithmic_bytes": by,
+                           "solve_GBps": round(by / solve_ms / 1e6, 2),
+                           "solve_frac": round(by / solve_ms / 1e6 / HBM_PEAK_GBS, 4)}
+
+    kkt = None
+    if not args.no_compare:
+        # the KKT step around the solve (right-hand side, then recovery) on
+        # the same batch after a build with the headline preconditioner;
+        # gamma is restored afterwards
+        gamma0 = db.gamma.clone()
+        db.build(args.pc, precision)
+        gen = torch.Generator(device="cpu").manual_seed(11)
+        nu_rows = int((b.N.astype(np.int64) * b.nu).sum())
+        q = torch.randn(int(b.off_v[-1]), dtype=torch.float64, generator=gen).cuda()
+        c = torch.randn(int(b.off_v[-1]), dtype=torch.float64, generator=gen).cuda()
+        r = torch.randn(max(nu_rows, 1), dtype=torch.float64, generator=gen).cuda()
+        rhs_ms = timed(lambda: db.kkt_rhs(q, r, c), 10)
+        db.solve(tol)
+        dx = torch.empty_like(db.gamma)
+        du = torch.empty(max(nu_rows, 1), dtype=torch.float64, device=dx.device)
+        rec_ms = timed(lambda: db.solver.kkt_recover(db.A, db.B, q, r, db.lam, dx, du), 10)
+        rb, cb = (float(x.sum()) for x in kkt_bytes(b))
+        kkt = {"rhs_ms": round(rhs_ms, 4), "recover_ms": round(rec_ms, 4),
+               "rhs_algorithmic_bytes": rb, "recover_algorithmic_bytes": cb,
+               "rhs_GBps": round(rb / rhs_ms / 1e6, 2), "recover_GBps": round(cb / rec_ms / 1e6, 2),
+               "rhs_frac": round(rb / rhs_ms / 1e6 / HBM_PEAK_GBS, 4),
+               "recover_frac": round(cb / rec_ms / 1e6 / HBM_PEAK_GBS, 4)}
+        db.gamma.copy_(gamma0)
+        del gamma0, q, c, r, dx, du
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -466,6 +530,7 @@ def main() -> int:
             "solve_algorithmic_bytes": bytes_solve,
             "solve_bytes_split": split,
             "compare": compare,
+            "kkt": kkt,
         },
         "roofline": {
             "kernel": {1: "k_pcg", 2: "k_pcg2", 3: "k_coop", 4: "k_pcg3"}[kern],

@@ -563,6 +563,17 @@ ssp_status ssp_batch_create(int32_t nprob, const int32_t *N, const int32_t *nx, 
         b->gen_nu_max = std::max(b->gen_nu_max, (int)nu[p]);
     }
     b->n_generic = (int64_t)generic.size();
+    // KKT work items, one list per kernel class, the generic class last
+    std::vector<int2> kkt;
+    kkt.reserve((size_t)b->knots);
+    for (int c = 0; c <= ssp::kKktClasses; ++c) {
+        b->kkt_off[c] = (int64_t)kkt.size();
+        const int want = c < ssp::kKktClasses ? c : -1, per = ssp::kkt_knots_per_item(want);
+        for (int p = 0; p < nprob; ++p)
+            if (ssp::kkt_class_of(nx[p], nu[p]) == want)
+                for (int k0 = 0; k0 < N[p]; k0 += per) kkt.push_back(make_int2(p, k0));
+    }
+    b->kkt_off[ssp::kKktClasses + 1] = (int64_t)kkt.size();
 
     DevGuard g(device);
     ssp_status rc = SSP_OK;
@@ -603,6 +614,7 @@ ssp_status ssp_batch_create(int32_t nprob, const int32_t *N, const int32_t *nx, 
     up(&b->dknot, knot_prob.data(), knot_prob.size());
     up(&b->ditems, items.data(), items.size());
     up(&b->dgeneric, generic.data(), generic.size());
+    up(&b->dkkt, kkt.data(), kkt.size());
     up(&b->doff_nn, b->off_nn.data(), nprob + 1);
     up(&b->doff_nu, b->off_nu.data(), nprob + 1);
     up(&b->doff_uu, b->off_uu.data(), nprob + 1);
@@ -659,7 +671,7 @@ ssp_status ssp_batch_destroy(ssp_batch *b) {
         for (hipEvent_t ev : b->gevents) (void)hipEventDestroy(ev);
         if (b->dgorder) (void)hipFree(b->dgorder);
         for (void *p : {(void *)b->dN, (void *)b->dnx, (void *)b->dnu, (void *)b->dorder, (void *)b->dknot,
-                        (void *)b->ditems, (void *)b->dgeneric, (void *)b->doff_nn, (void *)b->doff_nu, (void *)b->doff_uu, (void *)b->doff_v,
+                        (void *)b->ditems, (void *)b->dgeneric, (void *)b->dkkt, (void *)b->doff_nn, (void *)b->doff_nu, (void *)b->doff_uu, (void *)b->doff_v,
                         (void *)b->dkoff, (void *)b->doff_blk32, (void *)b->doff_blk64, (void *)b->doff_b3_32, (void *)b->doff_b3_64,
                         (void *)b->doff_pk32, (void *)b->dbar, (void *)b->drec, (void *)b->dwtag, (void *)b->Qinv, (void *)b->Rinv,
                         (void *)b->r64, (void *)b->douter, (void *)b->dqueue, (void *)b->doff_u})
@@ -1048,7 +1060,10 @@ ssp_status ssp_kkt_rhs(ssp_batch *b, const double *A, const double *B, const dou
     ssp::BuildArgs a = build_args(b);
     a.A = A;
     a.B = B;
-    SSP_HIP(ssp::launch_kkt_rhs(a, b->doff_v, b->doff_u, q, r, c, gamma, b->knots, (hipStream_t)stream));
+    for (int cls = 0; cls <= ssp::kKktClasses; ++cls)
+        SSP_HIP(ssp::launch_kkt_rhs(cls < ssp::kKktClasses ? cls : -1, a, b->dkkt + b->kkt_off[cls],
+                                    b->kkt_off[cls + 1] - b->kkt_off[cls], b->doff_v, b->doff_u, q, r, c, gamma,
+                                    (hipStream_t)stream));
     return SSP_OK;
 }
 
@@ -1064,7 +1079,10 @@ ssp_status ssp_kkt_recover(ssp_batch *b, const double *A, const double *B, const
     ssp::BuildArgs a = build_args(b);
     a.A = A;
     a.B = B;
-    SSP_HIP(ssp::launch_kkt_recover(a, b->doff_v, b->doff_u, q, r, lambda, dx, du, b->knots, (hipStream_t)stream));
+    for (int cls = 0; cls <= ssp::kKktClasses; ++cls)
+        SSP_HIP(ssp::launch_kkt_recover(cls < ssp::kKktClasses ? cls : -1, a, b->dkkt + b->kkt_off[cls],
+                                        b->kkt_off[cls + 1] - b->kkt_off[cls], b->doff_v, b->doff_u, q, r, lambda, dx,
+                                        du, (hipStream_t)stream));
     return SSP_OK;
 }
 

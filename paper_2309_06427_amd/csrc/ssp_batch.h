@@ -71,6 +71,10 @@ struct ssp_batch {
     int2 *ditems = nullptr;
     int32_t *dgeneric = nullptr;
     int item_off[ssp::kBuildClasses + 1] = {};
+    // KKT step: work items (problem, first knot) by kernel class
+    // (ssp::kkt_class_of), the generic class last, at dkkt + kkt_off[c]
+    int2 *dkkt = nullptr;
+    int64_t kkt_off[ssp::kKktClasses + 2] = {};
     int64_t n_generic = 0;
     int gen_nx_max = 1, gen_nu_max = 0;
     // global knot lists per state size (built on first use by the warm start)

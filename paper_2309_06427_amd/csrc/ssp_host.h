@@ -103,15 +103,24 @@ hipError_t launch_export(const BuildArgs &a, int which, const void *hi, const fl
                          int64_t knots, hipStream_t s);
 hipError_t launch_fill_i32(int32_t *dst, int32_t v, int64_t n, hipStream_t s);
 
-// KKT step around the solve (FP64, every knot of the batch): gamma from q,
-// r, c, and dx, du from lambda, with the Q^-1, R^-1 of the last build
-// (a.Qinv, a.Rinv) and the caller's A, B (a.A, a.B).  Vector offsets:
-// off_v (state, N nx per problem), off_u (control, N nu per problem).
-hipError_t launch_kkt_rhs(const BuildArgs &a, const int64_t *off_v, const int64_t *off_u, const double *q,
-                          const double *r, const double *c, double *gamma, int64_t knots, hipStream_t s);
-hipError_t launch_kkt_recover(const BuildArgs &a, const int64_t *off_v, const int64_t *off_u, const double *q,
-                              const double *r, const double *lam, double *dx, double *du, int64_t knots,
-                              hipStream_t s);
+// KKT step around the solve (FP64): gamma from q, r, c, and dx, du from
+// lambda, with the Q^-1, R^-1 of the last build (a.Qinv, a.Rinv) and the
+// caller's A, B (a.A, a.B), for the n work items (problem p, first knot k0)
+// of `items`: the knots k0 .. min(k0 + kkt_knots_per_item(cls), N) - 1.
+// Vector offsets: off_v (state, N nx per problem), off_u (control, N nu
+// per problem).  Class kkt_class_of(nx, nu) of every item's problem picks
+// the kernel compiled for state size kKktSizes[cls] (nu <= nx / 2), -1 the
+// generic one (any nx, nu <= 64; one knot per item).
+constexpr int kKktClasses = 3;
+extern const int kKktSizes[kKktClasses];
+int kkt_class_of(int nx, int nu);
+int kkt_knots_per_item(int cls);
+hipError_t launch_kkt_rhs(int cls, const BuildArgs &a, const int2 *list, int64_t n, const int64_t *off_v,
+                          const int64_t *off_u, const double *q, const double *r, const double *c, double *gamma,
+                          hipStream_t s);
+hipError_t launch_kkt_recover(int cls, const BuildArgs &a, const int2 *list, int64_t n, const int64_t *off_v,
+                              const int64_t *off_u, const double *q, const double *r, const double *lam, double *dx,
+                              double *du, hipStream_t s);
 hipError_t launch_fill_f64(double *dst, double v, int64_t n, hipStream_t s);
 
 // Explicit two-sweep PCG (stored Phi^-1 blocks).

@@ -47,3 +47,39 @@ def test_one_json_line_with_the_contract_keys(monkeypatch, capsys):
     assert 0 < roof["frac"] < 1
     cpu = d["cpu_baseline"]
     assert cpu["kind"] == "oracle" and cpu["value"] > 0 and cpu["cores"] >= 1
+
+
+def test_kkt_bytes_count_each_block_and_vector_once(monkeypatch):
+    """Three knots, nx = 2, nu = 1, counted by hand: Q^-1 on 3 knots (12
+    elements), A, B, R^-1 on the 2 knots with a successor (2 x (4 + 2 + 1));
+    right-hand side q, c, gamma (18) and r of 2 knots; recovery q, lambda, dx
+    (18), r of 2 knots and du (3)."""
+    if ROOT not in sys.path:
+        monkeypatch.syspath_prepend(ROOT)
+    import numpy as np
+    import bench
+    from paper_2309_06427_amd import inputs
+    b = inputs.pack([inputs.draw_problem(np.random.default_rng(0), 3, 2, 1)])
+    rhs, rec = bench.kkt_bytes(b)
+    assert rhs.tolist() == [8.0 * (12 + 14 + 18 + 2)]
+    assert rec.tolist() == [8.0 * (12 + 14 + 18 + 2 + 3)]
+
+
+@pytest.mark.gpu
+def test_compare_and_kkt_timings_are_reported(monkeypatch, capsys):
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    rc = _run(monkeypatch, "--workload", "single_n50_nx14", "--steps", "2", "--warmup", "1", "--warm", "zero",
+              "--no-cpu-baseline", "--no-graph")
+    assert rc == 0
+    d = json.loads([l for l in capsys.readouterr().out.splitlines() if l.strip()][0])
+    cmp = d["detail"]["compare"]
+    assert set(cmp) == {"jacobi", "bj", "add", "sym", "poly3"}
+    for pc, c in cmp.items():
+        assert c["solve_ms"] > 0 and c["build_ms"] > 0 and c["solve_algorithmic_bytes"] > 0, pc
+        assert 0 < c["solve_frac"] < 1, pc
+    kkt = d["detail"]["kkt"]
+    assert kkt["rhs_ms"] > 0 and kkt["recover_ms"] > 0
+    assert 0 < kkt["rhs_frac"] < 1 and 0 < kkt["recover_frac"] < 1
+    assert d["valid"]

@@ -25,10 +25,14 @@ def _need_gpu():
 
 
 def mixed_batch(seed):
-    """Ragged shapes incl. N = 1, nu = 0, nx = 1 and nx = 64 (the largest state size)."""
+    """Ragged shapes incl. N = 1, nu = 0, nx = 1 and nx = 64 (the largest state
+    size); nx = 6, 14, 26 with nu <= nx / 2 run the staged kernels (among them
+    N = 1, nu = 0, and horizons that span several of their strips of 64, 32
+    and 8 knots, with ragged ends), the other shapes the generic ones."""
     rng = np.random.default_rng(seed)
     shapes = [(1, 6, 3), (2, 4, 2), (17, 14, 7), (33, 26, 13), (9, 36, 12), (5, 1, 0), (12, 5, 0),
-              (3, 64, 16), (40, 6, 3), (64, 14, 1)]
+              (3, 64, 16), (40, 6, 3), (64, 14, 1), (1, 26, 13), (4, 14, 0), (7, 26, 2), (5, 26, 20),
+              (70, 6, 2), (131, 6, 3)]
     probs = [inputs.draw_problem(rng, N, nx, nu, "wishart", 1e4) for N, nx, nu in shapes]
     return inputs.pack(probs)
 
