@@ -34,15 +34,25 @@ MEASURED_TRAFFIC = {
     # + WRITE_SIZE x 1.0 (KiB, the factors a plain 1 GiB copy reads), summed over the three k_pcg3 instances (nx 6,
     # 14, 26) of one solve at 256 threads / 48 336 B
     ("batch4096_ragged", "sym", "fp32_refine64", 0):
-        ("2246ba680425411d", ((8416569.1875 + 2961907.0 + 570620.9375) * 2.0
-                              + (2917602.96875 + 1656755.53125 + 710684.875) * 1.0) * 1024),
+        ("2cb44bcd97f48d67", ((8416100.4375 + 2957751.75 + 571463.5625) * 2.0
+                              + (2917660.28125 + 1657787.09375 + 711501.4375) * 1.0) * 1024),
+}
+
+# The KKT step's HBM bytes per call, the same counters and factors, summed
+# over the kernels of the three state sizes (nx 26, 14, 6): (sources
+# sha256[:16], right-hand side bytes, recovery bytes)
+KKT_SOURCES = ("kkt.hip", "ssp_host.h", "host.hip")
+MEASURED_KKT_TRAFFIC = {
+    "batch4096_ragged": ("8419c7df4d045c8e",
+                         ((1421701.1 + 440623.3 + 89225.6) * 2.0 + (38556.5 + 21593.4 + 9357.2) * 1.0) * 1024,
+                         ((1522958.6 + 465590.4 + 93053.0) * 2.0 + (65205.9 + 34264.3 + 14282.9) * 1.0) * 1024),
 }
 
 
-def solve_sources_hash() -> str:
+def solve_sources_hash(sources=SOLVE_SOURCES) -> str:
     import hashlib
     h = hashlib.sha256()
-    for f in SOLVE_SOURCES:
+    for f in sources:
         with open(os.path.join(ROOT, "paper_2309_06427_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -458,11 +468,14 @@ def main() -> int:
         du = torch.empty(max(nu_rows, 1), dtype=torch.float64, device=dx.device)
         rec_ms = timed(lambda: db.solver.kkt_recover(db.A, db.B, q, r, db.lam, dx, du), 10)
         rb, cb = (float(x.sum()) for x in kkt_bytes(b))
+        krec = MEASURED_KKT_TRAFFIC.get(args.workload)
+        kt = krec[1:] if krec and krec[0] == solve_sources_hash(KKT_SOURCES) else (None, None)
         kkt = {"rhs_ms": round(rhs_ms, 4), "recover_ms": round(rec_ms, 4),
                "rhs_algorithmic_bytes": rb, "recover_algorithmic_bytes": cb,
                "rhs_GBps": round(rb / rhs_ms / 1e6, 2), "recover_GBps": round(cb / rec_ms / 1e6, 2),
                "rhs_frac": round(rb / rhs_ms / 1e6 / HBM_PEAK_GBS, 4),
-               "recover_frac": round(cb / rec_ms / 1e6 / HBM_PEAK_GBS, 4)}
+               "recover_frac": round(cb / rec_ms / 1e6 / HBM_PEAK_GBS, 4),
+               "rhs_traffic": kt[0], "recover_traffic": kt[1]}
         db.gamma.copy_(gamma0)
         del gamma0, q, c, r, dx, du
 
