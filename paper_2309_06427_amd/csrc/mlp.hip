@@ -216,87 +216,105 @@ hipError_t gemm(int M, int N, int K, int splits, const AL &al, const BL &bl, con
 
 // First layer, z = standardised inputs x W1 + b1, h = gelu(z), for 64 knots
 // by up to 128 hidden units per workgroup (4 waves, each 16 knots x 128
-// units as 8 MFMA tiles).  A thread loads four consecutive inputs of one
-// knot: entries of D_k from its packed upper triangle, L_k (stored as zeros
-// at the first knot) with one vector load; nx^2 must be a multiple of 4 so
-// that no quad straddles two input sections (the caller checks).
+// units as 8 MFMA tiles), K in steps of 32 through two LDS buffers.  A
+// thread gathers eight consecutive raw inputs of one knot per step through a
+// table of input offsets built in LDS at the start (D_k from its packed upper
+// triangle, L_k, gamma_k); the step's 32 means and inverse deviations go to
+// LDS beside the tile and standardise each A operand as it is read (features
+// past nin get inverse deviation 0, so they add nothing; rows past M only
+// feed outputs that are not stored).  The next step's loads are issued
+// before this step's products, at clamped addresses and without branches,
+// so that no wait separates them.
+constexpr int kL1N = 128, kL1K = 32;
+constexpr int kFeatL = 1, kFeatG = 2;  // input kinds in the table's top bits (0: D_k)
+constexpr int kL1MaxIn = 3136;         // table entries (the static tiles leave room for these)
+
 template <typename TM>
 __global__ __launch_bounds__(GT) void k_layer1(FeatSrc s, const float *__restrict__ W1, const float *__restrict__ b1,
                                                const float *__restrict__ mu, const float *__restrict__ isd, int nin,
                                                int H, float *__restrict__ Z, float *__restrict__ Hout) {
-    constexpr int L1N = 128;
-    __shared__ float As[BK][BM + PADL];
-    __shared__ float Bs[BK][L1N + PADL];
+    __shared__ float As[2][kL1K][BM + PADL];
+    __shared__ float Bs[2][kL1K][kL1N + PADL];
+    __shared__ float Ms[2][2][kL1K];  // mean, inverse deviation of the step's inputs
+    __shared__ int foff[kL1MaxIn];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    const int m0 = blockIdx.x * BM, n0 = blockIdx.y * L1N;
-    const int nn = s.nx * s.nx, nd = 2 * nn;
-    const int lofs = s.lofs;
-    // this thread's row of the A tile and its input quad
-    const int am = t >> 2, aq = (t & 3) * 4;
-    const bool arow = m0 + am < s.M;
-    KnotInfo q{};
-    if (arow) q = s.ki[m0 + am];
+    const int m0 = blockIdx.x * BM, n0 = blockIdx.y * kL1N;
+    const int nx = s.nx, nn = nx * nx;
+    for (int f = t; f < nin; f += GT) {
+        int v;
+        if (f < nn) {
+            const int r = f / nx, c = f - r * nx;
+            v = packed_index(r, c, nx);
+        } else if (f < 2 * nn) {
+            v = (kFeatL << 30) | (s.lofs + f - nn);
+        } else {
+            v = (kFeatG << 30) | (f - 2 * nn);
+        }
+        foff[f] = v;
+    }
+    // this thread's A row and its eight inputs of each step
+    const int am = t >> 2, aq = (t & 3) * 8;
+    const KnotInfo q = s.ki[min(m0 + am, s.M - 1)];  // rows past M: a valid knot (outputs not stored)
     const TM *src = (const TM *)s.B3 + q.blk;
-    // B tile: row t / 16, eight columns from 8 (t % 16)
-    const int bk = t >> 4, bn = (t & 15) * 8;
+    const double *gsrc = s.gamma + q.vec;
+    // B tile: row t / 8 of the step, sixteen columns from 16 (t % 8); the
+    // first 64 threads also fetch the step's scaling (t < 32 means, else
+    // inverse deviations)
+    const int bk = t >> 3, bn = (t & 7) * 16;
+    const int nlast = nin - 1;
     f32x4 acc[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < nin; k0 += BK) {
-        __syncthreads();
-        {
-            const int f = k0 + aq;
-            float x[4] = {0.f, 0.f, 0.f, 0.f};
-            if (arow) {
-                if (f < nn) {
+    // the next step's raw loads and their 0/1 weights: combined only when
+    // they are stored, so that the loads stay in flight over this step's
+    // products.  Both input loads are kept (weighted rather than selected) so
+    // that the compiler issues them unconditionally; they read finite inputs
+    // at valid addresses.
+    TM rd[8];
+    double rg[8];
+    float wd[8], wg[8], wb[4], rs, ws;
+    f32x4 rb[4];
+    auto load = [&](int k0) {
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        const int r = (f + j) / s.nx, c = f + j - r * s.nx;
-                        x[j] = (float)src[packed_index(r, c, s.nx)];
-                    }
-                } else if (f + 3 < nd) {
-                    const TM *lsrc = src + lofs + (f - nn);
-                    if constexpr (sizeof(TM) == 4) {
-                        const f32x4 v = *(const f32x4 *)lsrc;
-                        x[0] = v.x;
-                        x[1] = v.y;
-                        x[2] = v.z;
-                        x[3] = v.w;
-                    } else {
-#pragma unroll
-                        for (int j = 0; j < 4; ++j) x[j] = (float)lsrc[j];
-                    }
-                } else {
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        const int fj = f + j;
-                        if (fj < nd) x[j] = (float)src[lofs + (fj - nn)];
-                        else if (fj < nin) x[j] = (float)s.gamma[q.vec + (fj - nd)];
-                    }
-                }
-            }
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int fj = f + j;
-                As[aq + j][am] = (arow && fj < nin) ? (x[j] - mu[fj]) * isd[fj] : 0.f;
-            }
+        for (int j = 0; j < 8; ++j) {
+            const int fc = min(k0 + aq + j, nlast);
+            const int e = foff[fc], kind = (int)((unsigned)e >> 30), o = e & 0x3fffffff;
+            rd[j] = src[kind == kFeatG ? 0 : o];
+            rg[j] = gsrc[kind == kFeatG ? o : 0];
+            wd[j] = (kind == kFeatG || (kind == kFeatL && q.first)) ? 0.f : 1.f;
+            wg[j] = kind == kFeatG ? 1.f : 0.f;
         }
-        {
-            const int kr = k0 + bk;
+        const int kr = k0 + bk;
+        const float *wrow = W1 + (int64_t)min(kr, nlast) * H;
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int n = n0 + bn + j;
-                Bs[bk][bn + j] = (kr < nin && n < H) ? W1[(int64_t)kr * H + n] : 0.f;
-            }
+        for (int c = 0; c < 4; ++c) {
+            const int n = n0 + bn + 4 * c;
+            rb[c] = *(const f32x4 *)(wrow + min(n, H - 4));
+            wb[c] = (kr < nin && n < H) ? 1.f : 0.f;
         }
-        __syncthreads();
+        const int fs = k0 + (t & 31);
+        rs = (t < 32 ? mu : isd)[min(fs, nlast)];
+        ws = (t < 32 || fs < nin) ? 1.f : 0.f;
+    };
+    __syncthreads();  // the input table is complete
+    load(0);
+    for (int k0 = 0, buf = 0; k0 < nin; k0 += kL1K, buf ^= 1) {
 #pragma unroll
-        for (int sub = 0; sub < BK / 4; ++sub) {
+        for (int j = 0; j < 8; ++j) As[buf][aq + j][am] = (float)rd[j] * wd[j] + (float)rg[j] * wg[j];
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) Bs[buf][bk][bn + 4 * c + r] = rb[c][r] * wb[c];
+        if (t < 64) Ms[buf][t >> 5][t & 31] = rs * ws;
+        __syncthreads();  // this buffer is full; the other one's readers are done (they passed this barrier)
+        load(k0 + kL1K);  // past nin: clamped addresses, zero scaling
+#pragma unroll
+        for (int sub = 0; sub < kL1K / 4; ++sub) {
             const int kr = 4 * sub + (lane >> 4), c = lane & 15;
-            const float a = As[kr][16 * w + c];
+            const float a = (As[buf][kr][16 * w + c] - Ms[buf][0][kr]) * Ms[buf][1][kr];
 #pragma unroll
             for (int j = 0; j < 8; ++j)
-                acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, Bs[kr][16 * j + c], acc[j], 0, 0, 0);
+                acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, Bs[buf][kr][16 * j + c], acc[j], 0, 0, 0);
         }
     }
 #pragma unroll
@@ -501,9 +519,9 @@ template <typename TM>
 hipError_t forward_t(const FeatSrc &f, const NetView &w, const float *mu, const float *isd, float ys, float *Z1,
                      float *H1, float *Z2, float *H2, float *O, double *lam, hipStream_t s) {
     hipError_t e;
-    if ((f.nx * f.nx) % 4 == 0) {
-        hipLaunchKernelGGL(k_layer1<TM>, dim3((f.M + BM - 1) / BM, (w.H + 127) / 128), dim3(GT), 0, s, f, w.W1, w.b1,
-                           mu, isd, w.nin, w.H, Z1, H1);
+    if (w.nin <= kL1MaxIn && w.H % 4 == 0) {
+        hipLaunchKernelGGL(k_layer1<TM>, dim3((f.M + BM - 1) / BM, (w.H + kL1N - 1) / kL1N), dim3(GT), 0, s, f, w.W1,
+                           w.b1, mu, isd, w.nin, w.H, Z1, H1);
         if ((e = hipGetLastError())) return e;
     } else {
         FeatA<TM> fa{f, mu, isd, w.nin};

@@ -92,8 +92,10 @@ def test_scaling_statistics_match_numpy(nx, H):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32_refine64"])
-@pytest.mark.parametrize("nx,H", [(6, 128), (14, 32), (26, 128)])
+@pytest.mark.parametrize("nx,H", [(6, 128), (14, 32), (26, 128), (5, 32)])
 def test_forward_matches_oracle(nx, H, prec):
+    """The first layer gathers its inputs through a table of offsets; nx = 5
+    (nx^2 odd) and H = 32 (a partial hidden tile) check its edges."""
     b, db, probs, lam_star = _pool(nx, 4, 12, prec=prec)
     net, theta = _net(nx, H, 2)
     net.fit_scaling(db, lam_star)
