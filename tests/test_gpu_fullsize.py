@@ -18,6 +18,15 @@ Bars (per sampled problem):
     the original basis, so not step for step the same).
 Over the whole batch: every status is OK (no block-Jacobi takeover) and every
 reported residual is <= tol.
+
+The same batch and precision also run every other preconditioner (scalar
+Jacobi in the fused solve; block-Jacobi, additive stair and the degree-3
+Neumann polynomial in the scaled solve), as the benchmark's comparison does,
+with the same per-problem bars against the oracle's direct solution; and the
+KKT step around the solve (right-hand side from seeded q, r, c, then the
+recovery from the GPU's lambda), whose FP64 products must match the oracle's
+KKT functions to 1e-10 of the largest entry on the sampled problems, which
+cover every state size and so every KKT kernel class.
 """
 import numpy as np
 import pytest
@@ -85,3 +94,72 @@ def test_sampled_problems_match_the_oracle(full):
         assert err <= kap * TOL, (i, err, kap)
         it, it_ref = float(out["iters"][i]), float(ref["iters"][j])
         assert abs(it - it_ref) <= 0.25 * it_ref + 3, (i, it, it_ref)
+
+
+@pytest.fixture(scope="module")
+def refs(full):
+    """The oracle's S blocks, direct solution and kappa_2(S) of each sampled problem."""
+    b = full[0]
+    out = {}
+    for i in sample(b):
+        p = b.problem(i)
+        st, D, L, _, _ = oracle.build(p["A"], p["B"], p["Q"], p["R"], "sym")
+        assert st == oracle.OK
+        st, lam_star = oracle.direct(D, L, p["gamma"])
+        assert st == oracle.OK
+        out[i] = (D, L, lam_star, dense.kappa(D, L))
+    return out
+
+
+@pytest.mark.parametrize("pc", ["jacobi", "bj", "add", "poly3"])
+def test_every_preconditioner_at_full_size(full, refs, pc):
+    from paper_2309_06427_amd import solver
+    b = full[0]
+    with solver.DeviceBatch(b) as db:
+        db.build(pc, "fp32_refine64")
+        db.solve(TOL)
+        out = db.results()
+        kern = db.solver.solve_kernel()[0]
+    assert kern == (2 if pc == "jacobi" else 4), kern
+    assert ((out["status"] & ~16) == 0).all(), np.unique(out["status"], return_counts=True)
+    assert out["relres"].max() <= TOL
+    for i, (D, L, lam_star, kap) in refs.items():
+        p = b.problem(i)
+        lam = out["lam"][b.off_v[i]:b.off_v[i + 1]]
+        rr = oracle.relres(D, L, p["gamma"], lam)
+        assert rr <= TOL * 1.0001, (pc, i, rr)
+        err = np.linalg.norm(lam - lam_star) / np.linalg.norm(lam_star)
+        assert err <= kap * TOL, (pc, i, err, kap)
+
+
+def test_kkt_step_at_full_size(full):
+    from paper_2309_06427_amd import solver
+    b = full[0]
+    rng = np.random.default_rng(77)
+    off_u = np.concatenate([[0], np.cumsum(b.N.astype(np.int64) * b.nu)])
+    nv = int(b.off_v[-1])
+    q, c, r = rng.standard_normal(nv), rng.standard_normal(nv), rng.standard_normal(int(off_u[-1]))
+    dev = lambda x: torch.from_numpy(x).cuda()
+    with solver.DeviceBatch(b) as db:
+        assert np.array_equal(db.solver.off_u, off_u)
+        db.build("sym", "fp32_refine64")
+        db.kkt_rhs(dev(q), dev(r), dev(c))
+        torch.cuda.synchronize()
+        g = db.gamma.cpu().numpy()
+        db.solve(TOL)
+        lam = db.results()["lam"]
+        dx, du = db.kkt_recover(dev(q), dev(r))
+        torch.cuda.synchronize()
+        dx, du = dx.cpu().numpy(), du.cpu().numpy()
+    ids = sample(b)
+    assert set(int(x) for x in b.nx[ids]) == {6, 14, 26}
+    for i in ids:
+        p = b.problem(i)
+        sv, su = slice(b.off_v[i], b.off_v[i + 1]), slice(off_u[i], off_u[i + 1])
+        st, g_ref = oracle.kkt_rhs(p["A"], p["B"], p["Q"], p["R"], q[sv], r[su], c[sv])
+        assert st == oracle.OK
+        assert np.abs(g[sv] - g_ref).max() <= 1e-10 * np.abs(g_ref).max(), i
+        st, dx_ref, du_ref = oracle.kkt_recover(p["A"], p["B"], p["Q"], p["R"], q[sv], r[su], lam[sv])
+        assert st == oracle.OK
+        assert np.abs(dx[sv] - dx_ref).max() <= 1e-10 * np.abs(dx_ref).max(), i
+        assert np.abs(du[su] - du_ref).max() <= 1e-10 * np.abs(du_ref).max(), i
