@@ -5,10 +5,18 @@
  * positive-definite block-tridiagonal Schur-complement system S lambda = gamma
  * of a trajectory-optimization KKT system (Bu & Plancher, Sec. II-A,
  * Eq. (schur) and the theta/phi/zeta block definitions), with preconditioned
- * conjugate gradient (Sec. II-B) under one of three preconditioners:
- * block-Jacobi (Sec. II-C, Eq. (jacobi)), the additive stair preconditioner
- * (Sec. III, Eqs. (stair), (stair_inv) and the additive combination) and the
- * symmetric stair preconditioner (Sec. IV).
+ * conjugate gradient (Sec. II-B) under one of these preconditioners:
+ * block-Jacobi and scalar Jacobi (Sec. II-C, Eq. (jacobi)), the additive
+ * stair preconditioner (Sec. III, Eqs. (stair), (stair_inv) and the additive
+ * combination), the symmetric stair preconditioner (Sec. IV), and the
+ * Neumann polynomials of degree 2 and 3 (Sec. II-C, Eq. (polynomial_precon)
+ * with Psi = D).  The KKT step around the solve (ssp_kkt_rhs,
+ * ssp_kkt_recover) forms gamma and recovers the primal step (Sec. II-A).
+ *
+ * The handle, layout, export, mapping, autotuning and diagnostic calls cite
+ * no passage: the paper fixes what is computed, not how a GPU library holds
+ * its batch, lays out its arrays or launches its kernels.  Their comments
+ * state the contract instead.
  *
  * Conventions shared by every entry point
  *   - Problem p has N[p] >= 1 knots (block rows), state size nx[p] in [1, 64]
