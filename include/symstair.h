@@ -220,8 +220,8 @@ ssp_status ssp_solve_noalloc(ssp_batch *b, double rel_tol, int32_t max_iter, con
  * C the dynamics constraints (block row 0: +I on x_0; block row k + 1:
  * -A_k, -B_k, +I on x_k, u_k, x_{k+1}), the sign the paper's block form of
  * gamma fixes.  Both calls need the Q_k^-1, R_k^-1 of the preceding ssp_build
- * of this handle (SSP_ERR_STATE after ssp_build_from_blocks or before any
- * build) and take the same A, B device arrays; all vectors are device FP64
+ * of this handle (SSP_ERR_STATE after ssp_build_from_blocks, before any
+ * build, or after a build with ssp_set_keep_inverses(b, 0)) and take the same A, B device arrays; all vectors are device FP64
  * in the layout of ssp_layout (q, c, gamma, lambda, dx: off_v; r, du:
  * off_u).  Numerically they follow the build: a problem flagged NOT_SPD
  * there gets meaningless values.
@@ -366,6 +366,14 @@ ssp_status ssp_set_group_mapping(ssp_batch *b, int32_t nx, int32_t threads, int3
  * count goes to *ngroups. */
 ssp_status ssp_get_mapping(const ssp_batch *b, int32_t max_groups, int32_t *nx, int32_t *threads,
                            int32_t *lds_bytes, float *tuned_ms, int32_t *ngroups);
+
+/* Whether ssp_build stores Q_k^-1 and R_k^-1 for the KKT step: on = 1
+ * (default) stores them in the handle's FP64 workspace, on = 0 does not
+ * (a caller that only solves saves their HBM traffic; ssp_kkt_rhs and
+ * ssp_kkt_recover then return SSP_ERR_STATE until a build that keeps them).
+ * The stored S, preconditioner and scaled basis are the same either way.
+ * Takes effect at the next ssp_build. */
+ssp_status ssp_set_keep_inverses(ssp_batch *b, int32_t on);
 
 /* Accumulation of the PCG inner products (r.u, w.u, r.r; Sec. II-B) in the
  * scaled solve under FP32 storage: on = 0 (default) sums the FP32 products

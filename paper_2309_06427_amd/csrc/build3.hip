@@ -119,6 +119,14 @@ __device__ __forceinline__ void fmac_j2(double &a0, double &a1, double s0, doubl
 
 __device__ __forceinline__ void keep1(double v) { asm volatile("" ::"v"(v)); }
 
+// Settle a pivot test here: otherwise the compiler sinks the comparisons to
+// the flag's last use and holds every pivot in registers until then.
+__device__ __forceinline__ bool settle(bool f) {
+    int v = f;
+    asm volatile("" : "+v"(v));
+    return v != 0;
+}
+
 // Make every value of a[][] be computed here (in wave-uniform code).
 template <int R, int N>
 __device__ __forceinline__ void keep(const double (&a)[R][N]) {
@@ -521,52 +529,19 @@ __device__ __forceinline__ void lower_from_upper(double (&a)[RowGeo<NX>::R][NX],
 
 }  // namespace
 
-// Q_k^-1 for every knot and R_k^-1 for k < N-1, into the FP64 workspaces
-// (nu = NX / 2).  One wave, knots k0 .. k0 + 3.
-template <int NX>
-__global__ __launch_bounds__(kThreadsD) void k_bdpp_inv(BuildArgs a, const int2 *items) {
-    constexpr int R = RowGeo<NX>::R, P = RowGeo<NX>::P, NN = NX * NX, NU = NX / 2, UU = NU * NU;
-    constexpr int RU = (NU + P - 1) / P;
-    __shared__ __align__(16) double sm[kKnotsD * NN + 2];
-    double *spare = sm + kKnotsD * NN;  // sink of staged copies past their range
-    const int2 it = items[blockIdx.x];
-    const int pr = it.x, N = a.N[pr], k0 = it.y, nk = min(kKnotsD, N - k0);
-    const Dl<NX> d = dl_of<NX>(k0, N);
-    const int gc = min(d.g, nk - 1);  // staged knot of this row (clamped)
-    const int64_t oq = a.off_nn[pr] + (int64_t)k0 * NN, orr = a.off_uu[pr] + (int64_t)k0 * UU;
-
-    stage_in<kKnotsD * NN>(sm, a.Q + oq, nk * NN, spare);
-    wave_sync();
-    double q[R][NX];
-    lds_rows<NX>(sm + gc * NN, NX, NX, d.p, q);
-    identity_outside<NX>(q, d.p, d.act, NX);
-    bool ok = gj_dpp<P, R, NX>(q, d.p, NX);
-    wave_sync();
-    rows_to_lds<NX>(sm + d.g * NN, NX, d.act, d.p, q, 1.0);
-    wave_sync();
-    copy_out<kKnotsD * NN>(a.Qinv + oq, sm, nk * NN);
-    wave_sync();
-
-    const bool live = d.act && d.knot < N - 1;
-    const int nr = min(kKnotsD, N - 1 - k0);  // knots with an R_k^-1
-    stage_in<kKnotsD * UU>(sm, a.R + orr, nk * UU, spare);
-    wave_sync();
-    double r[RU][NU];
-    lds_rows<NX>(sm + gc * UU, NU, NU, d.p, r);
-    identity_outside<NX>(r, d.p, live, NU);
-    const bool okr = gj_dpp<P, RU, NU>(r, d.p, NU);
-    if (live) ok = ok && okr;
-    wave_sync();
-    rows_to_lds<NX>(sm + d.g * UU, NU, live, d.p, r, 1.0);
-    wave_sync();
-    if (nr > 0) copy_out<kKnotsD * UU>(a.Rinv + orr, sm, nr * UU);
-    if (d.act && !ok) atomicOr(a.status + pr, kNotSpd);
-}
-
+// One knot's blocks of S and of the scaled basis from the inputs A, B, Q, R:
 // D_k, L_k (storage type, FP32 remainder under FP32 storage) and then W_k
 // (SCALED: the scaled basis) or D_k^-1 (nu = NX / 2).  One wave, knots
 // k0 .. k0 + 3; at least two waves per SIMD (the compiler keeps the kernel
 // within 256 registers).
+//
+// The inverses Q_{k-1}^-1, R_{k-1}^-1 and Q_k^-1 are formed in registers
+// from the staged inputs, so every Q_k is inverted twice (by the rows of
+// knots k and k + 1).  That is a fifth more FP64 work than reading a stored
+// Q^-1, R^-1 back, and saves their store and both reads, which bound the
+// assembly in HBM.  With keep_qr set the knot's Q_k^-1 and R_{k-1}^-1 are
+// also stored (the KKT step reads them); items cover disjoint knot ranges,
+// so each block is stored once.
 template <typename TM, int NX, bool SCALED>
 __global__ __launch_bounds__(kThreadsD) __attribute__((amdgpu_waves_per_eu(2))) void k_bdpp_asm(BuildArgs a,
                                                                                               const int2 *items) {
@@ -579,6 +554,7 @@ __global__ __launch_bounds__(kThreadsD) __attribute__((amdgpu_waves_per_eu(2))) 
     const Dl<NX> d = dl_of<NX>(k0, N);
     const int k = d.knot, kc = min(k, N - 1), km = max(kc - 1, 0);
     const bool prev = d.act && k > 0;
+    const bool keep = a.keep_qr != 0;
     // blocks k-1 of the knots k0 .. k0+nk-1 (knot 0 reads block 0 with a zero multiplier)
     const int ks = max(k0 - 1, 0), ke = max(k0 + nk - 1, ks + 1), gm = km - ks, gc = kc - k0;
     const int bs = block_stride(NX, sizeof(TM)), bp = packed_stride(NX, sizeof(TM)), kst = 2 * bp + bs;
@@ -586,12 +562,15 @@ __global__ __launch_bounds__(kThreadsD) __attribute__((amdgpu_waves_per_eu(2))) 
     int rw[R];
     static_for<0, R>([&](auto s_) { rw[decltype(s_)::value] = min(d.row(decltype(s_)::value), NX - 1); });
 
-    // t = A_{k-1} Q_{k-1}^-1 (rows of Q^-1 broadcast)
+    // m = Q_{k-1}^-1 (identity where the knot has no predecessor)
     double m[R][NX], t[R][NX];
-    stage_in<kKnotsD * NN>(sm, a.Qinv + a.off_nn[pr] + (int64_t)ks * NN, (ke - ks) * NN, spare);
+    stage_in<kKnotsD * NN>(sm, a.Q + a.off_nn[pr] + (int64_t)ks * NN, (ke - ks) * NN, spare);
     wave_sync();
     lds_rows<NX>(sm + gm * NN, NX, NX, d.p, m);
+    identity_outside<NX>(m, d.p, prev, NX);
+    (void)gj_dpp<P, R, NX>(m, d.p, NX);  // Q_{k-1} is checked by the row of knot k-1
     wave_sync();
+    // t = A_{k-1} Q_{k-1}^-1 (rows of Q^-1 broadcast)
     stage_in<kKnotsD * NN>(sm, a.A + a.off_nn[pr] + (int64_t)ks * NN, (ke - ks) * NN, spare);
     wave_sync();
     int ro[R];  // this lane's rows in the staged block
@@ -621,23 +600,27 @@ __global__ __launch_bounds__(kThreadsD) __attribute__((amdgpu_waves_per_eu(2))) 
         }
         wave_sync();
     }
+    bool ok = true;
     // D_k += B u^T with u = B_{k-1} R_{k-1}^-1
     {
         double *Rb = sm, *Bb = sm + kKnotsD * UU;
-        stage_in<kKnotsD * UU>(Rb, a.Rinv + a.off_uu[pr] + (int64_t)ks * UU, (ke - ks) * UU, spare);
+        stage_in<kKnotsD * UU>(Rb, a.R + a.off_uu[pr] + (int64_t)ks * UU, (ke - ks) * UU, spare);
         stage_in<kKnotsD * XU>(Bb, a.B + a.off_nu[pr] + (int64_t)ks * XU, (ke - ks) * XU, spare);
         wave_sync();
         double ri[RU][NU], u[R][NU];
         lds_rows<NX>(Rb + gm * UU, NU, NU, d.p, ri);
-        // R_{N-1}^-1 is never formed: a one-knot problem's knot 0 (zero
-        // multiplier) must not read it
-        const bool rok = km < N - 1;
-        static_for<0, RU>([&](auto s_) {
-            static_for<0, NU>([&](auto jc) {
-                double &v = ri[decltype(s_)::value][decltype(jc)::value];
-                v = rok ? v : 0.0;
-            });
-        });
+        // R_{N-1} has no inverse in the method; knots without a predecessor
+        // (zero multiplier) take the identity
+        identity_outside<NX>(ri, d.p, prev, NU);
+        const bool okr = settle(gj_dpp<P, RU, NU>(ri, d.p, NU));
+        if (prev) ok = okr;
+        if (keep) {  // R_{k-1}^-1 of the knots k0-1 .. k0+nk-2 (from 0)
+            wave_sync();
+            rows_to_lds<NX>(Rb + gm * UU, NU, prev, d.p, ri, 1.0);
+            wave_sync();
+            const int nr = k0 + nk - 1 - ks;
+            if (nr > 0) copy_out<kKnotsD * UU>(a.Rinv + a.off_uu[pr] + (int64_t)ks * UU, Rb, nr * UU);
+        }
         static_for<0, R>([&](auto s_) { static_for<0, NU>([&](auto jc) { u[decltype(s_)::value][decltype(jc)::value] = 0.0; }); });
         int rb[R];
         static_for<0, R>([&](auto s_) { rb[decltype(s_)::value] = gm * XU + rw[decltype(s_)::value] * NU; });
@@ -652,15 +635,35 @@ __global__ __launch_bounds__(kThreadsD) __attribute__((amdgpu_waves_per_eu(2))) 
         wave_sync();
     }
     // D_k += Q_k^-1
-    stage_in<kKnotsD * NN>(sm, a.Qinv + a.off_nn[pr] + (int64_t)k0 * NN, nk * NN, spare);
-    wave_sync();
-    static_for<0, R>([&](auto s_) {
-        constexpr int s = decltype(s_)::value;
-        static_for<0, NX>([&](auto jc) {
-            constexpr int j = decltype(jc)::value;
-            dk[s][j] += sm[gc * NN + rw[s] * NX + j];
+    {
+        stage_in<kKnotsD * NN>(sm, a.Q + a.off_nn[pr] + (int64_t)k0 * NN, nk * NN, spare);
+        wave_sync();
+        double q[R][NX];
+        lds_rows<NX>(sm + gc * NN, NX, NX, d.p, q);
+        identity_outside<NX>(q, d.p, d.act, NX);
+        // D_k's rows wait in the knot's LDS block while Q_k is inverted (both
+        // in registers at once would not fit)
+        double *park = sm + d.g * NN;
+        wave_sync();
+        static_for<0, R>([&](auto s_) {
+            constexpr int s = decltype(s_)::value;
+            if (d.p < P) static_for<0, NX>([&](auto jc) { park[rw[s] * NX + decltype(jc)::value] = dk[s][decltype(jc)::value]; });
         });
-    });
+        ok = settle(gj_dpp<P, R, NX>(q, d.p, NX)) && ok;
+        static_for<0, R>([&](auto s_) {
+            constexpr int s = decltype(s_)::value;
+            static_for<0, NX>([&](auto jc) {
+                constexpr int j = decltype(jc)::value;
+                dk[s][j] = park[rw[s] * NX + j] + q[s][j];
+            });
+        });
+        if (keep) {  // Q_k^-1 of the knots k0 .. k0+nk-1
+            wave_sync();
+            rows_to_lds<NX>(sm + d.g * NN, NX, d.act, d.p, q, 1.0);
+            wave_sync();
+            copy_out<kKnotsD * NN>(a.Qinv + a.off_nn[pr] + (int64_t)k0 * NN, sm, nk * NN);
+        }
+    }
     lower_from_upper<NX>(dk, d.p, sm + d.g * P * NX);
     // D_k (packed upper triangle)
     {
@@ -674,22 +677,22 @@ __global__ __launch_bounds__(kThreadsD) __attribute__((amdgpu_waves_per_eu(2))) 
         }
         wave_sync();
     }
-    bool ok;
+    bool okd;
     if constexpr (SCALED) {
         // scaled basis: W_k = C_k^-1, stored full (zeros above the diagonal)
-        ok = lower_inverse_dpp<P, R, NX>(dk, d.p);
+        okd = lower_inverse_dpp<P, R, NX>(dk, d.p);
         TM *w = (TM *)sm;
         split_rows_to_lds<NX, TM>(w + d.g * NN, nullptr, d.act, d.p, dk, 1.0);
         wave_sync();
         for (int g = 0; g < nk; ++g) copy_out<NN>((TM *)a.Zs + a.off_blk[pr] + (int64_t)(k0 + g) * bs, w + g * NN, NN);
     } else {
-        ok = gj_dpp<P, R, NX>(dk, d.p, NX);
+        okd = gj_dpp<P, R, NX>(dk, d.p, NX);
         TM *di = (TM *)sm;
         split_packed_to_lds<NX, TM>(di + d.g * PK, nullptr, d.act, d.p, dk);
         wave_sync();
         for (int g = 0; g < nk; ++g) copy_out<PK>(b3 + (int64_t)g * kst + bp + bs, di + g * PK, PK);
     }
-    if (d.act && !ok) atomicOr(a.status + pr, kNotSpd);
+    if (d.act && !(ok && okd)) atomicOr(a.status + pr, kNotSpd);
 }
 
 // Oh_k = W_k L_k W_{k-1}^T (k >= 1, Oh_0 = 0) in FP64 from the stored W and
@@ -739,9 +742,6 @@ __global__ __launch_bounds__(kThreadsD) void k_bdpp_ohat(BuildArgs a, const int2
 template <int NX>
 hipError_t launch_dpp_class(const BuildArgs &a, const int2 *items, int nitems, bool fp32, hipStream_t s) {
     if (nitems == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_bdpp_inv<NX>, dim3(nitems), dim3(kThreadsD), 0, s, a, items);
-    hipError_t e = hipGetLastError();
-    if (e) return e;
     const bool sc = a.Zs != nullptr;
     const dim3 g(nitems), t(kThreadsD);
     if (fp32 && sc)

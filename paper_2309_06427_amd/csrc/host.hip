@@ -196,6 +196,7 @@ ssp::BuildArgs build_args(const ssp_batch *b) {
     a.Zs = a.OH = nullptr;
     a.pc = (int)b->pc;
     a.mx = std::max(b->nx_max, b->nu_max);
+    a.keep_qr = b->keep_qr;
     return a;
 }
 
@@ -749,7 +750,7 @@ ssp_status ssp_build(ssp_batch *b, ssp_precon pc, ssp_precision prec, const doub
     b->prec = prec;
     b->scaled = scaled;
     b->dinv_valid = !scaled;
-    b->have_qr = true;
+    b->have_qr = b->keep_qr != 0;
     SSP_HIP(ssp::launch_fill_i32(prob_status, 0, b->P, s));
     ssp::BuildArgs a = build_args(b);
     a.A = A;
@@ -1053,7 +1054,7 @@ ssp_status ssp_kkt_rhs(ssp_batch *b, const double *A, const double *B, const dou
     if (!b || !A || !q || !c || !gamma) return SSP_ERR_ARG;
     if (b->nu_max > 0 && (!B || !r)) return SSP_ERR_ARG;
     if (!b->built || !b->have_qr) {
-        g_last_error = "ssp_kkt_rhs needs a preceding ssp_build (its Q^-1, R^-1)";
+        g_last_error = "ssp_kkt_rhs needs a preceding ssp_build that kept Q^-1, R^-1 (ssp_set_keep_inverses)";
         return SSP_ERR_STATE;
     }
     DevGuard g(b->device);
@@ -1072,7 +1073,7 @@ ssp_status ssp_kkt_recover(ssp_batch *b, const double *A, const double *B, const
     if (!b || !A || !q || !lambda || !dx) return SSP_ERR_ARG;
     if (b->nu_max > 0 && (!B || !r || !du)) return SSP_ERR_ARG;
     if (!b->built || !b->have_qr) {
-        g_last_error = "ssp_kkt_recover needs a preceding ssp_build (its Q^-1, R^-1)";
+        g_last_error = "ssp_kkt_recover needs a preceding ssp_build that kept Q^-1, R^-1 (ssp_set_keep_inverses)";
         return SSP_ERR_STATE;
     }
     DevGuard g(b->device);
@@ -1083,6 +1084,12 @@ ssp_status ssp_kkt_recover(ssp_batch *b, const double *A, const double *B, const
         SSP_HIP(ssp::launch_kkt_recover(cls < ssp::kKktClasses ? cls : -1, a, b->dkkt + b->kkt_off[cls],
                                         b->kkt_off[cls + 1] - b->kkt_off[cls], b->doff_v, b->doff_u, q, r, lambda, dx,
                                         du, (hipStream_t)stream));
+    return SSP_OK;
+}
+
+ssp_status ssp_set_keep_inverses(ssp_batch *b, int32_t on) {
+    if (!b || (on != 0 && on != 1)) return SSP_ERR_ARG;
+    b->keep_qr = on;
     return SSP_OK;
 }
 

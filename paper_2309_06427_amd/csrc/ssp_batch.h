@@ -119,6 +119,7 @@ struct ssp_batch {
     unsigned *dbar = nullptr;
     unsigned long long *drec = nullptr, *dwtag = nullptr;
     int coop_key = -1, coop_W = 0, coop_G = 0;  // cached plan (key: storage precision)
+    int keep_qr = 1;                              // builds store Q^-1, R^-1 for the KKT step
     int acc64 = 0;                                // scaled solve: FP64 sums of the FP32 inner products
     int last_kernel = 0;                          // kernel of the last solve: 1 explicit, 2 fused, 3 cooperative, 4 scaled
     // Fused solve groups: the problems of one state size, largest first,

@@ -27,6 +27,7 @@ struct BuildArgs {
     int32_t *status;
     int pc;  // 0 block-Jacobi, 1 additive stair, 2 symmetric stair, 3 scalar Jacobi, 4/5 Neumann degree 2/3
     int mx;  // max(nx, nu) over the batch
+    int keep_qr;  // store Q_k^-1, R_k^-1 in Qinv, Rinv (the KKT step reads them)
 };
 
 struct SolveArgs {

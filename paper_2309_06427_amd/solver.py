@@ -112,6 +112,10 @@ class BatchSolver:
                                 C.byref(n)), "ssp_get_mapping")
         return [(int(nx[i]), int(th[i]), int(lds[i]), float(ms[i])) for i in range(k)]
 
+    def set_keep_inverses(self, on: bool):
+        """Whether builds store Q_k^-1, R_k^-1 for the KKT step (default on)."""
+        check(_lib.load().ssp_set_keep_inverses(self._h, int(bool(on))), "ssp_set_keep_inverses")
+
     def set_reduction_fp64(self, on: bool):
         """Scaled solve under FP32 storage: sum the inner products in FP64."""
         check(_lib.load().ssp_set_reduction_fp64(self._h, int(bool(on))), "ssp_set_reduction_fp64")

@@ -139,3 +139,40 @@ def test_kkt_calls_need_a_build_of_their_own():
         db.solver.build_from_blocks("sym", "fp64", dev(D), dev(L), db.status)
         with pytest.raises(RuntimeError, match="ssp_kkt_rhs"):
             db.kkt_rhs(dq, dr, dc)
+
+
+@pytest.mark.parametrize("kind,prec", [("mixed", "fp64"), ("mixed", "fp32_refine64"), ("scaled", "fp32_refine64")])
+def test_build_without_stored_inverses(kind, prec):
+    """With ssp_set_keep_inverses(b, 0) the build stores the same S and the
+    same preconditioner blocks, bit for bit, and
+    the KKT calls are refused until a build that keeps Q^-1, R^-1; after one,
+    gamma matches the oracle again."""
+    from paper_2309_06427_amd import solver
+    # "scaled": state sizes 14 and 26 with nu = nx / 2 only, whose default
+    # build is the scaled basis (compared through export(3))
+    b = mixed_batch(97) if kind == "mixed" else inputs.batch(12, seed=99, N_range=(1, 40), nx_choices=(14, 26))
+    which = (0, 1) if kind == "mixed" else (0, 1, 3)
+    q, r, c, off_u = vectors(b, 98)
+    with solver.DeviceBatch(b) as db:
+        dq, dr, dc = dev(q), dev(r), dev(c)
+        db.build("sym", prec)
+        keep = [db.export(w) for w in which]
+        db.solver.set_keep_inverses(False)
+        db.build("sym", prec)
+        lean = [db.export(w) for w in which]
+        for (d0, o0), (d1, o1) in zip(keep, lean):
+            assert np.array_equal(d0, d1) and np.array_equal(o0, o1)
+        assert (db.results()["status"] == 0).all()
+        with pytest.raises(RuntimeError, match="ssp_kkt_rhs"):
+            db.kkt_rhs(dq, dr, dc)
+        with pytest.raises(RuntimeError, match="ssp_kkt_recover"):
+            db.kkt_recover(dq, dr)
+        db.solver.set_keep_inverses(True)
+        db.build("sym", prec)
+        db.kkt_rhs(dq, dr, dc)
+        g = db.gamma.cpu().numpy()
+    for i in range(b.P):
+        p = b.problem(i)
+        sv, su = slice(b.off_v[i], b.off_v[i + 1]), slice(off_u[i], off_u[i + 1])
+        _, g_ref = oracle.kkt_rhs(p["A"], p["B"], p["Q"], p["R"], q[sv], r[su], c[sv])
+        assert np.abs(g[sv] - g_ref).max() <= 1e-10 * np.abs(g_ref).max(), i
