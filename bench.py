@@ -34,8 +34,8 @@ MEASURED_TRAFFIC = {
     # + WRITE_SIZE x 1.0 (KiB, the factors a plain 1 GiB copy reads), summed over the three k_pcg3 instances (nx 6,
     # 14, 26) of one solve at 256 threads / 48 336 B
     ("batch4096_ragged", "sym", "fp32_refine64", 0):
-        ("2cb44bcd97f48d67", ((8416100.4375 + 2957751.75 + 571463.5625) * 2.0
-                              + (2917660.28125 + 1657787.09375 + 711501.4375) * 1.0) * 1024),
+        ("0a62598386ca9dd6", ((8429720.875 + 2947985.8125 + 569933.0625) * 2.0
+                              + (2915743.875 + 1658933.53125 + 713781.90625) * 1.0) * 1024),
 }
 
 # The KKT step's HBM bytes per call, the same counters and factors, summed
@@ -43,9 +43,9 @@ MEASURED_TRAFFIC = {
 # sha256[:16], right-hand side bytes, recovery bytes)
 KKT_SOURCES = ("kkt.hip", "ssp_host.h", "host.hip")
 MEASURED_KKT_TRAFFIC = {
-    "batch4096_ragged": ("8419c7df4d045c8e",
-                         ((1421701.1 + 440623.3 + 89225.6) * 2.0 + (38556.5 + 21593.4 + 9357.2) * 1.0) * 1024,
-                         ((1522958.6 + 465590.4 + 93053.0) * 2.0 + (65205.9 + 34264.3 + 14282.9) * 1.0) * 1024),
+    "batch4096_ragged": ("bc54e970c07f0d7c",
+                         ((1421700.93 + 440623.26 + 89225.60) * 2.0 + (38555.82 + 21590.15 + 9357.00) * 1.0) * 1024,
+                         ((1522958.36 + 465590.51 + 93053.43) * 2.0 + (65205.94 + 34264.34 + 14282.89) * 1.0) * 1024),
 }
 
 
