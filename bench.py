@@ -58,7 +58,7 @@ def solve_sources_hash(sources=SOLVE_SOURCES) -> str:
     return h.hexdigest()[:16]
 
 
-def algorithmic_bytes(b, iters, outer, pc: str, precision: str, kernel: int = 0) -> np.ndarray:
+def algorithmic_bytes(b, iters, outer, pc: str, precision: str, kernel: int = 0, onchip=None) -> np.ndarray:
     """Bytes the solve must stream per problem in the library's storage format:
     every stored block element each pass reads, once per pass, plus gamma in
     and lambda out once.  D_k and D_k^-1 are symmetric and stored packed
@@ -77,7 +77,7 @@ def algorithmic_bytes(b, iters, outer, pc: str, precision: str, kernel: int = 0)
     their sum.
     """
     if kernel == 4:
-        blk, vec = scaled_bytes(b, iters, outer, precision)
+        blk, vec = scaled_bytes(b, iters, outer, precision, onchip)
         return blk + vec
     N = b.N.astype(np.float64)
     nx = b.nx.astype(np.float64)
@@ -100,7 +100,16 @@ def algorithmic_bytes(b, iters, outer, pc: str, precision: str, kernel: int = 0)
     return inner + 8.0 * sweeps * (N * npk + (N - 1) * nn) + 16.0 * N * nx
 
 
-def scaled_bytes(b, iters, outer, precision: str):
+def onchip_mask(b, pc: str, precision: str, mapping) -> np.ndarray:
+    """Problems whose six recurrence vectors the scaled solve keeps in LDS,
+    by the library's own rule for the scaled mapping (threads, lds_bytes)."""
+    from paper_2309_06427_amd import solver
+    hor = {int(x): solver.scaled_onchip_horizon(int(x), pc, precision, mapping[0], mapping[1])
+           for x in np.unique(b.nx)}
+    return np.array([int(b.N[i]) <= hor[int(b.nx[i])] for i in range(b.P)], dtype=bool)
+
+
+def scaled_bytes(b, iters, outer, precision: str, onchip=None):
     """Bytes the scaled solve must move per problem, split into block bytes
     and vector bytes.  Per PCG pass (iters + outer passes: one initial pass
     per inner solve) it streams Oh_k (N - 1 blocks of nx^2 in the storage
@@ -112,7 +121,9 @@ def scaled_bytes(b, iters, outer, precision: str):
     step, and moves FP64 vectors: residual 24 B per row (lambda, gamma in,
     r out), transforms 16 + 8 + e + 16 B per row (r in, rh out; x in, lambda
     read and written).  Once per solve: gamma read for its norm and lambda
-    zeroed (16 B per row)."""
+    zeroed (16 B per row).  Problems in `onchip` keep the six recurrence
+    vectors in LDS: no vector bytes per update pass, the initial pass reads
+    only the FP64 residual and the back transform does not read x."""
     N = b.N.astype(np.float64)
     nx = b.nx.astype(np.float64)
     nn = nx * nx
@@ -124,7 +135,8 @@ def scaled_bytes(b, iters, outer, precision: str):
     passes = it + st
     sweeps = np.maximum(st - 1, 0)  # zero start: the first outer step takes gamma as its residual
     blk = e * (N - 1) * nn * passes + 2 * e * N * nn * st + 8.0 * (N * npk + (N - 1) * nn) * sweeps
-    vec = (rows * (12 * e * it + (8 + 4 * e) * st) + rows * (24.0 * sweeps + (40.0 + e) * st) + 16.0 * rows)
+    ve = np.where(onchip, 0.0, e) if onchip is not None else e  # storage-type vector bytes per element in HBM
+    vec = (rows * (12 * ve * it + (8 + 4 * ve) * st) + rows * (24.0 * sweeps + (40.0 + ve) * st) + 16.0 * rows)
     return blk, vec
 
 
@@ -408,11 +420,13 @@ def main() -> int:
     if args.graph:
         ok = ok and all(r["graph_matches_eager"] for r in runs.values())
     kern, coop_w, coop_g = db.solver.solve_kernel()  # the kernel the solves ran: 1 explicit, 2 fused, 3 cooperative
-    bytes_solve = float(algorithmic_bytes(b, res["iters"], res["outer"], args.pc, precision, kern).sum())
+    oc = onchip_mask(b, args.pc, precision, db.solver.scaled_mapping()) if kern == 4 else None
+    bytes_solve = float(algorithmic_bytes(b, res["iters"], res["outer"], args.pc, precision, kern, oc).sum())
     split = None
     if kern == 4:
-        bb, vb = scaled_bytes(b, res["iters"], res["outer"], precision)
-        split = {"block_bytes": float(bb.sum()), "vector_bytes": float(vb.sum())}
+        bb, vb = scaled_bytes(b, res["iters"], res["outer"], precision, oc)
+        split = {"block_bytes": float(bb.sum()), "vector_bytes": float(vb.sum()),
+                 "problems_with_vectors_in_lds": int(oc.sum())}
     rec = MEASURED_TRAFFIC.get((args.workload, args.pc, precision, args.kernel))
     traffic = rec[1] if rec and rec[0] == solve_sources_hash() else None
     solve_avg_s = float(plain["solve_ms"].mean()) / 1e3
@@ -440,7 +454,8 @@ def main() -> int:
             solve_ms = timed(lambda: db.solve(tol), 3)
             r = db.results()
             pk = db.solver.solve_kernel()[0]
-            by = float(algorithmic_bytes(b, r["iters"], r["outer"], pc, precision, pk).sum())
+            oc = onchip_mask(b, pc, precision, db.solver.scaled_mapping()) if pk == 4 else None
+            by = float(algorithmic_bytes(b, r["iters"], r["outer"], pc, precision, pk, oc).sum())
             compare[pc] = {"iters_mean": round(float(r["iters"].mean()), 3),
                            "outer_mean": round(float(r["outer"].mean()), 3),
                            "max_relres": float(r["relres"].max()),

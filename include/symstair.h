@@ -395,6 +395,15 @@ ssp_status ssp_set_scaled_mapping(ssp_batch *b, int32_t threads, int32_t lds_byt
  * not tuned); any pointer may be NULL. */
 ssp_status ssp_get_scaled_mapping(const ssp_batch *b, int32_t *threads, int32_t *lds_bytes, int32_t *grid,
                                   float *tuned_ms);
+/* The largest horizon N whose six PCG recurrence vectors the scaled solve
+ * keeps in the workgroup's LDS instead of HBM, for state size nx,
+ * preconditioner pc, storage precision prec and a mapping of threads (128
+ * or 256) and lds_bytes (as ssp_get_scaled_mapping reports it): problems
+ * with N <= *max_n stream only the Oh blocks per pass.  0 = none (state
+ * sizes above 14 never).  A pure function of its arguments (no device call);
+ * SSP_ERR_ARG for a NULL max_n or an unknown pc or prec. */
+ssp_status ssp_scaled_onchip_horizon(int32_t nx, ssp_precon pc, ssp_precision prec, int32_t threads,
+                                     int32_t lds_bytes, int32_t *max_n);
 
 /* The kernel the last ssp_solve (or ssp_autotune) of this batch enqueued:
  * 1 explicit two-sweep, 2 fused (one workgroup per problem), 3 cooperative

@@ -34,6 +34,7 @@ SIGNATURES = {
     "ssp_build_from_blocks": (C.c_int, [_vp, C.c_int, C.c_int, _vp, _vp, _vp, _vp]),
     "ssp_solve": (C.c_int, [_vp, _d, _i32, _vp, _vp, C.c_int, _vp, _vp, _vp, _vp]),
     "ssp_set_keep_inverses": (C.c_int, [_vp, _i32]),
+    "ssp_scaled_onchip_horizon": (C.c_int, [_i32, _i32, _i32, _i32, _i32, C.POINTER(C.c_int32)]),
     "ssp_set_reduction_fp64": (C.c_int, [_vp, _i32]),
     "ssp_solve_noalloc": (C.c_int, [_vp, _d, _i32, _vp, _vp, C.c_int, _vp, _vp, _vp, _vp]),
     "ssp_export": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp]),

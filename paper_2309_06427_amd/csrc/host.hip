@@ -1122,6 +1122,16 @@ ssp_status ssp_set_scaled_mapping(ssp_batch *b, int32_t threads, int32_t lds_byt
     return SSP_OK;
 }
 
+ssp_status ssp_scaled_onchip_horizon(int32_t nx, ssp_precon pc, ssp_precision prec, int32_t threads,
+                                     int32_t lds_bytes, int32_t *max_n) {
+    if (!max_n || pc < SSP_PC_BLOCK_JACOBI || pc > SSP_PC_NEUMANN3) return SSP_ERR_ARG;
+    if (prec < SSP_FP64 || prec > SSP_FP32_REFINE64) return SSP_ERR_ARG;
+    // scalar Jacobi never runs the scaled solve
+    *max_n = pc == SSP_PC_SCALAR_JACOBI ? 0
+                                        : ssp::pcg3_onchip_horizon(nx, prec != SSP_FP64, threads, lds_bytes, poly_steps(pc));
+    return SSP_OK;
+}
+
 ssp_status ssp_get_scaled_mapping(const ssp_batch *b, int32_t *threads, int32_t *lds_bytes, int32_t *grid,
                                   float *tuned_ms) {
     if (!b) return SSP_ERR_ARG;

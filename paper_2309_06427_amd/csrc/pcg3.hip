@@ -82,8 +82,26 @@ __host__ __device__ inline int knots3(int lds_bytes, int m) {
 }
 
 template <typename TM, int BLOCK, int NX>
-int lds3_for(int C, int m) {
+__host__ __device__ inline int lds3_for(int C, int m) {
     return (C + m + 2) * (bstride<TM, NX>() + (m + 1) * vstride<TM, NX>()) * (int)sizeof(TM) + 16;
+}
+
+// The six recurrence vectors of a problem of N knots stay in the
+// workgroup's LDS, behind the pass's ring, windows and spare spot, when
+// they fit in the budget: the passes then stream only the Oh blocks from
+// HBM.  Returns their byte offset in the dynamic LDS, or -1 if they do not
+// fit.  Compiled for the small state sizes only (at nx 26 a budget that
+// keeps three workgroups per CU holds no horizon of the workloads).
+template <typename TM, int BLOCK, int NX>
+__host__ __device__ inline int vectors3_offset(int N, int lds_bytes, int m) {
+    if constexpr (NX > 14) {
+        return -1;
+    } else {
+        const int C = knots3<TM, BLOCK, NX>(lds_bytes, m);
+        if (C < 1) return -1;
+        const int off = (lds3_for<TM, BLOCK, NX>(C, m) + 15) & ~15;
+        return (int64_t)off + 6 * (int64_t)N * NX * (int64_t)sizeof(TM) <= lds_bytes ? off : -1;
+    }
 }
 
 // Knots per step of residual_lean for an LDS budget: C + 1 knot slots of D
@@ -442,7 +460,11 @@ struct Outcome3 {
     double rnorm = 0.0;
 };
 
-template <typename TI, int BLOCK, int NX, bool ACC>
+// VL: the recurrence vectors live in LDS (vectors3_offset), a separate
+// instantiation so that the compiler sees LDS pointers there and global
+// pointers in the other (a pointer that may be either would turn every
+// access into a flat one, whose waits also hold the LDS traffic).
+template <typename TI, int BLOCK, int NX, bool ACC, bool VL>
 __device__ __forceinline__ Outcome3 solve_scaled(const SolveArgs &a, const Prob3<TI> &q, unsigned char *smem_raw,
                                                  double *red64, TI *redT) {
     const int N = q.N, n = N * NX, tid = threadIdx.x;
@@ -453,6 +475,11 @@ __device__ __forceinline__ Outcome3 solve_scaled(const SolveArgs &a, const Prob3
     g.acc64 = ACC;
     g.C = knots3<TI, BLOCK, NX>(a.lds_bytes, g.m);
     g.R = g.C + g.m + 2;
+    Vecs3<TI> vv = q.v;
+    if constexpr (VL) {
+        TI *vb = (TI *)(smem_raw + vectors3_offset<TI, BLOCK, NX>(N, a.lds_bytes, g.m));
+        vv = Vecs3<TI>{vb + 1 * n, vb + 2 * n, vb + 3 * n, vb + 4 * n, vb + 5 * n, vb};
+    }
     const int Cres = residual3_knots<TI, NX>(a.lds_bytes);
     const TI cc = (TI)a.pc_c;
     int pending = kOk, base = 0;
@@ -519,7 +546,7 @@ __device__ __forceinline__ Outcome3 solve_scaled(const SolveArgs &a, const Prob3
         gc.m = mcur;
         gc.R = g.C + mcur + 2;
         int it = 0, ist = kOk;
-        Dots3<TI> dt = scaled_pass<TI, BLOCK, NX>(gc, true, false, TI(0), TI(0), cc, 1.0 / hn, q.rh64, q.OH, q.v,
+        Dots3<TI> dt = scaled_pass<TI, BLOCK, NX>(gc, true, false, TI(0), TI(0), cc, 1.0 / hn, q.rh64, q.OH, vv,
                                                   (TI *)smem_raw);
         dt = reduce_dots<TI, BLOCK>(dt, gc.acc64, red64, redT);
         const TI bnorm = sqrt(dt.rho);
@@ -550,14 +577,14 @@ __device__ __forceinline__ Outcome3 solve_scaled(const SolveArgs &a, const Prob3
             }
             alpha = dt.gam / den;
             gam_prev = dt.gam;
-            dt = scaled_pass<TI, BLOCK, NX>(gc, false, it == 0, alpha, beta, cc, 0.0, q.rh64, q.OH, q.v,
+            dt = scaled_pass<TI, BLOCK, NX>(gc, false, it == 0, alpha, beta, cc, 0.0, q.rh64, q.OH, vv,
                                             (TI *)smem_raw);
             dt = reduce_dots<TI, BLOCK>(dt, gc.acc64, red64, redT);
             ++it;
         }
         o.total += it;
         ++o.steps;
-        z_apply_add<TI, TI, BLOCK, NX>(N, q.Z, q.v.x, hn, q.lam);
+        z_apply_add<TI, TI, BLOCK, NX>(N, q.Z, vv.x, hn, q.lam);
         // under refinement a float breakdown only ends the inner solve; with a
         // polynomial in Oh it also hands the rest of the solve to block-Jacobi
         broke = a.refine && ist == kBreakdown;
@@ -608,7 +635,10 @@ __device__ __forceinline__ void solve_one3(const SolveArgs &a, int p, Prob3<TI> 
     } else if (gg == 0.0) {
         for (int row = tid; row < n; row += BLOCK) q.lam[row] = 0.0;
     } else {
-        o = solve_scaled<TI, BLOCK, NX, ACC>(a, q, smem_raw, red64, redT);
+        if (vectors3_offset<TI, BLOCK, NX>(N, a.lds_bytes, a.poly) >= 0)
+            o = solve_scaled<TI, BLOCK, NX, ACC, NX <= 14>(a, q, smem_raw, red64, redT);
+        else
+            o = solve_scaled<TI, BLOCK, NX, ACC, false>(a, q, smem_raw, red64, redT);
     }
     if (tid == 0) {
         a.iters[p] = o.total;
@@ -757,6 +787,28 @@ int pcg3_residual_steps(int nx, bool fp32, int lds_bytes) {
         case 36: return fp32 ? residual3_knots<float, 36>(lds_bytes) : residual3_knots<double, 36>(lds_bytes);
     }
     return 0;
+}
+
+template <typename TI>
+int onchip3_rt(int nx, int threads, int lds_bytes, int m) {
+    // the largest N whose vectors vectors3_offset keeps in LDS (0: none)
+    int lo = 0;
+    for (int N = 1; N <= 4096; ++N) {
+        int off = -1;
+        switch (threads * 100 + nx) {
+            case 25606: off = vectors3_offset<TI, 256, 6>(N, lds_bytes, m); break;
+            case 25614: off = vectors3_offset<TI, 256, 14>(N, lds_bytes, m); break;
+            case 12806: off = vectors3_offset<TI, 128, 6>(N, lds_bytes, m); break;
+            case 12814: off = vectors3_offset<TI, 128, 14>(N, lds_bytes, m); break;
+        }
+        if (off < 0) break;
+        lo = N;
+    }
+    return lo;
+}
+
+int pcg3_onchip_horizon(int nx, bool fp32, int threads, int lds_bytes, int m) {
+    return fp32 ? onchip3_rt<float>(nx, threads, lds_bytes, m) : onchip3_rt<double>(nx, threads, lds_bytes, m);
 }
 
 int pcg3_steps_for(int nx, bool fp32, int threads, int lds_bytes, int m) {

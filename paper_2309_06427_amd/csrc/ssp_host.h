@@ -167,6 +167,8 @@ hipError_t launch_pcg3(const SolveArgs &a, bool fp32, int threads, int nx, int g
 // gives (< 1: cannot run).
 int pcg3_lds(int nx, bool fp32, int threads, int m);
 int pcg3_steps_for(int nx, bool fp32, int threads, int lds_bytes, int m);
+// largest horizon whose recurrence vectors the scaled solve keeps in LDS
+int pcg3_onchip_horizon(int nx, bool fp32, int threads, int lds_bytes, int m);
 // Knots per step of the scaled solve's FP64 residual for a budget (< 1: none).
 int pcg3_residual_steps(int nx, bool fp32, int lds_bytes);
 // Workgroups of k_pcg3 for state size nx resident per CU with this LDS

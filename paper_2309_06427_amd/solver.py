@@ -24,6 +24,14 @@ def _stream(stream) -> int:
     return s.cuda_stream
 
 
+def scaled_onchip_horizon(nx: int, pc: str, precision: str, threads: int, lds_bytes: int) -> int:
+    """Largest horizon whose PCG vectors the scaled solve keeps in LDS for a
+    mapping (threads, lds_bytes); 0 = none."""
+    out = C.c_int32()
+    check(_lib.load().ssp_scaled_onchip_horizon(int(nx), PC[pc], PREC[precision], int(threads), int(lds_bytes),
+                                                C.byref(out)), "ssp_scaled_onchip_horizon")
+    return int(out.value)
+
 class BatchSolver:
     """Handle over ``ssp_batch``: sizes are fixed at construction."""
 

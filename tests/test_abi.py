@@ -61,3 +61,27 @@ def test_mlp_create_rejects_bad_sizes():
     assert L.ssp_mlp_create(0, 128, 0, C.byref(h)) == _lib.SSP_ERR_ARG
     assert L.ssp_mlp_create(6, 100, 0, C.byref(h)) == _lib.SSP_ERR_ARG
     assert L.ssp_mlp_create(6, 128, 0, None) == _lib.SSP_ERR_ARG
+
+
+def test_onchip_horizon_query():
+    """ssp_scaled_onchip_horizon is a pure host function.  At the bench's
+    mapping (256 threads, 48 336 B of LDS), FP32 storage and the symmetric
+    stair (one Horner step), the pass's LDS holds a ring of C + 3 Oh slots and
+    two vector windows of C + 3 slots, plus a 16-byte spot:
+      nx 6:  C = 40 knots, 43 (36 + 2 * 8) * 4 + 16 = 8 960 B, and the six
+             vectors of N knots take 6 * 6 * 4 N = 144 N B: N <= 273;
+      nx 14: C = 16 knots, 19 (196 + 2 * 16) * 4 + 16 = 17 344 B, 336 N B:
+             N <= 92;
+    nx 26 and 36 never keep their vectors in LDS, nor does scalar Jacobi
+    (no scaled solve); a larger budget or block-Jacobi (no Horner window)
+    holds longer horizons."""
+    import ctypes as C
+    from paper_2309_06427_amd import solver
+    h = lambda nx, pc="sym", prec="fp32_refine64", t=256, l=48336: solver.scaled_onchip_horizon(nx, pc, prec, t, l)
+    assert h(6) == 273 and h(14) == 92
+    assert h(26) == 0 and h(36) == 0
+    assert h(14, pc="jacobi") == 0
+    assert h(14, pc="bj") > 92 and h(14, l=64000) > 92
+    assert h(14, prec="fp64") < 92
+    out = C.c_int32()
+    assert _lib.load().ssp_scaled_onchip_horizon(14, 9, 2, 256, 48336, C.byref(out)) != _lib.SSP_OK
