@@ -34,8 +34,8 @@ MEASURED_TRAFFIC = {
     # + WRITE_SIZE x 1.0 (KiB, the factors a plain 1 GiB copy reads), summed over the three k_pcg3 instances (nx 6,
     # 14, 26) of one solve at 256 threads / 48 336 B
     ("batch4096_ragged", "sym", "fp32_refine64", 0):
-        ("0a62598386ca9dd6", ((8429720.875 + 2947985.8125 + 569933.0625) * 2.0
-                              + (2915743.875 + 1658933.53125 + 713781.90625) * 1.0) * 1024),
+        ("288c10f5e1e9adbf", ((8430454.4375 + 2917252.5 + 146791.5625) * 2.0
+                              + (2916019.4375 + 1500533.46875 + 41721.78125) * 1.0) * 1024),
 }
 
 # The KKT step's HBM bytes per call, the same counters and factors, summed
