@@ -575,6 +575,12 @@ ssp_status ssp_batch_create(int32_t nprob, const int32_t *N, const int32_t *nx, 
                 for (int k0 = 0; k0 < N[p]; k0 += per) kkt.push_back(make_int2(p, k0));
     }
     b->kkt_off[ssp::kKktClasses + 1] = (int64_t)kkt.size();
+    std::vector<ssp::KktRec> kktrec(kkt.size());
+    for (size_t j = 0; j < kkt.size(); ++j) {
+        const int p = kkt[j].x;
+        kktrec[j] = ssp::KktRec{p, kkt[j].y, N[p], nu[p], b->off_nn[p], b->off_v[p], b->off_u[p], b->off_nu[p],
+                                b->off_uu[p], 0};
+    }
 
     DevGuard g(device);
     ssp_status rc = SSP_OK;
@@ -616,6 +622,7 @@ ssp_status ssp_batch_create(int32_t nprob, const int32_t *N, const int32_t *nx, 
     up(&b->ditems, items.data(), items.size());
     up(&b->dgeneric, generic.data(), generic.size());
     up(&b->dkkt, kkt.data(), kkt.size());
+    up(&b->dkktrec, kktrec.data(), kktrec.size());
     up(&b->doff_nn, b->off_nn.data(), nprob + 1);
     up(&b->doff_nu, b->off_nu.data(), nprob + 1);
     up(&b->doff_uu, b->off_uu.data(), nprob + 1);
@@ -672,7 +679,7 @@ ssp_status ssp_batch_destroy(ssp_batch *b) {
         for (hipEvent_t ev : b->gevents) (void)hipEventDestroy(ev);
         if (b->dgorder) (void)hipFree(b->dgorder);
         for (void *p : {(void *)b->dN, (void *)b->dnx, (void *)b->dnu, (void *)b->dorder, (void *)b->dknot,
-                        (void *)b->ditems, (void *)b->dgeneric, (void *)b->dkkt, (void *)b->doff_nn, (void *)b->doff_nu, (void *)b->doff_uu, (void *)b->doff_v,
+                        (void *)b->ditems, (void *)b->dgeneric, (void *)b->dkkt, (void *)b->dkktrec, (void *)b->doff_nn, (void *)b->doff_nu, (void *)b->doff_uu, (void *)b->doff_v,
                         (void *)b->dkoff, (void *)b->doff_blk32, (void *)b->doff_blk64, (void *)b->doff_b3_32, (void *)b->doff_b3_64,
                         (void *)b->doff_pk32, (void *)b->dbar, (void *)b->drec, (void *)b->dwtag, (void *)b->Qinv, (void *)b->Rinv,
                         (void *)b->r64, (void *)b->douter, (void *)b->dqueue, (void *)b->doff_u})
@@ -1063,7 +1070,8 @@ ssp_status ssp_kkt_rhs(ssp_batch *b, const double *A, const double *B, const dou
     a.B = B;
     for (int cls = 0; cls <= ssp::kKktClasses; ++cls)
         SSP_HIP(ssp::launch_kkt_rhs(cls < ssp::kKktClasses ? cls : -1, a, b->dkkt + b->kkt_off[cls],
-                                    b->kkt_off[cls + 1] - b->kkt_off[cls], b->doff_v, b->doff_u, q, r, c, gamma,
+                                    b->dkktrec + b->kkt_off[cls], b->kkt_off[cls + 1] - b->kkt_off[cls], b->doff_v,
+                                    b->doff_u, q, r, c, gamma,
                                     (hipStream_t)stream));
     return SSP_OK;
 }
@@ -1082,7 +1090,8 @@ ssp_status ssp_kkt_recover(ssp_batch *b, const double *A, const double *B, const
     a.B = B;
     for (int cls = 0; cls <= ssp::kKktClasses; ++cls)
         SSP_HIP(ssp::launch_kkt_recover(cls < ssp::kKktClasses ? cls : -1, a, b->dkkt + b->kkt_off[cls],
-                                        b->kkt_off[cls + 1] - b->kkt_off[cls], b->doff_v, b->doff_u, q, r, lambda, dx,
+                                        b->dkktrec + b->kkt_off[cls], b->kkt_off[cls + 1] - b->kkt_off[cls],
+                                        b->doff_v, b->doff_u, q, r, lambda, dx,
                                         du, (hipStream_t)stream));
     return SSP_OK;
 }

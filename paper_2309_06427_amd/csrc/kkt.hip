@@ -171,8 +171,7 @@ __device__ __forceinline__ double lds_col(const double *M, int ld, int i, const 
 // wave issues every block load of the item before its first LDS write.
 
 template <int NX>
-__global__ __launch_bounds__(64 * KktGeo<NX>::WAVES) void k_kkt_rhs_nx(BuildArgs a, const int2 *items, int64_t n,
-                                                                     const int64_t *off_v, const int64_t *off_u,
+__global__ __launch_bounds__(64 * KktGeo<NX>::WAVES) void k_kkt_rhs_nx(BuildArgs a, const KktRec *recs, int64_t n,
                                                                      const double *q, const double *r,
                                                                      const double *c, double *gamma) {
     using G = KktGeo<NX>;
@@ -182,10 +181,10 @@ __global__ __launch_bounds__(64 * KktGeo<NX>::WAVES) void k_kkt_rhs_nx(BuildArgs
     // item j + 1 reads the last Q^-1 block of item j: neighbours share an XCD
     const int64_t g = xcd_block() * G::WAVES + w;
     if (g >= n) return;  // whole wave; the kernel uses no workgroup barrier
-    const int2 it = items[g];
-    const int p = it.x, k0 = it.y, N = a.N[p], nu = a.nu[p];
+    const KktRec it = recs[g];
+    const int k0 = it.k0, N = it.N, nu = it.nu;
     const int nk = min(KP, N - k0);
-    const int64_t ov = off_v[p], ou = off_u[p], onn = a.off_nn[p];
+    const int64_t ov = it.ov, ou = it.ou, onn = it.onn;
     // blocks in LDS: Q^-1_{k0-1+j} in Q slot j (j = 0 .. nk), and A_{k-1},
     // B_{k-1}, R^-1_{k-1} of knot k = k0 + s in slot s; k0 = 0 has no Q
     // slot 0 and no slot 0 of the others
@@ -200,8 +199,8 @@ __global__ __launch_bounds__(64 * KktGeo<NX>::WAVES) void k_kkt_rhs_nx(BuildArgs
         rr[regs_for<KP * NUM * NUM>()];
     ld_range<(KP + 1) * NN>(rq, a.Qinv + onn + (int64_t)(k0 - 1 + h) * NN, (nk + 1 - h) * NN, ln);
     ld_range<KP * NN>(ra, na ? a.A + onn + kb * NN : any, na * NN, ln);
-    ld_range<KP * NX * NUM>(rb, nb ? a.B + a.off_nu[p] + kb * NX * nu : any, nb, ln);
-    ld_range<KP * NUM * NUM>(rr, nr ? a.Rinv + a.off_uu[p] + kb * nu * nu : any, nr, ln);
+    ld_range<KP * NX * NUM>(rb, nb ? a.B + it.onu + kb * NX * nu : any, nb, ln);
+    ld_range<KP * NUM * NUM>(rr, nr ? a.Rinv + it.ouu + kb * nu * nu : any, nr, ln);
     // this lane's knot k = k0 + s and row i (clamped for the idle lanes)
     const int s = min(ln / RL, nk - 1), i = min(ln % RL, NX - 1), iu = min(ln % RL, max(nu, 1) - 1);
     const int k = k0 + s;
@@ -233,9 +232,8 @@ __global__ __launch_bounds__(64 * KktGeo<NX>::WAVES) void k_kkt_rhs_nx(BuildArgs
 }
 
 template <int NX>
-__global__ __launch_bounds__(64 * KktGeo<NX>::WAVES) void k_kkt_recover_nx(BuildArgs a, const int2 *items,
-                                                                         int64_t n, const int64_t *off_v,
-                                                                         const int64_t *off_u, const double *q,
+__global__ __launch_bounds__(64 * KktGeo<NX>::WAVES) void k_kkt_recover_nx(BuildArgs a, const KktRec *recs,
+                                                                         int64_t n, const double *q,
                                                                          const double *r, const double *lam,
                                                                          double *dx, double *du) {
     using G = KktGeo<NX>;
@@ -244,10 +242,10 @@ __global__ __launch_bounds__(64 * KktGeo<NX>::WAVES) void k_kkt_recover_nx(Build
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), ln = threadIdx.x & 63;
     const int64_t g = (int64_t)blockIdx.x * G::WAVES + w;
     if (g >= n) return;  // whole wave; the kernel uses no workgroup barrier
-    const int2 it = items[g];
-    const int p = it.x, k0 = it.y, N = a.N[p], nu = a.nu[p];
+    const KktRec it = recs[g];
+    const int k0 = it.k0, N = it.N, nu = it.nu;
     const int nk = min(KP, N - k0);
-    const int64_t ov = off_v[p], ou = off_u[p], onn = a.off_nn[p];
+    const int64_t ov = it.ov, ou = it.ou, onn = it.onn;
     // Q^-1_k, A_k, B_k, R^-1_k of knot k = k0 + s in slot s; the last knot
     // of the problem has no A, B, R^-1 term
     const int na = min(nk, N - 1 - k0);
@@ -259,8 +257,8 @@ __global__ __launch_bounds__(64 * KktGeo<NX>::WAVES) void k_kkt_recover_nx(Build
         rr[regs_for<KP * NUM * NUM>()];
     ld_range<KP * NN>(rq, a.Qinv + onn + (int64_t)k0 * NN, nk * NN, ln);
     ld_range<KP * NN>(ra, na ? a.A + onn + (int64_t)k0 * NN : any, na * NN, ln);
-    ld_range<KP * NX * NUM>(rb, nb ? a.B + a.off_nu[p] + (int64_t)k0 * NX * nu : any, nb, ln);
-    ld_range<KP * NUM * NUM>(rr, nr ? a.Rinv + a.off_uu[p] + (int64_t)k0 * nu * nu : any, nr, ln);
+    ld_range<KP * NX * NUM>(rb, nb ? a.B + it.onu + (int64_t)k0 * NX * nu : any, nb, ln);
+    ld_range<KP * NUM * NUM>(rr, nr ? a.Rinv + it.ouu + (int64_t)k0 * nu * nu : any, nr, ln);
     const int s = min(ln / RL, nk - 1), i = min(ln % RL, NX - 1), iu = min(ln % RL, max(nu, 1) - 1);
     const int k = k0 + s;
     const bool next = k + 1 < N, row = ln / RL < nk && ln % RL < NX, urow = ln / RL < nk && ln % RL < nu;
@@ -386,15 +384,15 @@ int64_t kkt_grid(int64_t n) {
 
 }  // namespace
 
-hipError_t launch_kkt_rhs(int cls, const BuildArgs &a, const int2 *items, int64_t n, const int64_t *off_v,
-                          const int64_t *off_u, const double *q, const double *r, const double *c, double *gamma,
-                          hipStream_t s) {
+hipError_t launch_kkt_rhs(int cls, const BuildArgs &a, const int2 *items, const KktRec *recs, int64_t n,
+                          const int64_t *off_v, const int64_t *off_u, const double *q, const double *r,
+                          const double *c, double *gamma, hipStream_t s) {
     if (n == 0) return hipSuccess;
     switch (cls) {
 #define SSP_KKT_RHS(C, NX)                                                                                        \
     case C:                                                                                                       \
         hipLaunchKernelGGL(k_kkt_rhs_nx<NX>, dim3((unsigned)kkt_grid<NX>(n)), dim3(64 * KktGeo<NX>::WAVES), 0, s, \
-                           a, items, n, off_v, off_u, q, r, c, gamma);                                             \
+                           a, recs, n, q, r, c, gamma);                                                            \
         break;
         SSP_KKT_RHS(0, 6)
         SSP_KKT_RHS(1, 14)
@@ -407,15 +405,15 @@ hipError_t launch_kkt_rhs(int cls, const BuildArgs &a, const int2 *items, int64_
     return hipGetLastError();
 }
 
-hipError_t launch_kkt_recover(int cls, const BuildArgs &a, const int2 *items, int64_t n, const int64_t *off_v,
-                              const int64_t *off_u, const double *q, const double *r, const double *lam, double *dx,
-                              double *du, hipStream_t s) {
+hipError_t launch_kkt_recover(int cls, const BuildArgs &a, const int2 *items, const KktRec *recs, int64_t n,
+                              const int64_t *off_v, const int64_t *off_u, const double *q, const double *r,
+                              const double *lam, double *dx, double *du, hipStream_t s) {
     if (n == 0) return hipSuccess;
     switch (cls) {
 #define SSP_KKT_REC(C, NX)                                                                                  \
     case C:                                                                                                 \
         hipLaunchKernelGGL(k_kkt_recover_nx<NX>, dim3((unsigned)kkt_grid<NX>(n)), dim3(64 * KktGeo<NX>::WAVES), \
-                           0, s, a, items, n, off_v, off_u, q, r, lam, dx, du);                              \
+                           0, s, a, recs, n, q, r, lam, dx, du);                                             \
         break;
         SSP_KKT_REC(0, 6)
         SSP_KKT_REC(1, 14)

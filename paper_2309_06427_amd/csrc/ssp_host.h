@@ -112,16 +112,23 @@ hipError_t launch_fill_i32(int32_t *dst, int32_t v, int64_t n, hipStream_t s);
 // per problem).  Class kkt_class_of(nx, nu) of every item's problem picks
 // the kernel compiled for state size kKktSizes[cls] (nu <= nx / 2), -1 the
 // generic one (any nx, nu <= 64; one knot per item).
+// One work item of the staged KKT kernels with everything a wave needs
+// before its block loads: one 64-byte record, a single scalar load (the
+// problem's sizes and offsets are not looked up through the problem index).
+struct alignas(16) KktRec {
+    int32_t p, k0, N, nu;
+    int64_t onn, ov, ou, onu, ouu, pad;
+};
 constexpr int kKktClasses = 3;
 extern const int kKktSizes[kKktClasses];
 int kkt_class_of(int nx, int nu);
 int kkt_knots_per_item(int cls);
-hipError_t launch_kkt_rhs(int cls, const BuildArgs &a, const int2 *list, int64_t n, const int64_t *off_v,
-                          const int64_t *off_u, const double *q, const double *r, const double *c, double *gamma,
-                          hipStream_t s);
-hipError_t launch_kkt_recover(int cls, const BuildArgs &a, const int2 *list, int64_t n, const int64_t *off_v,
-                              const int64_t *off_u, const double *q, const double *r, const double *lam, double *dx,
-                              double *du, hipStream_t s);
+hipError_t launch_kkt_rhs(int cls, const BuildArgs &a, const int2 *list, const KktRec *recs, int64_t n,
+                          const int64_t *off_v, const int64_t *off_u, const double *q, const double *r,
+                          const double *c, double *gamma, hipStream_t s);
+hipError_t launch_kkt_recover(int cls, const BuildArgs &a, const int2 *list, const KktRec *recs, int64_t n,
+                              const int64_t *off_v, const int64_t *off_u, const double *q, const double *r,
+                              const double *lam, double *dx, double *du, hipStream_t s);
 hipError_t launch_fill_f64(double *dst, double v, int64_t n, hipStream_t s);
 
 // Explicit two-sweep PCG (stored Phi^-1 blocks).
