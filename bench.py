@@ -43,9 +43,9 @@ MEASURED_TRAFFIC = {
 # sha256[:16], right-hand side bytes, recovery bytes)
 KKT_SOURCES = ("kkt.hip", "ssp_host.h", "host.hip")
 MEASURED_KKT_TRAFFIC = {
-    "batch4096_ragged": ("5731e9c3b3a3247d",
-                         ((1421701.11 + 440623.29 + 89225.65) * 2.0 + (38557.31 + 21592.43 + 9357.16) * 1.0) * 1024,
-                         ((1522958.32 + 465590.67 + 93053.75) * 2.0 + (65205.94 + 34264.34 + 14282.90) * 1.0) * 1024),
+    "batch4096_ragged": ("f2c980f859701405",
+                         ((1431882.48 + 443152.39 + 90428.69) * 2.0 + (38559.67 + 21612.10 + 9358.55) * 1.0) * 1024,
+                         ((1521474.33 + 464100.25 + 92836.65) * 2.0 + (65205.94 + 34264.34 + 14283.51) * 1.0) * 1024),
 }
 
 
