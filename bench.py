@@ -245,7 +245,7 @@ def main() -> int:
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+        print(f"bench.py: this benchmark runs on one GPU only (asked for --gpus {args.gpus}); "
               "problems are independent and would shard across GPUs by problem, "
               "which is not implemented here", file=sys.stderr)
         return 2
