@@ -549,8 +549,9 @@ __global__ __launch_bounds__(kThreadsD) __attribute__((amdgpu_waves_per_eu(2))) 
     constexpr int RU = (NU + P - 1) / P, PK = NX * (NX + 1) / 2;
     __shared__ __align__(16) double sm[kKnotsD * NN + 2];
     double *spare = sm + kKnotsD * NN;  // sink of staged copies past their range
-    const int2 it = items[blockIdx.x];
-    const int pr = it.x, N = a.N[pr], k0 = it.y, nk = min(kKnotsD, N - k0);
+    const BuildRec it = a.brec[blockIdx.x];  // the item items[blockIdx.x] with its problem's offsets
+    const int pr = it.pr, N = it.N, k0 = it.k0, nk = min(kKnotsD, N - k0);
+    const int64_t oblk = sizeof(TM) == 4 ? it.oblk32 : it.oblk64, ob3 = sizeof(TM) == 4 ? it.ob3_32 : it.ob3_64;
     const Dl<NX> d = dl_of<NX>(k0, N);
     const int k = d.knot, kc = min(k, N - 1), km = max(kc - 1, 0);
     const bool prev = d.act && k > 0;
@@ -558,20 +559,20 @@ __global__ __launch_bounds__(kThreadsD) __attribute__((amdgpu_waves_per_eu(2))) 
     // blocks k-1 of the knots k0 .. k0+nk-1 (knot 0 reads block 0 with a zero multiplier)
     const int ks = max(k0 - 1, 0), ke = max(k0 + nk - 1, ks + 1), gm = km - ks, gc = kc - k0;
     const int bs = block_stride(NX, sizeof(TM)), bp = packed_stride(NX, sizeof(TM)), kst = 2 * bp + bs;
-    TM *b3 = (TM *)a.B3 + a.off_b3[pr] + (int64_t)k0 * kst;  // per knot: D_k (packed), L_k, D_k^-1 (packed)
+    TM *b3 = (TM *)a.B3 + ob3 + (int64_t)k0 * kst;  // per knot: D_k (packed), L_k, D_k^-1 (packed)
     int rw[R];
     static_for<0, R>([&](auto s_) { rw[decltype(s_)::value] = min(d.row(decltype(s_)::value), NX - 1); });
 
     // m = Q_{k-1}^-1 (identity where the knot has no predecessor)
     double m[R][NX], t[R][NX];
-    stage_in<kKnotsD * NN>(sm, a.Q + a.off_nn[pr] + (int64_t)ks * NN, (ke - ks) * NN, spare);
+    stage_in<kKnotsD * NN>(sm, a.Q + it.onn + (int64_t)ks * NN, (ke - ks) * NN, spare);
     wave_sync();
     lds_rows<NX>(sm + gm * NN, NX, NX, d.p, m);
     identity_outside<NX>(m, d.p, prev, NX);
     (void)gj_dpp<P, R, NX>(m, d.p, NX);  // Q_{k-1} is checked by the row of knot k-1
     wave_sync();
     // t = A_{k-1} Q_{k-1}^-1 (rows of Q^-1 broadcast)
-    stage_in<kKnotsD * NN>(sm, a.A + a.off_nn[pr] + (int64_t)ks * NN, (ke - ks) * NN, spare);
+    stage_in<kKnotsD * NN>(sm, a.A + it.onn + (int64_t)ks * NN, (ke - ks) * NN, spare);
     wave_sync();
     int ro[R];  // this lane's rows in the staged block
     static_for<0, R>([&](auto s_) { ro[decltype(s_)::value] = gm * NN + rw[decltype(s_)::value] * NX; });
@@ -596,7 +597,7 @@ __global__ __launch_bounds__(kThreadsD) __attribute__((amdgpu_waves_per_eu(2))) 
         wave_sync();
         for (int g = 0; g < nk; ++g) {
             copy_out<NN>(b3 + (int64_t)g * kst + bp, hi + g * NN, NN);
-            if (lo) copy_out<NN>(a.SLlo + a.off_blk[pr] + (int64_t)(k0 + g) * bs, lo + g * NN, NN);
+            if (lo) copy_out<NN>(a.SLlo + oblk + (int64_t)(k0 + g) * bs, lo + g * NN, NN);
         }
         wave_sync();
     }
@@ -604,8 +605,8 @@ __global__ __launch_bounds__(kThreadsD) __attribute__((amdgpu_waves_per_eu(2))) 
     // D_k += B u^T with u = B_{k-1} R_{k-1}^-1
     {
         double *Rb = sm, *Bb = sm + kKnotsD * UU;
-        stage_in<kKnotsD * UU>(Rb, a.R + a.off_uu[pr] + (int64_t)ks * UU, (ke - ks) * UU, spare);
-        stage_in<kKnotsD * XU>(Bb, a.B + a.off_nu[pr] + (int64_t)ks * XU, (ke - ks) * XU, spare);
+        stage_in<kKnotsD * UU>(Rb, a.R + it.ouu + (int64_t)ks * UU, (ke - ks) * UU, spare);
+        stage_in<kKnotsD * XU>(Bb, a.B + it.onu + (int64_t)ks * XU, (ke - ks) * XU, spare);
         wave_sync();
         double ri[RU][NU], u[R][NU];
         lds_rows<NX>(Rb + gm * UU, NU, NU, d.p, ri);
@@ -619,7 +620,7 @@ __global__ __launch_bounds__(kThreadsD) __attribute__((amdgpu_waves_per_eu(2))) 
             rows_to_lds<NX>(Rb + gm * UU, NU, prev, d.p, ri, 1.0);
             wave_sync();
             const int nr = k0 + nk - 1 - ks;
-            if (nr > 0) copy_out<kKnotsD * UU>(a.Rinv + a.off_uu[pr] + (int64_t)ks * UU, Rb, nr * UU);
+            if (nr > 0) copy_out<kKnotsD * UU>(a.Rinv + it.ouu + (int64_t)ks * UU, Rb, nr * UU);
         }
         static_for<0, R>([&](auto s_) { static_for<0, NU>([&](auto jc) { u[decltype(s_)::value][decltype(jc)::value] = 0.0; }); });
         int rb[R];
@@ -636,7 +637,7 @@ __global__ __launch_bounds__(kThreadsD) __attribute__((amdgpu_waves_per_eu(2))) 
     }
     // D_k += Q_k^-1
     {
-        stage_in<kKnotsD * NN>(sm, a.Q + a.off_nn[pr] + (int64_t)k0 * NN, nk * NN, spare);
+        stage_in<kKnotsD * NN>(sm, a.Q + it.onn + (int64_t)k0 * NN, nk * NN, spare);
         wave_sync();
         double q[R][NX];
         lds_rows<NX>(sm + gc * NN, NX, NX, d.p, q);
@@ -661,7 +662,7 @@ __global__ __launch_bounds__(kThreadsD) __attribute__((amdgpu_waves_per_eu(2))) 
             wave_sync();
             rows_to_lds<NX>(sm + d.g * NN, NX, d.act, d.p, q, 1.0);
             wave_sync();
-            copy_out<kKnotsD * NN>(a.Qinv + a.off_nn[pr] + (int64_t)k0 * NN, sm, nk * NN);
+            copy_out<kKnotsD * NN>(a.Qinv + it.onn + (int64_t)k0 * NN, sm, nk * NN);
         }
     }
     lower_from_upper<NX>(dk, d.p, sm + d.g * P * NX);
@@ -673,7 +674,7 @@ __global__ __launch_bounds__(kThreadsD) __attribute__((amdgpu_waves_per_eu(2))) 
         wave_sync();
         for (int g = 0; g < nk; ++g) {
             copy_out<PK>(b3 + (int64_t)g * kst, hi + g * PK, PK);
-            if (lo) copy_out<PK>(a.SDlo + a.off_pk[pr] + (int64_t)(k0 + g) * bp, lo + g * PK, PK);
+            if (lo) copy_out<PK>(a.SDlo + it.opk + (int64_t)(k0 + g) * bp, lo + g * PK, PK);
         }
         wave_sync();
     }
@@ -684,7 +685,7 @@ __global__ __launch_bounds__(kThreadsD) __attribute__((amdgpu_waves_per_eu(2))) 
         TM *w = (TM *)sm;
         split_rows_to_lds<NX, TM>(w + d.g * NN, nullptr, d.act, d.p, dk, 1.0);
         wave_sync();
-        for (int g = 0; g < nk; ++g) copy_out<NN>((TM *)a.Zs + a.off_blk[pr] + (int64_t)(k0 + g) * bs, w + g * NN, NN);
+        for (int g = 0; g < nk; ++g) copy_out<NN>((TM *)a.Zs + oblk + (int64_t)(k0 + g) * bs, w + g * NN, NN);
     } else {
         okd = gj_dpp<P, R, NX>(dk, d.p, NX);
         TM *di = (TM *)sm;
@@ -703,14 +704,15 @@ __global__ __launch_bounds__(kThreadsD) __attribute__((amdgpu_waves_per_eu(2))) 
 template <typename TM, int NX>
 __global__ __launch_bounds__(kThreadsD) void k_bdpp_ohat(BuildArgs a, const int2 *items) {
     constexpr int R = RowGeo<NX>::R, P = RowGeo<NX>::P;
-    const int2 it = items[blockIdx.x];
-    const int pr = it.x, N = a.N[pr];
-    const Dl<NX> d = dl_of<NX>(it.y, N);
+    const BuildRec it = a.brec[blockIdx.x];  // the item items[blockIdx.x] with its problem's offsets
+    const int N = it.N;
+    const int64_t oblk = sizeof(TM) == 4 ? it.oblk32 : it.oblk64, ob3 = sizeof(TM) == 4 ? it.ob3_32 : it.ob3_64;
+    const Dl<NX> d = dl_of<NX>(it.k0, N);
     const int k = d.knot, kc = min(k, N - 1), km = max(kc - 1, 0);
     const bool prev = d.act && k > 0;
     const int bs = block_stride(NX, sizeof(TM)), bp = packed_stride(NX, sizeof(TM));
-    const TM *Z = (const TM *)a.Zs + a.off_blk[pr];
-    const TM *Lk = (const TM *)a.B3 + a.off_b3[pr] + (int64_t)kc * (2 * bp + bs) + bp;
+    const TM *Z = (const TM *)a.Zs + oblk;
+    const TM *Lk = (const TM *)a.B3 + ob3 + (int64_t)kc * (2 * bp + bs) + bp;
     int rw[R];
     static_for<0, R>([&](auto s_) { rw[decltype(s_)::value] = min(d.row(decltype(s_)::value), NX - 1); });
     double w[R][NX], x[R][NX];
@@ -736,7 +738,7 @@ __global__ __launch_bounds__(kThreadsD) void k_bdpp_ohat(BuildArgs a, const int2
         });
     });
     keep(o);
-    store_split_slots<TM, NX>((TM *)a.OH + a.off_blk[pr] + (int64_t)kc * bs, (float *)nullptr, d, o, 1.0);
+    store_split_slots<TM, NX>((TM *)a.OH + oblk + (int64_t)kc * bs, (float *)nullptr, d, o, 1.0);
 }
 
 template <int NX>

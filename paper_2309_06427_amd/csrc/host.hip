@@ -557,6 +557,12 @@ ssp_status ssp_batch_create(int32_t nprob, const int32_t *N, const int32_t *nx, 
                 for (int k0 = 0; k0 < N[p]; k0 += per) items.push_back(make_int2(p, k0));
     }
     b->item_off[ssp::kBuildClasses] = (int)items.size();
+    std::vector<ssp::BuildRec> itemrec(items.size());
+    for (size_t j = 0; j < items.size(); ++j) {
+        const int p = items[j].x;
+        itemrec[j] = ssp::BuildRec{p, items[j].y, N[p], 0, b->off_nn[p], b->off_nu[p], b->off_uu[p], b->off_pk32[p],
+                                   b->off_blk32[p], b->off_blk64[p], b->off_b3_32[p], b->off_b3_64[p]};
+    }
     for (int p = 0; p < nprob; ++p) {
         if (ssp::build_class_of(nx[p], nu[p]) >= 0) continue;
         for (int64_t g = b->koff[p]; g < b->koff[p + 1]; ++g) generic.push_back((int32_t)g);
@@ -620,6 +626,7 @@ ssp_status ssp_batch_create(int32_t nprob, const int32_t *N, const int32_t *nx, 
     }
     up(&b->dknot, knot_prob.data(), knot_prob.size());
     up(&b->ditems, items.data(), items.size());
+    up(&b->ditemrec, itemrec.data(), itemrec.size());
     up(&b->dgeneric, generic.data(), generic.size());
     up(&b->dkkt, kkt.data(), kkt.size());
     up(&b->dkktrec, kktrec.data(), kktrec.size());
@@ -679,7 +686,7 @@ ssp_status ssp_batch_destroy(ssp_batch *b) {
         for (hipEvent_t ev : b->gevents) (void)hipEventDestroy(ev);
         if (b->dgorder) (void)hipFree(b->dgorder);
         for (void *p : {(void *)b->dN, (void *)b->dnx, (void *)b->dnu, (void *)b->dorder, (void *)b->dknot,
-                        (void *)b->ditems, (void *)b->dgeneric, (void *)b->dkkt, (void *)b->dkktrec, (void *)b->doff_nn, (void *)b->doff_nu, (void *)b->doff_uu, (void *)b->doff_v,
+                        (void *)b->ditems, (void *)b->ditemrec, (void *)b->dgeneric, (void *)b->dkkt, (void *)b->dkktrec, (void *)b->doff_nn, (void *)b->doff_nu, (void *)b->doff_uu, (void *)b->doff_v,
                         (void *)b->dkoff, (void *)b->doff_blk32, (void *)b->doff_blk64, (void *)b->doff_b3_32, (void *)b->doff_b3_64,
                         (void *)b->doff_pk32, (void *)b->dbar, (void *)b->drec, (void *)b->dwtag, (void *)b->Qinv, (void *)b->Rinv,
                         (void *)b->r64, (void *)b->douter, (void *)b->dqueue, (void *)b->doff_u})
@@ -785,6 +792,7 @@ ssp_status ssp_build(ssp_batch *b, ssp_precon pc, ssp_precision prec, const doub
         if (fork)
             for (int i = 0; i < ng; ++i)
                 if (b->groups[i].nx == ssp::kBuildSizes[c]) cs = b->gstreams[i];
+        a.brec = b->ditemrec + b->item_off[c];
         SSP_HIP(ssp::launch_build_class(c, a, b->ditems + b->item_off[c], n, fp32, cs));
         if (scaled) SSP_HIP(ssp::launch_build_ohat(c, a, b->ditems + b->item_off[c], n, fp32, cs));
     }

@@ -74,7 +74,8 @@ struct ssp_batch {
     // KKT step: work items (problem, first knot) by kernel class
     // (ssp::kkt_class_of), the generic class last, at dkkt + kkt_off[c]
     int2 *dkkt = nullptr;
-    ssp::KktRec *dkktrec = nullptr;  // the same items with their problem's sizes and offsets
+    ssp::KktRec *dkktrec = nullptr;
+    ssp::BuildRec *ditemrec = nullptr;  // the assembly work items with their problem's horizon and offsets  // the same items with their problem's sizes and offsets
     int64_t kkt_off[ssp::kKktClasses + 2] = {};
     int64_t n_generic = 0;
     int gen_nx_max = 1, gen_nu_max = 0;

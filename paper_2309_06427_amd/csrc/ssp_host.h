@@ -6,6 +6,15 @@
 
 namespace ssp {
 
+// One work item (problem, first knot) of the DPP assembly kernels with its
+// problem's horizon and offsets, so that a wave's first loads depend on one
+// round of scalar loads (the offsets are not looked up through the problem
+// index); both storage precisions' block offsets are kept.
+struct alignas(16) BuildRec {
+    int32_t pr, k0, N, pad;
+    int64_t onn, onu, ouu, opk, oblk32, oblk64, ob3_32, ob3_64;
+};
+
 struct BuildArgs {
     const int32_t *N, *nx, *nu;
     const int64_t *off_nn, *off_nu, *off_uu;  // input (caller) layout
@@ -28,6 +37,7 @@ struct BuildArgs {
     int pc;  // 0 block-Jacobi, 1 additive stair, 2 symmetric stair, 3 scalar Jacobi, 4/5 Neumann degree 2/3
     int mx;  // max(nx, nu) over the batch
     int keep_qr;  // store Q_k^-1, R_k^-1 in Qinv, Rinv (the KKT step reads them)
+    const BuildRec *brec;  // DPP classes: the launched class's item records, in the order of its items
 };
 
 struct SolveArgs {
