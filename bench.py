@@ -34,8 +34,8 @@ MEASURED_TRAFFIC = {
     # + WRITE_SIZE x 1.0 (KiB, the factors a plain 1 GiB copy reads), summed over the three k_pcg3 instances (nx 6,
     # 14, 26) of one solve at 256 threads / 48 336 B
     ("batch4096_ragged", "sym", "fp32_refine64", 0):
-        ("288c10f5e1e9adbf", ((8430454.4375 + 2917252.5 + 146791.5625) * 2.0
-                              + (2916019.4375 + 1500533.46875 + 41721.78125) * 1.0) * 1024),
+        ("7832a2dd28d9765a", ((8431864.3125 + 2908337.1875 + 148507.75) * 2.0
+                              + (2916113.21875 + 1499994.59375 + 41748.65625) * 1.0) * 1024),
 }
 
 # The KKT step's HBM bytes per call, the same counters and factors, summed
@@ -43,9 +43,9 @@ MEASURED_TRAFFIC = {
 # sha256[:16], right-hand side bytes, recovery bytes)
 KKT_SOURCES = ("kkt.hip", "ssp_host.h", "host.hip")
 MEASURED_KKT_TRAFFIC = {
-    "batch4096_ragged": ("f2c980f859701405",
-                         ((1431882.48 + 443152.39 + 90428.69) * 2.0 + (38559.67 + 21612.10 + 9358.55) * 1.0) * 1024,
-                         ((1521474.33 + 464100.25 + 92836.65) * 2.0 + (65205.94 + 34264.34 + 14283.51) * 1.0) * 1024),
+    "batch4096_ragged": ("f647674a887fd787",
+                         ((1431882.47 + 443152.46 + 90428.95) * 2.0 + (38557.83 + 21607.56 + 9358.26) * 1.0) * 1024,
+                         ((1521470.02 + 464100.26 + 92836.45) * 2.0 + (65205.94 + 34264.34 + 14283.5) * 1.0) * 1024),
 }
 
 
