@@ -65,6 +65,32 @@ def test_kkt_bytes_count_each_block_and_vector_once(monkeypatch):
     assert rec.tolist() == [8.0 * (12 + 14 + 18 + 2 + 3)]
 
 
+def test_scaled_bytes_by_hand_and_on_chip_vectors(monkeypatch):
+    """One problem, N = 3 knots, nx = 2, FP32 storage, 5 inner iterations in
+    one outer step from a zero start, counted by hand:
+      blocks: Oh on N - 1 = 2 knots per pass, 6 passes (5 + the initial one),
+              4 * 4 * 2 * 6 = 192 B; W twice, 2 * 4 * 3 * 4 = 96 B; no FP64
+              residual sweep (zero start): 288 B;
+      vectors, per row (6 rows): 12 * 4 * 5 update-pass bytes, 8 + 4 * 4 for
+              the initial pass, 40 + 4 for the transforms, 16 once: 324 B per
+              row, 1944 B.
+    With the vectors in LDS only the FP64 parts remain: 8 + 40 + 16 = 64 B per
+    row; the block bytes do not change."""
+    if ROOT not in sys.path:
+        monkeypatch.syspath_prepend(ROOT)
+    import numpy as np
+    import bench
+    from paper_2309_06427_amd import inputs
+    b = inputs.pack([inputs.draw_problem(np.random.default_rng(0), 3, 2, 1)])
+    it, st = np.array([5]), np.array([1])
+    blk, vec = bench.scaled_bytes(b, it, st, "fp32_refine64")
+    assert blk.tolist() == [288.0] and vec.tolist() == [6 * 324.0]
+    blk2, vec2 = bench.scaled_bytes(b, it, st, "fp32_refine64", np.array([True]))
+    assert blk2.tolist() == [288.0] and vec2.tolist() == [6 * 64.0]
+    _, vec3 = bench.scaled_bytes(b, it, st, "fp32_refine64", np.array([False]))
+    assert vec3.tolist() == vec.tolist()
+
+
 @pytest.mark.gpu
 def test_compare_and_kkt_timings_are_reported(monkeypatch, capsys):
     torch = pytest.importorskip("torch")
