@@ -417,12 +417,16 @@ __device__ __forceinline__ void load_slots_t(const TM *__restrict__ src, int p, 
     });
 }
 
-// rows that are not this lane's real rows become identity rows
+// rows that are not this lane's real rows become identity rows.  The row
+// index is made opaque to the compiler, so each call forms its own identity
+// values: shared between calls, they were held (and spilled) across the
+// whole assembly, and reloaded one dependent scratch load at a time.
 template <int NX, int RS, int NC>
 __device__ __forceinline__ void identity_outside(double (&a)[RS][NC], int p, bool live, int n) {
     static_for<0, RS>([&](auto s_) {
         constexpr int s = decltype(s_)::value;
-        const int r = p + s * RowGeo<NX>::P;
+        int r = p + s * RowGeo<NX>::P;
+        asm volatile("" : "+v"(r));
         const bool real = live && r < n;
         static_for<0, NC>([&](auto jc) {
             constexpr int j = decltype(jc)::value;
