@@ -23,8 +23,9 @@
 // is made symmetric by copying its upper triangle onto the lower one (the
 // upper triangle is what is stored).
 //
-// Memory: the inverse and assembly kernels move blocks between HBM and LDS
-// only in wave-wide copies of contiguous ranges, and lanes read their rows
+// Memory: the assembly kernel (which forms the inverses in registers, see
+// k_bdpp_asm) moves blocks between HBM and LDS only in wave-wide copies of
+// contiguous ranges, and lanes read their rows
 // from LDS (a lane that loads or stores its own rows touches a separate cache
 // line per lane and instruction, which bounded an earlier version in the
 // memory pipeline); the Oh kernel, with few loads per knot, reads its rows
